@@ -1,0 +1,328 @@
+"""Benchmark of the Cole-Hopf MRT-LB hot path on one MI355X.
+
+One benchmark step is one complete solve of the workload: initialise from
+theta0 and its analytic gradient, advance all LB time steps (fused
+collide-stream kernel), and form theta and u.  Default workload: D2Q9 on a
+4096 x 4096 periodic unit square, nu = 0.01, eps = 0.2, 10,000 time steps
+(theta0 = 2 + cos 2pi x cos 2pi y).  The timed region holds exactly
+--steps solves between two device synchronisations; inputs are resident in
+HBM before it starts.
+
+Printed (one JSON line on stdout): throughput in MLUPS (lattice updates per
+second), the dominant kernel's achieved algorithmic bandwidth against the
+8 TB/s HBM peak (HIP events on the launch stream), the CPU oracle timed on a
+bounded sample, and the other forms (3-D D3Q19, batched, adjoint) measured on
+the same GPU.  Progress goes to stderr.
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "FP64 MLUPS + HBM GB/s (% roofline); batched and adjoint vs plain step"
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_LU = {1: 48, 2: 144, 3: 304}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_step.json")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2309_02825_amd", "csrc", n)
+                  for n in ("lbm_kernels.hip", "lbm_lattice.h", "lbm_kernels.h")]
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(p, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def workload(name: str):
+    from paper_2309_02825_amd import workloads as W
+    table = {
+        "heat2d_4096": lambda: W.heat_2d(4096, 10000),
+        "heat2d_1024": lambda: W.heat_2d(1024, 10000),
+        "heat3d_256": lambda: W.heat_3d(256, 2000),
+        "heat3d_512": lambda: W.heat_3d(512, 2000),
+    }
+    return table[name]()
+
+
+def traffic_for(name: str, lb_steps: int):
+    """HBM bytes per launch of the dominant kernel from the committed
+    rocprofv3 counter summary, or None if absent or the kernel changed."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    entry = t.get(name)
+    if not entry or entry.get("kernel_sha") != kernel_source_hash():
+        return None
+    return entry.get("hbm_bytes_per_launch")
+
+
+class Timer:
+    """HIP events on the stream the kernels are launched on."""
+
+    def __init__(self, torch, stream):
+        self.torch = torch
+        self.stream = stream
+        self.pairs = []
+
+    def start(self):
+        e = self.torch.cuda.Event(enable_timing=True)
+        e.record(self.stream)
+        self.pairs.append([e, None])
+
+    def stop(self):
+        e = self.torch.cuda.Event(enable_timing=True)
+        e.record(self.stream)
+        self.pairs[-1][1] = e
+
+    def total_ms(self):
+        return sum(a.elapsed_time(b) for a, b in self.pairs)
+
+
+def solve_timed(torch, SV, W, wl, steps, warmup, dev):
+    """Returns (wall seconds for `steps` solves, kernel ms per LB step)."""
+    stream = torch.cuda.current_stream()
+    s = SV.Solver(wl.grid, wl.dx, wl.dt, wl.nu, device=dev)
+    th0, g0 = W.evaluate(wl.modes, wl.grid, wl.dx, xp=torch, device=dev)
+
+    def one(timer=None):
+        s.init(th0, g0)
+        if timer:
+            timer.start()
+        s.step(wl.nsteps)
+        if timer:
+            timer.stop()
+        return s.macro()
+
+    for _ in range(warmup):
+        one()
+    timer = Timer(torch, stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        out = one(timer)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kms = timer.total_ms() / (steps * wl.nsteps)
+    del out
+    s.close()
+    return wall, kms
+
+
+def kernel_only(torch, SV, W, wl, lb_steps, dev):
+    """Average duration of one LB step on a resident state (HIP events)."""
+    stream = torch.cuda.current_stream()
+    s = SV.Solver(wl.grid, wl.dx, wl.dt, wl.nu, device=dev)
+    th0, g0 = W.evaluate(wl.modes, wl.grid, wl.dx, xp=torch, device=dev)
+    s.init(th0, g0)
+    del th0, g0
+    s.step(10)
+    timer = Timer(torch, stream)
+    timer.start()
+    s.step(lb_steps)
+    timer.stop()
+    torch.cuda.synchronize()
+    ms = timer.total_ms() / lb_steps
+    s.close()
+    return ms
+
+
+def form_batched(torch, SV, W, dev):
+    insts = W.batch_instances()
+    bs = SV.BatchSolver(insts, device=dev)
+    th, gr = [], []
+    for p in insts:
+        t, g = W.evaluate(p.modes, p.grid, p.dx, xp=torch, device=dev)
+        th.append(t)
+        gr.append(g)
+    bs.init(th, gr)
+    del th, gr
+    tile = bs.autotune(3)
+    bs.step(1000, graph=True)        # capture + warm
+    stream = torch.cuda.current_stream()
+    timer = Timer(torch, stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    timer.start()
+    bs.step(1000, graph=True)
+    timer.stop()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = timer.total_ms()
+    nodes = bs.total_nodes
+    bs.close()
+    mlups = nodes * 1000 / (ms / 1e3) / 1e6
+    return {"instances": len(insts), "total_nodes": nodes, "lb_steps": 1000,
+            "launch": "one hipGraph of 1000 tile-table kernels", "tile": list(tile),
+            "graph_ms": round(ms, 3), "wall_s": round(wall, 4), "mlups": round(mlups, 1),
+            "gbs_algorithmic": round(mlups * 144 / 1e3, 1)}
+
+
+def form_adjoint(torch, SV, W, dev):
+    tgt, gue = W.adjoint_problem()
+    dx, dt, nu, N = gue.dx, gue.dt, gue.nu, gue.nsteps
+    th_t, _ = W.evaluate(tgt.modes, tgt.grid, tgt.dx, xp=torch, device=dev, with_grad=False)
+    th0, _ = W.evaluate(gue.modes, gue.grid, gue.dx, xp=torch, device=dev, with_grad=False)
+    nu_t = torch.tensor(nu, dtype=torch.float64, device=dev)
+    with torch.no_grad():
+        u_target = SV.velocity(th_t, nu_t, gue.grid, dx, dt, N)
+
+    def fwd_only():
+        with torch.no_grad():
+            return SV.velocity(th0, nu_t, gue.grid, dx, dt, N)
+
+    def fwd_bwd():
+        a = th0.clone().requires_grad_(True)
+        b = nu_t.clone().requires_grad_(True)
+        u = SV.velocity(a, b, gue.grid, dx, dt, N)
+        loss = ((u - u_target) ** 2).sum()
+        loss.backward()
+        return loss, a.grad, b.grad
+
+    fwd_only()
+    fwd_bwd()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    fwd_only()
+    torch.cuda.synchronize()
+    t_f = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    loss, g_th, g_nu = fwd_bwd()
+    torch.cuda.synchronize()
+    t_fb = time.perf_counter() - t0
+    V = gue.nodes
+    return {"grid": list(gue.grid), "lb_steps": N, "checkpoints": len(SV.checkpoint_segments(N)),
+            "forward_s": round(t_f, 4), "forward_backward_s": round(t_fb, 4),
+            "backward_over_forward": round((t_fb - t_f) / t_f, 3),
+            "mlups_forward": round(V * N / t_f / 1e6, 1),
+            "loss": float(loss.item()), "dL_dnu": float(g_nu.item()),
+            "grad_theta0_norm": float(g_th.norm().item())}
+
+
+def cpu_baseline(wl, budget_s: float = 12.0):
+    import numpy as np  # noqa: F401
+    from oracle import oracle as O
+    from paper_2309_02825_amd import workloads as W
+    th0, g0 = W.evaluate(wl.modes, wl.grid, wl.dx)
+    f = O.init(th0, g0, wl.dx, wl.dt, wl.nu)
+    steps = 0
+    t0 = time.perf_counter()
+    while True:
+        f = O.run(f, wl.dx, wl.dt, wl.nu, 1)
+        steps += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s or steps >= 50:
+            break
+    mlups = wl.nodes * steps / el / 1e6
+    return {"value": round(mlups, 3), "unit": "MLUPS", "cores": O.num_threads(), "kind": "oracle",
+            "sample": f"oracle_run (C, OpenMP) on the {wl.name} workload: {steps} of its "
+                      f"{wl.nsteps} time steps, initialisation excluded, {el:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="heat2d_4096",
+                    choices=["heat2d_4096", "heat2d_1024", "heat3d_256", "heat3d_512"])
+    ap.add_argument("--lb-steps", type=int, default=0,
+                    help="override the LB time steps per solve (profiling runs)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-forms", action="store_true")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2309_02825_amd import solver as SV
+    from paper_2309_02825_amd import workloads as W
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    wl = workload(args.workload)
+    if args.lb_steps > 0:
+        wl.nsteps = args.lb_steps
+    d = wl.d
+    log(f"workload {wl.name}: grid {wl.grid}, {wl.nsteps} LB steps per solve, "
+        f"eps {wl.eps:.4g}")
+
+    wall, kms = solve_timed(torch, SV, W, wl, args.steps, args.warmup, dev)
+    V = wl.nodes
+    mlups = V * wl.nsteps * args.steps / wall / 1e6
+    achieved = BYTES_PER_LU[d] * V / (kms / 1e3) / 1e9
+    log(f"{mlups:.1f} MLUPS, kernel {kms * 1e3:.2f} us/step, {achieved:.1f} GB/s")
+    traffic = traffic_for(args.workload, wl.nsteps)
+    lattice = {1: "D1Q3", 2: "D2Q9", 3: "D3Q19"}[d]
+    rec = {
+        "metric": METRIC,
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall / args.steps * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "lattice": lattice, "grid": list(wl.grid),
+                   "lb_steps_per_step": wl.nsteps, "nu": wl.nu, "eps": round(wl.eps, 6),
+                   "theta0": "2 + prod cos(2 pi x_a)", "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic, "kernel": f"k_step<{d}>",
+                     "kernel_us_per_launch": round(kms * 1e3, 3),
+                     "bytes_per_lu": BYTES_PER_LU[d]},
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        rec["cpu_baseline"] = cpu_baseline(wl)
+    if not args.no_forms:
+        forms = {}
+        for name in ("heat2d_1024", "heat3d_256", "heat3d_512"):
+            if name == args.workload:
+                continue
+            w2 = workload(name)
+            n = 400 if w2.d == 3 else 2000
+            ms = kernel_only(torch, SV, W, w2, n, dev)
+            ml = w2.nodes / (ms / 1e3) / 1e6
+            gbs = BYTES_PER_LU[w2.d] * ml / 1e3
+            forms[name] = {"lattice": {2: "D2Q9", 3: "D3Q19"}[w2.d], "kernel_us_per_step": round(ms * 1e3, 2),
+                           "mlups": round(ml, 1), "gbs_algorithmic": round(gbs, 1),
+                           "frac": round(gbs / HBM_PEAK_GBS, 4), "lb_steps_timed": n}
+            log(name, forms[name])
+        b = form_batched(torch, SV, W, dev)
+        plain = V / (kms / 1e3) / 1e6 if d == 2 else None
+        if plain:
+            b["mlups_ratio_vs_plain"] = round(b["mlups"] / plain, 4)
+        forms["batched"] = b
+        log("batched", b)
+        a = form_adjoint(torch, SV, W, dev)
+        forms["adjoint"] = a
+        log("adjoint", a)
+        rec["forms"] = forms
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,231 @@
+/*
+ * lbm.h - C ABI of the MI355X (gfx950) Cole-Hopf fourth-order MRT lattice
+ * Boltzmann solver (Chen, Liu, Chai & Shi, arXiv:2309.02825).
+ *
+ * The library advances the transformed diffusion equation theta_t = nu lap theta
+ * (Sec. II, Cole-Hopf transformation of the coupled Burgers equations) with the
+ * D1Q3 / D2Q9 / D3Q19 natural-moment MRT-LB model of Sec. III.A, using the
+ * relaxation rates and weights of Theorem 2 (Sec. III.D) that make the scheme
+ * and the velocity u = -2 nu grad(theta)/theta fourth-order accurate.  All
+ * arithmetic is IEEE double precision on the GPU; boundaries are periodic.
+ *
+ * Conventions shared by every entry point
+ *   - Every function returns lb_status: LB_OK (0) or a negative error code.
+ *     No C++ exception crosses the ABI.  lb_last_error() returns a message
+ *     for the last failure on the calling thread.
+ *   - Device memory is owned by the caller (plain device pointers, e.g. from
+ *     torch tensors).  A solver borrows the pointers given to it and must be
+ *     destroyed before they are freed.  The library owns only its host-side
+ *     solver object and a few small device tables (parameters, reduction
+ *     partials), allocated at creation and freed by lb_destroy.
+ *   - Work is enqueued asynchronously on the HIP stream given at creation
+ *     (NULL = the default stream); the host returns before the GPU finishes.
+ *   - Grid: n[0] nodes along x_0 (fastest), n[1] along x_1, n[2] along x_2;
+ *     unused dimensions must be 1.  Node index k = x0 + n0*(x1 + n1*x2),
+ *     V = n0*n1*n2 nodes, node spacing dx, time step dt, lattice speed
+ *     c = dx/dt, eps = nu*dt/dx^2.
+ *   - Dense fields: theta is V doubles; a vector field (grad theta, u) is
+ *     d planes of V doubles (component a = along x_a) back to back.
+ *   - State buffers hold q population planes, plane i starting at element
+ *     i*lb_state_stride(cfg); elements past V in a plane are padding.
+ *     Storage layout ("stream-shifted"): element k of plane i holds
+ *     f_i(k + e_i), the pre-collision population of node k + e_i at the
+ *     current time (the value node k sent along e_i after its last
+ *     collision), so the distribution at node x is f_i(x) = buf_i(x - e_i).
+ *   - Distribution-shaped adjoint buffers (lambda) use the same plane stride
+ *     but the canonical layout: element k of plane i is d L / d f_i(node k)
+ *     for the pre-collision f.
+ *   - Velocity order (Sec. III.A): D1Q3 (0, +1, -1); D2Q9 (0,0) (1,0) (0,1)
+ *     (-1,0) (0,-1) (1,1) (-1,1) (-1,-1) (1,-1); D3Q19 rest, +x, +y, +z, -x,
+ *     -y, -z, then the xy, xz, yz edges each as (+,+) (-,+) (-,-) (+,-).
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    LB_OK = 0,
+    LB_ERR_INVALID_ARG = -1, /* bad dimension/size/spacing, NULL pointer, ... */
+    LB_ERR_UNSTABLE = -2,    /* eps outside the range where the weights stay
+                                non-negative (d = 2: eps < 0.5, d = 3: eps <= 0.25) */
+    LB_ERR_NONFINITE = -3,   /* a non-finite or non-positive theta was found */
+    LB_ERR_OOM = -4,         /* the library could not allocate its small tables */
+    LB_ERR_HIP = -5,         /* a HIP runtime call failed */
+    LB_ERR_STATE = -6        /* call out of order (e.g. lb_step before lb_init) */
+} lb_status;
+
+typedef struct lb_solver lb_solver; /* opaque, library-owned host object */
+typedef struct lb_batch lb_batch;   /* opaque, library-owned host object */
+
+typedef struct {
+    int32_t dim;     /* 1, 2 or 3 */
+    int32_t flags;   /* reserved, must be 0 */
+    int64_t n[3];    /* nodes per axis, >= 1; n[a] = 1 for a >= dim */
+    double dx;       /* node spacing, > 0 */
+    double dt;       /* time step, > 0 */
+    double nu;       /* viscosity of the Burgers equations (Sec. II), > 0 */
+} lb_config;
+
+/* Relaxation rates and weights of Theorem 2 (Sec. III.D) for a config:
+ * s1 = 2/(6 eps + 1), s21 = 24 eps/(6 eps + 1)^2 (s2 when d = 1),
+ * s22 = 4/(6 eps + 3), w0, w1 = 1/6 - (d-1) eps/3 (1/6 for d = 1),
+ * w_{1+2d} = eps/6 (0 for d = 1).  out[0..6] = eps, s1, s21, s22, w0, w1, wd. */
+lb_status lb_parameters(const lb_config* cfg, double* out7);
+
+/* Number of populations q = 1 + 2 d^2 (3, 9, 19) for cfg->dim. */
+int32_t lb_num_populations(int32_t dim);
+
+/* Elements between consecutive population planes of a state buffer (V
+ * rounded up, plus padding that staggers the planes across HBM channels). */
+int64_t lb_state_stride(const lb_config* cfg);
+
+/* Bytes of one state buffer: q * lb_state_stride(cfg) * sizeof(double).
+ * Returns 0 for an invalid config. */
+size_t lb_state_bytes(const lb_config* cfg);
+
+/* Create a solver over two caller-owned state buffers of lb_state_bytes each
+ * (ping-pong; f_a and f_b must not overlap).  hip_stream is a hipStream_t or
+ * NULL.  Validates the config (LB_ERR_INVALID_ARG, LB_ERR_UNSTABLE). */
+lb_status lb_create(const lb_config* cfg, void* hip_stream, double* f_a, double* f_b,
+                    lb_solver** out);
+
+/* Initial state from theta0 (V doubles) and grad theta0 (d x V, or NULL):
+ * f_i = w_i theta0 - dt Lambda^{-1} Dbar f^eq with Lambda^{-1} = M^-1 S^-1 M
+ * (Sec. IV initialisation, first two terms of the expansion of Theorem 1),
+ * in closed form f_i = w_i theta0 - dx w_i (e_i . g)
+ *                      - (1/s1 - 1)(dx/6) sum_a (delta_{i,+a} - delta_{i,-a}) g_a.
+ * With grad_theta0 == NULL, g is the fourth-order central difference
+ * (-theta(x+2) + 8 theta(x+1) - 8 theta(x-1) + theta(x-2)) / (12 dx).
+ * Writes f_a and resets the step counter.  If check_theta != 0 the call also
+ * verifies theta0 > 0 and finite (Cole-Hopf needs theta > 0, Sec. II) and
+ * returns LB_ERR_NONFINITE otherwise; the check synchronises the stream. */
+lb_status lb_init(lb_solver* s, const double* theta0, const double* grad_theta0,
+                  int32_t check_theta);
+
+/* Advance nsteps >= 0 time steps (evolution equation of Sec. III.A: collide in
+ * moment space, then stream), alternating the two buffers. */
+lb_status lb_step(lb_solver* s, int64_t nsteps);
+
+/* One time step from an explicit source buffer to an explicit destination
+ * buffer (both in the storage layout, lb_state_bytes each, not overlapping).
+ * Does not touch the solver's own buffers or step counter. */
+lb_status lb_step_buffers(lb_solver* s, const double* src, double* dst);
+
+/* Buffer that holds the current state (f_a or f_b) and the steps taken. */
+double* lb_current_state(const lb_solver* s);
+int64_t lb_steps_taken(const lb_solver* s);
+
+/* Macroscopic output at the current time t = steps * dt from the
+ * pre-collision distribution (Sec. III.C):
+ *   theta = sum_i f_i,
+ *   u_a   = (2 - s1) sum_i c_{ia} f^ne_i / theta,  f^ne = f - w theta,
+ * which equals -2 nu d_a theta / theta with the fourth-order gradient
+ * d_a theta = -(s1/(dt c_s^2)) sum_i c_{ia} f^ne_i.  theta (V) or u (d x V)
+ * may be NULL. */
+lb_status lb_macro(lb_solver* s, double* theta, double* u);
+
+/* Same as lb_macro for an explicit state buffer in the storage layout. */
+lb_status lb_macro_buffer(lb_solver* s, const double* state, double* theta, double* u);
+
+/* Copy the current pre-collision distribution to f_out in the dense
+ * canonical layout (q planes of V doubles, f_out[i*V + k] = f_i(node k)). */
+lb_status lb_get_state(lb_solver* s, double* f_out);
+
+/* Load a dense canonical distribution (q x V) as the current state and set
+ * the step counter to step. */
+lb_status lb_set_state(lb_solver* s, const double* f_in, int64_t step);
+
+/* ---------------------------------------------------------------------- */
+/* Discrete adjoint (reverse mode).  The forward map is f^{n+1} = P C f^n
+ * with the per-node collision C = I - M^-1 S M (I - w 1^T) (Sec. III.A) and
+ * the streaming permutation P.  g_eps is one device double that every
+ * adjoint call increments (+=) by a deterministic reduction; with
+ * eps = nu dt / dx^2, dL/dnu = (dt/dx^2) dL/deps.                          */
+/* ---------------------------------------------------------------------- */
+
+/* Adjoint of lb_macro_buffer at the state buffer `state`: given g_theta
+ * (V, may be NULL) and g_u (d x V, may be NULL) writes lambda = dL/df
+ * (canonical, plane stride lb_state_stride) and adds the explicit eps
+ * dependence of u (through s1) to *g_eps. */
+lb_status lb_macro_adjoint(lb_solver* s, const double* state, const double* g_theta,
+                           const double* g_u, double* lambda, double* g_eps);
+
+/* One reverse step: state_n is f^n in the storage layout (as written by
+ * lb_init/lb_step_buffers), lambda_in = dL/df^{n+1}, lambda_out = dL/df^n
+ * (= C^T P^T lambda_in), both canonical and not overlapping; adds
+ * <P^T lambda_in, (dC/deps) f^n> to *g_eps. */
+lb_status lb_adjoint_step(lb_solver* s, const double* state_n, const double* lambda_in,
+                          double* lambda_out, double* g_eps);
+
+/* Adjoint of lb_init: given lambda0 = dL/df^0 (canonical) writes g_theta0 (V).
+ * If grad_theta0 != NULL the gradient input was independent and its adjoint
+ * is written to g_grad (d x V, may be NULL); if grad_theta0 == NULL the
+ * fourth-order difference stencil is transposed into g_theta0.  theta0 and
+ * grad_theta0 are the inputs given to lb_init; the eps dependence of the
+ * initial state is added to *g_eps. */
+lb_status lb_init_adjoint(lb_solver* s, const double* theta0, const double* grad_theta0,
+                          const double* lambda0, double* g_theta0, double* g_grad,
+                          double* g_eps);
+
+/* Destroy a solver (does not free the caller's buffers).  NULL is allowed. */
+lb_status lb_destroy(lb_solver* s);
+
+/* ---------------------------------------------------------------------- */
+/* Batched form: many independent 2-D periodic instances of different sizes
+ * and viscosities advanced together.  Instance b occupies q planes of
+ * stride_b elements starting at element offset_b of the pool.               */
+/* ---------------------------------------------------------------------- */
+
+/* Total pool elements (doubles) for count 2-D configs; offsets (count) and
+ * strides (count) receive each instance's first element and plane stride.
+ * Either output may be NULL.  Returns -1 on an invalid config. */
+int64_t lb_batch_layout(const lb_config* cfgs, int32_t count, int64_t* offsets,
+                        int64_t* strides);
+
+/* Create a batch over two caller-owned pools of lb_batch_layout elements
+ * each.  Only dim = 2 configs are accepted. */
+lb_status lb_batch_create(const lb_config* cfgs, int32_t count, void* hip_stream,
+                          double* pool_a, double* pool_b, lb_batch** out);
+
+/* Initialise every instance: theta0 and grad are packed pools, instance b's
+ * theta0 at element node_offset_b (prefix sum of V_b) and its gradient at
+ * 2*node_offset_b (two planes of V_b).  grad may be NULL (fourth-order
+ * differences per instance). */
+lb_status lb_batch_init(lb_batch* b, const double* theta0, const double* grad);
+
+/* Tile shape (threads along x, rows per block); tx*ty must be 256 and tx a
+ * power of two in [16, 256].  Applies to subsequent steps. */
+lb_status lb_batch_set_tile(lb_batch* b, int32_t tx, int32_t ty);
+
+/* Time candidate tile shapes on the real pools (state is restored) and keep
+ * the fastest; best_tx/best_ty receive the choice (may be NULL). */
+lb_status lb_batch_autotune(lb_batch* b, int32_t steps_per_trial, int32_t* best_tx,
+                            int32_t* best_ty);
+
+/* Advance every instance nsteps.  With use_graph != 0 the nsteps launches
+ * are captured once into a hipGraph (cached per nsteps) and replayed with a
+ * single hipGraphLaunch. */
+lb_status lb_batch_step(lb_batch* b, int64_t nsteps, int32_t use_graph);
+
+/* theta (packed V_b per instance) and u (packed 2 x V_b per instance, at
+ * 2*node_offset_b); either may be NULL. */
+lb_status lb_batch_macro(lb_batch* b, double* theta, double* u);
+
+/* Current pool (pool_a or pool_b) and steps taken. */
+double* lb_batch_current(const lb_batch* b);
+lb_status lb_batch_destroy(lb_batch* b);
+
+/* Message for the last error on the calling thread ("" if none). */
+const char* lb_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM_H */

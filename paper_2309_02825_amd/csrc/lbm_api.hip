@@ -1,0 +1,613 @@
+// C ABI of the solver (declared in include/lbm.h): validation, parameters of
+// Theorem 2 (Sec. III.D), buffer bookkeeping and kernel launches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <climits>
+#include <cmath>
+#include <map>
+#include <new>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "lbm.h"
+#include "lbm_kernels.h"
+
+using lbm::BatchInst;
+using lbm::BatchTile;
+using lbm::Geo;
+using lbm::Launch;
+using lbm::Rates;
+
+namespace {
+
+thread_local std::string g_err;
+
+lb_status fail(lb_status st, const std::string& msg) {
+    g_err = msg;
+    return st;
+}
+
+lb_status hip_fail(hipError_t e, const char* what) {
+    g_err = std::string(what) + ": " + hipGetErrorString(e);
+    return LB_ERR_HIP;
+}
+
+#define LB_HIP(call, what)                          \
+    do {                                            \
+        hipError_t e_ = (call);                     \
+        if (e_ != hipSuccess) return hip_fail(e_, what); \
+    } while (0)
+
+// Relaxation rates and weights of Theorem 2 (Sec. III.D, parameter solution):
+//   s1 = 2/(6 eps + 1), s21 = 24 eps/(6 eps + 1)^2, s22 = 4/(6 eps + 3),
+//   w1 = 1/6 - (d-1) eps/3 (1/6 in 1-D), w_{1+2d} = eps/6 (absent in 1-D),
+//   w0 = 1 - 2 d w1 - 2 d (d-1) w_{1+2d}  (weight structure, Sec. III.A),
+// plus their eps-derivatives for the adjoint.
+Rates make_rates(int d, double dx, double dt, double nu) {
+    Rates r;
+    const double eps = nu * dt / (dx * dx);
+    const double a6 = 6.0 * eps + 1.0;
+    r.eps = eps;
+    r.s1 = 2.0 / a6;
+    r.s21 = 24.0 * eps / (a6 * a6);
+    r.s22 = 4.0 / (6.0 * eps + 3.0);
+    double dw1, dwd;
+    if (d == 1) {
+        r.w1 = 1.0 / 6.0;
+        r.wd = 0.0;
+        dw1 = 0.0;
+        dwd = 0.0;
+    } else {
+        r.w1 = 1.0 / 6.0 - (d - 1) * eps / 3.0;
+        r.wd = eps / 6.0;
+        dw1 = -(d - 1) / 3.0;
+        dwd = 1.0 / 6.0;
+    }
+    r.w0 = 1.0 - 2.0 * d * r.w1 - 2.0 * d * (d - 1) * r.wd;
+    r.one_m_s1 = 1.0 - r.s1;
+    r.one_m_s21 = 1.0 - r.s21;
+    r.one_m_s22 = 1.0 - r.s22;
+    r.R4wd = 4.0 * r.wd;
+    r.c = dx / dt;
+    r.ucoef = (2.0 - r.s1) * r.c;
+    r.dx = dx;
+    r.inv_s1_m1 = 1.0 / r.s1 - 1.0;
+    r.inv12dx = 1.0 / (12.0 * dx);
+    r.ds1 = -12.0 / (a6 * a6);
+    r.ds21 = 24.0 * (1.0 - 6.0 * eps) / (a6 * a6 * a6);
+    r.ds22 = -24.0 / ((6.0 * eps + 3.0) * (6.0 * eps + 3.0));
+    r.dw1 = dw1;
+    r.dwd = dwd;
+    r.dw0 = -2.0 * d * dw1 - 2.0 * d * (d - 1) * dwd;
+    r.dinv_s1 = 3.0;
+    return r;
+}
+
+int q_of(int d) { return d == 1 ? 3 : (d == 2 ? 9 : (d == 3 ? 19 : 0)); }
+
+lb_status validate(const lb_config* c) {
+    if (!c) return fail(LB_ERR_INVALID_ARG, "config is NULL");
+    if (c->dim < 1 || c->dim > 3) return fail(LB_ERR_INVALID_ARG, "dim must be 1, 2 or 3");
+    if (c->flags != 0) return fail(LB_ERR_INVALID_ARG, "flags must be 0");
+    int64_t V = 1;
+    for (int a = 0; a < 3; ++a) {
+        if (c->n[a] < 1) return fail(LB_ERR_INVALID_ARG, "every n[a] must be >= 1");
+        if (a >= c->dim && c->n[a] != 1)
+            return fail(LB_ERR_INVALID_ARG, "n[a] must be 1 for a >= dim");
+        if (c->n[a] > INT_MAX) return fail(LB_ERR_INVALID_ARG, "n[a] too large");
+        V *= c->n[a];
+        if (V > (int64_t)INT_MAX) return fail(LB_ERR_INVALID_ARG, "more than 2^31-1 nodes");
+    }
+    if (c->dim >= 2 && (c->n[1] + 3) / 4 > 65535)
+        return fail(LB_ERR_INVALID_ARG, "n[1] exceeds the launch-grid limit");
+    if (c->dim == 3 && c->n[2] > 65535)
+        return fail(LB_ERR_INVALID_ARG, "n[2] exceeds the launch-grid limit");
+    if (!(c->dx > 0) || !(c->dt > 0) || !(c->nu > 0) || !std::isfinite(c->dx) ||
+        !std::isfinite(c->dt) || !std::isfinite(c->nu))
+        return fail(LB_ERR_INVALID_ARG, "dx, dt and nu must be finite and > 0");
+    const double eps = c->nu * c->dt / (c->dx * c->dx);
+    if (!std::isfinite(eps) || !(eps > 0)) return fail(LB_ERR_INVALID_ARG, "eps is not finite");
+    if (c->dim == 2 && eps >= 0.5)
+        return fail(LB_ERR_UNSTABLE, "D2Q9 needs eps < 0.5 (w1 = 1/6 - eps/3 > 0)");
+    if (c->dim == 3 && eps > 0.25)
+        return fail(LB_ERR_UNSTABLE, "D3Q19 needs eps <= 0.25 (w1 = 1/6 - 2 eps/3 >= 0)");
+    return LB_OK;
+}
+
+// Plane stride: whole 2 KiB blocks plus one extra block on large grids, so
+// the q planes do not all start on the same large power-of-two boundary.
+int64_t stride_of(int64_t V) {
+    if (V < 65536) return (V + 63) / 64 * 64;
+    return (V + 255) / 256 * 256 + 256;
+}
+
+Geo make_geo(const lb_config* c) {
+    Geo g;
+    g.nx = (int)c->n[0];
+    g.ny = (int)c->n[1];
+    g.nz = (int)c->n[2];
+    g.V = (int64_t)g.nx * g.ny * g.nz;
+    g.stride = stride_of(g.V);
+    return g;
+}
+
+}  // namespace
+
+struct lb_solver {
+    lb_config cfg;
+    int d, q;
+    Geo g;
+    Rates r;
+    hipStream_t stream;
+    double* buf[2];
+    int cur;
+    int64_t steps;
+    bool inited;
+    double* partials;
+    int64_t npartials;
+    int* flag;
+};
+
+extern "C" {
+
+const char* lb_last_error(void) { return g_err.c_str(); }
+
+int32_t lb_num_populations(int32_t dim) { return q_of(dim); }
+
+lb_status lb_parameters(const lb_config* cfg, double* out7) {
+    lb_status st = validate(cfg);
+    if (st == LB_ERR_UNSTABLE) st = LB_OK;  // parameters are defined for any eps > 0
+    if (st != LB_OK) return st;
+    if (!out7) return fail(LB_ERR_INVALID_ARG, "out is NULL");
+    const Rates r = make_rates(cfg->dim, cfg->dx, cfg->dt, cfg->nu);
+    out7[0] = r.eps;
+    out7[1] = r.s1;
+    out7[2] = r.s21;
+    out7[3] = r.s22;
+    out7[4] = r.w0;
+    out7[5] = r.w1;
+    out7[6] = r.wd;
+    return LB_OK;
+}
+
+int64_t lb_state_stride(const lb_config* cfg) {
+    if (validate(cfg) == LB_ERR_INVALID_ARG) return 0;
+    return make_geo(cfg).stride;
+}
+
+size_t lb_state_bytes(const lb_config* cfg) {
+    if (validate(cfg) == LB_ERR_INVALID_ARG) return 0;
+    return (size_t)q_of(cfg->dim) * (size_t)make_geo(cfg).stride * sizeof(double);
+}
+
+lb_status lb_create(const lb_config* cfg, void* hip_stream, double* f_a, double* f_b,
+                    lb_solver** out) {
+    if (!out) return fail(LB_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    lb_status st = validate(cfg);
+    if (st != LB_OK) return st;
+    if (!f_a || !f_b) return fail(LB_ERR_INVALID_ARG, "state buffers must not be NULL");
+    const size_t bytes = lb_state_bytes(cfg);
+    const char* a = (const char*)f_a;
+    const char* b = (const char*)f_b;
+    if (a < b + bytes && b < a + bytes) return fail(LB_ERR_INVALID_ARG, "f_a and f_b overlap");
+    lb_solver* s = new (std::nothrow) lb_solver();
+    if (!s) return fail(LB_ERR_OOM, "host allocation failed");
+    s->cfg = *cfg;
+    s->d = cfg->dim;
+    s->q = q_of(cfg->dim);
+    s->g = make_geo(cfg);
+    s->r = make_rates(cfg->dim, cfg->dx, cfg->dt, cfg->nu);
+    s->stream = (hipStream_t)hip_stream;
+    s->buf[0] = f_a;
+    s->buf[1] = f_b;
+    s->cur = 0;
+    s->steps = 0;
+    s->inited = false;
+    s->npartials = lbm::launch_shape(s->d, s->g).nblocks;
+    s->partials = nullptr;
+    s->flag = nullptr;
+    hipError_t e = hipMalloc((void**)&s->partials, sizeof(double) * (size_t)s->npartials);
+    if (e == hipSuccess) e = hipMalloc((void**)&s->flag, sizeof(int));
+    if (e != hipSuccess) {
+        if (s->partials) (void)hipFree(s->partials);
+        delete s;
+        return hip_fail(e, "hipMalloc of solver tables");
+    }
+    *out = s;
+    return LB_OK;
+}
+
+lb_status lb_destroy(lb_solver* s) {
+    if (!s) return LB_OK;
+    if (s->partials) (void)hipFree(s->partials);
+    if (s->flag) (void)hipFree(s->flag);
+    delete s;
+    return LB_OK;
+}
+
+static lb_status check_theta(lb_solver* s, const double* theta, int64_t n) {
+    LB_HIP(hipMemsetAsync(s->flag, 0, sizeof(int), s->stream), "hipMemsetAsync");
+    LB_HIP(lbm::launch_check_theta(theta, n, s->flag, s->stream), "check_theta launch");
+    int h = 0;
+    LB_HIP(hipMemcpyAsync(&h, s->flag, sizeof(int), hipMemcpyDeviceToHost, s->stream),
+           "hipMemcpyAsync");
+    LB_HIP(hipStreamSynchronize(s->stream), "hipStreamSynchronize");
+    if (h) return fail(LB_ERR_NONFINITE, "theta0 must be finite and > 0 (Cole-Hopf)");
+    return LB_OK;
+}
+
+lb_status lb_init(lb_solver* s, const double* theta0, const double* grad_theta0,
+                  int32_t check) {
+    if (!s || !theta0) return fail(LB_ERR_INVALID_ARG, "solver and theta0 must not be NULL");
+    if (check) {
+        lb_status st = check_theta(s, theta0, s->g.V);
+        if (st != LB_OK) return st;
+    }
+    LB_HIP(lbm::launch_init(s->d, s->g, s->r, theta0, grad_theta0, s->buf[0], s->stream),
+           "init launch");
+    s->cur = 0;
+    s->steps = 0;
+    s->inited = true;
+    return LB_OK;
+}
+
+lb_status lb_step(lb_solver* s, int64_t nsteps) {
+    if (!s) return fail(LB_ERR_INVALID_ARG, "solver is NULL");
+    if (nsteps < 0) return fail(LB_ERR_INVALID_ARG, "nsteps must be >= 0");
+    if (!s->inited) return fail(LB_ERR_STATE, "lb_step before lb_init/lb_set_state");
+    for (int64_t n = 0; n < nsteps; ++n) {
+        LB_HIP(lbm::launch_step(s->d, s->g, s->r, s->buf[s->cur], s->buf[1 - s->cur], s->stream),
+               "step launch");
+        s->cur ^= 1;
+        ++s->steps;
+    }
+    return LB_OK;
+}
+
+lb_status lb_step_buffers(lb_solver* s, const double* src, double* dst) {
+    if (!s || !src || !dst) return fail(LB_ERR_INVALID_ARG, "NULL argument");
+    if (src == dst) return fail(LB_ERR_INVALID_ARG, "src and dst must differ");
+    LB_HIP(lbm::launch_step(s->d, s->g, s->r, src, dst, s->stream), "step launch");
+    return LB_OK;
+}
+
+double* lb_current_state(const lb_solver* s) { return s ? s->buf[s->cur] : nullptr; }
+int64_t lb_steps_taken(const lb_solver* s) { return s ? s->steps : -1; }
+
+lb_status lb_macro_buffer(lb_solver* s, const double* state, double* theta, double* u) {
+    if (!s || !state) return fail(LB_ERR_INVALID_ARG, "NULL argument");
+    if (!theta && !u) return LB_OK;
+    LB_HIP(lbm::launch_macro(s->d, s->g, s->r, state, theta, u, s->stream), "macro launch");
+    return LB_OK;
+}
+
+lb_status lb_macro(lb_solver* s, double* theta, double* u) {
+    if (!s) return fail(LB_ERR_INVALID_ARG, "solver is NULL");
+    if (!s->inited) return fail(LB_ERR_STATE, "lb_macro before lb_init/lb_set_state");
+    return lb_macro_buffer(s, s->buf[s->cur], theta, u);
+}
+
+lb_status lb_get_state(lb_solver* s, double* f_out) {
+    if (!s || !f_out) return fail(LB_ERR_INVALID_ARG, "NULL argument");
+    if (!s->inited) return fail(LB_ERR_STATE, "no state yet");
+    LB_HIP(lbm::launch_get_state(s->d, s->g, s->buf[s->cur], f_out, s->stream), "get_state");
+    return LB_OK;
+}
+
+lb_status lb_set_state(lb_solver* s, const double* f_in, int64_t step) {
+    if (!s || !f_in) return fail(LB_ERR_INVALID_ARG, "NULL argument");
+    if (step < 0) return fail(LB_ERR_INVALID_ARG, "step must be >= 0");
+    LB_HIP(lbm::launch_set_state(s->d, s->g, f_in, s->buf[0], s->stream), "set_state");
+    s->cur = 0;
+    s->steps = step;
+    s->inited = true;
+    return LB_OK;
+}
+
+lb_status lb_macro_adjoint(lb_solver* s, const double* state, const double* g_theta,
+                           const double* g_u, double* lambda, double* g_eps) {
+    if (!s || !state || !lambda || !g_eps) return fail(LB_ERR_INVALID_ARG, "NULL argument");
+    LB_HIP(lbm::launch_macro_adjoint(s->d, s->g, s->r, state, g_theta, g_u, lambda, s->partials,
+                                     s->stream),
+           "macro_adjoint launch");
+    LB_HIP(lbm::launch_finalize(s->partials, s->npartials, g_eps, s->stream), "finalize");
+    return LB_OK;
+}
+
+lb_status lb_adjoint_step(lb_solver* s, const double* state_n, const double* lambda_in,
+                          double* lambda_out, double* g_eps) {
+    if (!s || !state_n || !lambda_in || !lambda_out || !g_eps)
+        return fail(LB_ERR_INVALID_ARG, "NULL argument");
+    if (lambda_in == lambda_out) return fail(LB_ERR_INVALID_ARG, "lambda_in == lambda_out");
+    LB_HIP(lbm::launch_adjoint_step(s->d, s->g, s->r, state_n, lambda_in, lambda_out, s->partials,
+                                    s->stream),
+           "adjoint_step launch");
+    LB_HIP(lbm::launch_finalize(s->partials, s->npartials, g_eps, s->stream), "finalize");
+    return LB_OK;
+}
+
+lb_status lb_init_adjoint(lb_solver* s, const double* theta0, const double* grad_theta0,
+                          const double* lambda0, double* g_theta0, double* g_grad,
+                          double* g_eps) {
+    if (!s || !theta0 || !lambda0 || !g_theta0 || !g_eps)
+        return fail(LB_ERR_INVALID_ARG, "NULL argument");
+    LB_HIP(lbm::launch_init_adjoint(s->d, s->g, s->r, theta0, grad_theta0, lambda0, g_theta0,
+                                    g_grad, s->partials, s->stream),
+           "init_adjoint launch");
+    LB_HIP(lbm::launch_finalize(s->partials, s->npartials, g_eps, s->stream), "finalize");
+    return LB_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// batched form
+// ---------------------------------------------------------------------------
+
+struct lb_batch {
+    std::vector<lb_config> cfgs;
+    std::vector<int64_t> offsets, strides, node_offsets;
+    std::vector<BatchInst> insts;
+    hipStream_t stream;
+    hipStream_t capture;
+    double* pool[2];
+    int64_t pool_elems;
+    int cur;
+    int64_t steps;
+    bool inited;
+    BatchInst* d_insts;
+    BatchTile* d_tiles;
+    int64_t ntiles;
+    int tx, ty;
+    std::map<std::pair<int64_t, int>, hipGraphExec_t> graphs;
+};
+
+static void drop_graphs(lb_batch* b) {
+    for (auto& kv : b->graphs) (void)hipGraphExecDestroy(kv.second);
+    b->graphs.clear();
+}
+
+static lb_status build_tiles(lb_batch* b, int tx, int ty) {
+    std::vector<BatchTile> tiles;
+    for (size_t i = 0; i < b->insts.size(); ++i) {
+        const BatchInst& in = b->insts[i];
+        for (int y0 = 0; y0 < in.ny; y0 += ty)
+            for (int x0 = 0; x0 < in.nx; x0 += tx) tiles.push_back(BatchTile{(int)i, x0, y0, 0});
+    }
+    if (tiles.size() > (size_t)INT_MAX) return fail(LB_ERR_INVALID_ARG, "too many tiles");
+    if (b->d_tiles) (void)hipFree(b->d_tiles);
+    b->d_tiles = nullptr;
+    if (!tiles.empty()) {
+        LB_HIP(hipMalloc((void**)&b->d_tiles, sizeof(BatchTile) * tiles.size()), "hipMalloc tiles");
+        LB_HIP(hipMemcpy(b->d_tiles, tiles.data(), sizeof(BatchTile) * tiles.size(),
+                         hipMemcpyHostToDevice),
+               "hipMemcpy tiles");
+    }
+    b->ntiles = (int64_t)tiles.size();
+    b->tx = tx;
+    b->ty = ty;
+    drop_graphs(b);
+    return LB_OK;
+}
+
+extern "C" {
+
+int64_t lb_batch_layout(const lb_config* cfgs, int32_t count, int64_t* offsets,
+                        int64_t* strides) {
+    if (count < 0 || (count > 0 && !cfgs)) return -1;
+    int64_t total = 0;
+    for (int32_t i = 0; i < count; ++i) {
+        if (validate(&cfgs[i]) == LB_ERR_INVALID_ARG || cfgs[i].dim != 2) return -1;
+        const int64_t st = make_geo(&cfgs[i]).stride;
+        if (offsets) offsets[i] = total;
+        if (strides) strides[i] = st;
+        total += 9 * st;
+    }
+    return total;
+}
+
+lb_status lb_batch_create(const lb_config* cfgs, int32_t count, void* hip_stream,
+                          double* pool_a, double* pool_b, lb_batch** out) {
+    if (!out) return fail(LB_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (count < 1 || !cfgs) return fail(LB_ERR_INVALID_ARG, "need at least one instance");
+    for (int32_t i = 0; i < count; ++i) {
+        lb_status st = validate(&cfgs[i]);
+        if (st != LB_OK) return st;
+        if (cfgs[i].dim != 2) return fail(LB_ERR_INVALID_ARG, "batched form is 2-D only");
+    }
+    if (!pool_a || !pool_b || pool_a == pool_b)
+        return fail(LB_ERR_INVALID_ARG, "two distinct pools are required");
+    lb_batch* b = new (std::nothrow) lb_batch();
+    if (!b) return fail(LB_ERR_OOM, "host allocation failed");
+    b->cfgs.assign(cfgs, cfgs + count);
+    b->offsets.resize(count);
+    b->strides.resize(count);
+    b->pool_elems = lb_batch_layout(cfgs, count, b->offsets.data(), b->strides.data());
+    int64_t nodes = 0;
+    for (int32_t i = 0; i < count; ++i) {
+        b->node_offsets.push_back(nodes);
+        nodes += cfgs[i].n[0] * cfgs[i].n[1];
+        BatchInst in;
+        in.offset = b->offsets[i];
+        in.stride = b->strides[i];
+        in.nx = (int)cfgs[i].n[0];
+        in.ny = (int)cfgs[i].n[1];
+        in.r = make_rates(2, cfgs[i].dx, cfgs[i].dt, cfgs[i].nu);
+        b->insts.push_back(in);
+    }
+    b->stream = (hipStream_t)hip_stream;
+    b->capture = nullptr;
+    b->pool[0] = pool_a;
+    b->pool[1] = pool_b;
+    b->cur = 0;
+    b->steps = 0;
+    b->inited = false;
+    b->d_insts = nullptr;
+    b->d_tiles = nullptr;
+    b->ntiles = 0;
+    hipError_t e = hipMalloc((void**)&b->d_insts, sizeof(BatchInst) * b->insts.size());
+    if (e == hipSuccess)
+        e = hipMemcpy(b->d_insts, b->insts.data(), sizeof(BatchInst) * b->insts.size(),
+                      hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        if (b->d_insts) (void)hipFree(b->d_insts);
+        delete b;
+        return hip_fail(e, "batch setup");
+    }
+    lb_status st = build_tiles(b, 64, 4);
+    if (st != LB_OK) {
+        lb_batch_destroy(b);
+        return st;
+    }
+    *out = b;
+    return LB_OK;
+}
+
+lb_status lb_batch_destroy(lb_batch* b) {
+    if (!b) return LB_OK;
+    drop_graphs(b);
+    if (b->d_tiles) (void)hipFree(b->d_tiles);
+    if (b->d_insts) (void)hipFree(b->d_insts);
+    if (b->capture) (void)hipStreamDestroy(b->capture);
+    delete b;
+    return LB_OK;
+}
+
+lb_status lb_batch_init(lb_batch* b, const double* theta0, const double* grad) {
+    if (!b || !theta0) return fail(LB_ERR_INVALID_ARG, "NULL argument");
+    for (size_t i = 0; i < b->insts.size(); ++i) {
+        const lb_config* c = &b->cfgs[i];
+        Geo g = make_geo(c);
+        const int64_t no = b->node_offsets[i];
+        LB_HIP(lbm::launch_init(2, g, b->insts[i].r, theta0 + no, grad ? grad + 2 * no : nullptr,
+                                b->pool[0] + b->offsets[i], b->stream),
+               "batch init launch");
+    }
+    b->cur = 0;
+    b->steps = 0;
+    b->inited = true;
+    return LB_OK;
+}
+
+lb_status lb_batch_set_tile(lb_batch* b, int32_t tx, int32_t ty) {
+    if (!b) return fail(LB_ERR_INVALID_ARG, "batch is NULL");
+    if (tx < 16 || tx > 256 || (tx & (tx - 1)) != 0 || tx * ty != 256)
+        return fail(LB_ERR_INVALID_ARG, "tile must be tx*ty = 256 with tx a power of two in [16,256]");
+    if (tx == b->tx && ty == b->ty) return LB_OK;
+    return build_tiles(b, tx, ty);
+}
+
+static lb_status batch_launch_plain(lb_batch* b, int64_t nsteps, hipStream_t st, int cur) {
+    for (int64_t n = 0; n < nsteps; ++n) {
+        LB_HIP(lbm::launch_batch_step(b->d_insts, b->d_tiles, b->ntiles, b->tx, b->ty, b->pool[cur],
+                                      b->pool[1 - cur], st),
+               "batch step launch");
+        cur ^= 1;
+    }
+    return LB_OK;
+}
+
+lb_status lb_batch_step(lb_batch* b, int64_t nsteps, int32_t use_graph) {
+    if (!b) return fail(LB_ERR_INVALID_ARG, "batch is NULL");
+    if (nsteps < 0) return fail(LB_ERR_INVALID_ARG, "nsteps must be >= 0");
+    if (!b->inited) return fail(LB_ERR_STATE, "lb_batch_step before lb_batch_init");
+    if (nsteps == 0) return LB_OK;
+    if (!use_graph) {
+        lb_status st = batch_launch_plain(b, nsteps, b->stream, b->cur);
+        if (st != LB_OK) return st;
+    } else {
+        auto key = std::make_pair(nsteps, b->cur);
+        auto it = b->graphs.find(key);
+        if (it == b->graphs.end()) {
+            hipGraph_t graph = nullptr;
+            LB_HIP(hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal),
+                   "hipStreamBeginCapture");
+            lb_status st = batch_launch_plain(b, nsteps, b->capture, b->cur);
+            hipError_t e = hipStreamEndCapture(b->capture, &graph);
+            if (st != LB_OK) {
+                if (graph) (void)hipGraphDestroy(graph);
+                return st;
+            }
+            if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+            hipGraphExec_t exec = nullptr;
+            e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+            it = b->graphs.emplace(key, exec).first;
+        }
+        LB_HIP(hipGraphLaunch(it->second, b->stream), "hipGraphLaunch");
+    }
+    if (nsteps & 1) b->cur ^= 1;
+    b->steps += nsteps;
+    return LB_OK;
+}
+
+lb_status lb_batch_autotune(lb_batch* b, int32_t steps_per_trial, int32_t* best_tx,
+                            int32_t* best_ty) {
+    if (!b) return fail(LB_ERR_INVALID_ARG, "batch is NULL");
+    if (!b->inited) return fail(LB_ERR_STATE, "autotune needs an initialised batch");
+    if (steps_per_trial < 1) steps_per_trial = 1;
+    static const int cand[][2] = {{256, 1}, {128, 2}, {64, 4}, {32, 8}, {16, 16}};
+    hipEvent_t e0, e1;
+    LB_HIP(hipEventCreate(&e0), "hipEventCreate");
+    LB_HIP(hipEventCreate(&e1), "hipEventCreate");
+    float best = 1e30f;
+    int bx = b->tx, by = b->ty;
+    lb_status st = LB_OK;
+    for (const auto& c : cand) {
+        st = build_tiles(b, c[0], c[1]);
+        if (st != LB_OK) break;
+        // Trials always step pool[cur] -> pool[1-cur]: the current state is
+        // untouched and the other pool is scratch.
+        auto trial = [&](int reps) -> lb_status {
+            for (int r = 0; r < reps; ++r)
+                LB_HIP(lbm::launch_batch_step(b->d_insts, b->d_tiles, b->ntiles, b->tx, b->ty,
+                                              b->pool[b->cur], b->pool[1 - b->cur], b->stream),
+                       "batch step launch");
+            return LB_OK;
+        };
+        if ((st = trial(1)) != LB_OK) break;
+        if (hipEventRecord(e0, b->stream) != hipSuccess) { st = fail(LB_ERR_HIP, "event"); break; }
+        if ((st = trial(steps_per_trial)) != LB_OK) break;
+        if (hipEventRecord(e1, b->stream) != hipSuccess) { st = fail(LB_ERR_HIP, "event"); break; }
+        if (hipEventSynchronize(e1) != hipSuccess) { st = fail(LB_ERR_HIP, "event sync"); break; }
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (ms < best) {
+            best = ms;
+            bx = c[0];
+            by = c[1];
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != LB_OK) return st;
+    st = build_tiles(b, bx, by);
+    if (st != LB_OK) return st;
+    if (best_tx) *best_tx = bx;
+    if (best_ty) *best_ty = by;
+    return LB_OK;
+}
+
+lb_status lb_batch_macro(lb_batch* b, double* theta, double* u) {
+    if (!b) return fail(LB_ERR_INVALID_ARG, "batch is NULL");
+    if (!b->inited) return fail(LB_ERR_STATE, "lb_batch_macro before lb_batch_init");
+    if (!theta && !u) return LB_OK;
+    for (size_t i = 0; i < b->insts.size(); ++i) {
+        Geo g = make_geo(&b->cfgs[i]);
+        const int64_t no = b->node_offsets[i];
+        LB_HIP(lbm::launch_macro(2, g, b->insts[i].r, b->pool[b->cur] + b->offsets[i],
+                                 theta ? theta + no : nullptr, u ? u + 2 * no : nullptr, b->stream),
+               "batch macro launch");
+    }
+    return LB_OK;
+}
+
+double* lb_batch_current(const lb_batch* b) { return b ? b->pool[b->cur] : nullptr; }
+
+}  // extern "C"

@@ -1,0 +1,64 @@
+// Host-side launchers of the HIP kernels (defined in lbm_kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lbm_lattice.h"
+
+namespace lbm {
+
+struct Geo {
+    int nx, ny, nz;     // nodes per axis (1 for unused axes)
+    int64_t V;          // nx * ny * nz
+    int64_t stride;     // elements between population planes
+};
+
+// Launch shape of the per-node kernels for one grid.
+struct Launch {
+    dim3 grid, block;
+    int64_t nblocks;
+};
+Launch launch_shape(int d, const Geo& g);
+
+hipError_t launch_step(int d, const Geo& g, const Rates& r, const double* src, double* dst,
+                       hipStream_t st);
+hipError_t launch_init(int d, const Geo& g, const Rates& r, const double* theta0,
+                       const double* grad, double* dst, hipStream_t st);
+hipError_t launch_macro(int d, const Geo& g, const Rates& r, const double* state, double* theta,
+                        double* u, hipStream_t st);
+hipError_t launch_get_state(int d, const Geo& g, const double* state, double* dense,
+                            hipStream_t st);
+hipError_t launch_set_state(int d, const Geo& g, const double* dense, double* state,
+                            hipStream_t st);
+hipError_t launch_check_theta(const double* theta, int64_t n, int* flag, hipStream_t st);
+
+// Adjoint kernels write one partial sum of the eps-gradient per block into
+// `partials`; launch_finalize then adds their sum (fixed order) to *g_eps.
+hipError_t launch_macro_adjoint(int d, const Geo& g, const Rates& r, const double* state,
+                                const double* g_theta, const double* g_u, double* lambda,
+                                double* partials, hipStream_t st);
+hipError_t launch_adjoint_step(int d, const Geo& g, const Rates& r, const double* state,
+                               const double* lam_in, double* lam_out, double* partials,
+                               hipStream_t st);
+hipError_t launch_init_adjoint(int d, const Geo& g, const Rates& r, const double* theta0,
+                               const double* grad, const double* lambda0, double* g_theta0,
+                               double* g_grad, double* partials, hipStream_t st);
+hipError_t launch_finalize(const double* partials, int64_t n, double* g_eps, hipStream_t st);
+
+// Batched 2-D form.
+struct BatchInst {
+    int64_t offset;     // first element of plane 0 in the pool
+    int64_t stride;     // plane stride
+    int nx, ny;
+    Rates r;
+};
+struct BatchTile {
+    int inst;           // instance index
+    int x0, y0;         // tile origin
+    int pad;
+};
+hipError_t launch_batch_step(const BatchInst* insts, const BatchTile* tiles, int64_t ntiles,
+                             int tx, int ty, const double* src, double* dst, hipStream_t st);
+
+}  // namespace lbm

@@ -1,0 +1,556 @@
+// HIP kernels (gfx950) of the Cole-Hopf fourth-order MRT-LB solver.
+//
+// Data layout: a state buffer holds q planes of `stride` doubles (structure
+// of arrays, x fastest).  It is kept "stream-shifted": element k of plane i
+// is the post-collision population that arrives at node k + e_i at the next
+// step, so one time step is a pull:
+//     f_i(x) = src_i(x - e_i)          (pre-collision distribution at x)
+//     dst_i(x) = (C f(x))_i            (collision, Sec. III.A)
+// Every store is aligned and coalesced; the loads of a wavefront are 64
+// consecutive doubles shifted by at most one element.  The update is
+// HBM-bound (q*8 bytes read + q*8 written per node and step, a few flops per
+// byte), so no matrix cores are used.
+//
+// Every thread owns one node; blocks are 256 threads (64 x 4 in 2-D/3-D,
+// one wavefront per row segment), z (3-D) runs over grid.z.
+#include <type_traits>
+
+#include "lbm_kernels.h"
+
+namespace lbm {
+namespace {
+
+constexpr int BX = 64;   // threads along x (2-D/3-D)
+constexpr int BY = 4;    // rows per block (2-D/3-D)
+constexpr int B1 = 256;  // threads per block (1-D)
+
+// Offsets of the neighbour x - e (e = -1, 0, +1) along each axis, periodic.
+struct Nbr {
+    int sx[3];
+    int sy[3];
+    int sz[3];
+};
+
+template <int D>
+__device__ __forceinline__ Nbr make_nbr(int x, int y, int z, const Geo& g) {
+    Nbr nb;
+    const int xm = x == 0 ? g.nx - 1 : x - 1;
+    const int xp = x == g.nx - 1 ? 0 : x + 1;
+    nb.sx[0] = xp;
+    nb.sx[1] = x;
+    nb.sx[2] = xm;
+    if constexpr (D >= 2) {
+        const int ym = y == 0 ? g.ny - 1 : y - 1;
+        const int yp = y == g.ny - 1 ? 0 : y + 1;
+        nb.sy[0] = yp * g.nx;
+        nb.sy[1] = y * g.nx;
+        nb.sy[2] = ym * g.nx;
+    } else {
+        nb.sy[0] = nb.sy[1] = nb.sy[2] = 0;
+    }
+    if constexpr (D == 3) {
+        const int nxy = g.nx * g.ny;
+        const int zm = z == 0 ? g.nz - 1 : z - 1;
+        const int zp = z == g.nz - 1 ? 0 : z + 1;
+        nb.sz[0] = zp * nxy;
+        nb.sz[1] = z * nxy;
+        nb.sz[2] = zm * nxy;
+    } else {
+        nb.sz[0] = nb.sz[1] = nb.sz[2] = 0;
+    }
+    return nb;
+}
+
+// Index of x - e_i (pull source) and x + e_i (push target).
+template <int D>
+__device__ __forceinline__ int pull_index(const Nbr& nb, int i) {
+    return nb.sz[Lat<D>::E[i][2] + 1] + nb.sy[Lat<D>::E[i][1] + 1] + nb.sx[Lat<D>::E[i][0] + 1];
+}
+template <int D>
+__device__ __forceinline__ int push_index(const Nbr& nb, int i) {
+    return nb.sz[1 - Lat<D>::E[i][2]] + nb.sy[1 - Lat<D>::E[i][1]] + nb.sx[1 - Lat<D>::E[i][0]];
+}
+
+template <int D>
+__device__ __forceinline__ bool thread_node(const Geo& g, int& x, int& y, int& z) {
+    if constexpr (D == 1) {
+        x = blockIdx.x * B1 + threadIdx.x;
+        y = 0;
+        z = 0;
+    } else {
+        x = blockIdx.x * BX + threadIdx.x;
+        y = blockIdx.y * BY + threadIdx.y;
+        z = (D == 3) ? (int)blockIdx.z : 0;
+    }
+    return x < g.nx && y < g.ny;
+}
+
+__device__ __forceinline__ int node_index(const Geo& g, int x, int y, int z) {
+    return (z * g.ny + y) * g.nx + x;
+}
+
+// Deterministic sum over the 256 threads of a block; result valid in thread 0.
+__device__ __forceinline__ double block_sum(double v) {
+    __shared__ double sh[4];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    const int tid = threadIdx.x + threadIdx.y * blockDim.x;
+    if ((tid & 63) == 0) sh[tid >> 6] = v;
+    __syncthreads();
+    return tid == 0 ? (sh[0] + sh[1]) + (sh[2] + sh[3]) : 0.0;
+}
+
+__device__ __forceinline__ int64_t block_linear() {
+    return (int64_t)blockIdx.x + (int64_t)gridDim.x * ((int64_t)blockIdx.y + (int64_t)gridDim.y * blockIdx.z);
+}
+
+// ---------------------------------------------------------------------------
+// time step
+// ---------------------------------------------------------------------------
+template <int D>
+__global__ void __launch_bounds__(256) k_step(const double* __restrict__ src,
+                                              double* __restrict__ dst, Geo g, Rates r) {
+    constexpr int Q = Lat<D>::Q;
+    int x, y, z;
+    if (!thread_node<D>(g, x, y, z)) return;
+    const Nbr nb = make_nbr<D>(x, y, z, g);
+    double f[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) f[i] = src[(int64_t)i * g.stride + pull_index<D>(nb, i)];
+    collide<D>(f, r);
+    const int k = node_index(g, x, y, z);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) __builtin_nontemporal_store(f[i], dst + (int64_t)i * g.stride + k);
+}
+
+// ---------------------------------------------------------------------------
+// initialisation
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int wrapi(int v, int n) {
+    v %= n;
+    return v < 0 ? v + n : v;
+}
+
+// Fourth-order central difference of theta along axis a at node (x,y,z).
+template <int D>
+__device__ double fd4(const double* __restrict__ th, const Geo& g, int x, int y, int z, int a,
+                      double inv12dx) {
+    int c[3] = {x, y, z};
+    const int n[3] = {g.nx, g.ny, g.nz};
+    double v[4];
+    const int off[4] = {2, 1, -1, -2};
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        int cc[3] = {c[0], c[1], c[2]};
+        cc[a] = wrapi(c[a] + off[t], n[a]);
+        v[t] = th[node_index(g, cc[0], cc[1], cc[2])];
+    }
+    return ((v[3] - v[0]) + 8.0 * (v[1] - v[2])) * inv12dx;
+}
+
+// dst_i(y) = f0_i(y + e_i) with the closed-form initial distribution
+// f0_i = w_i theta0 - dx w_i (e_i . g) - (1/s1 - 1)(dx/6) sum_a (d_{i,+a} - d_{i,-a}) g_a.
+template <int D>
+__global__ void __launch_bounds__(256) k_init(const double* __restrict__ th0,
+                                              const double* __restrict__ grad,
+                                              double* __restrict__ dst, Geo g, Rates r) {
+    constexpr int Q = Lat<D>::Q;
+    int x, y, z;
+    if (!thread_node<D>(g, x, y, z)) return;
+    const int k = node_index(g, x, y, z);
+    const double corr = r.inv_s1_m1 * r.dx * (1.0 / 6.0);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const int sx = wrapi(x + Lat<D>::E[i][0], g.nx);
+        const int sy = wrapi(y + Lat<D>::E[i][1], g.ny);
+        const int sz = wrapi(z + Lat<D>::E[i][2], g.nz);
+        const int src = node_index(g, sx, sy, sz);
+        const double t = th0[src];
+        double eg = 0.0, ax = 0.0;
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            const int e = Lat<D>::E[i][a];
+            if (e == 0) continue;
+            const double ga = grad ? grad[(int64_t)a * g.V + src] : fd4<D>(th0, g, sx, sy, sz, a, r.inv12dx);
+            eg = e == 1 ? eg + ga : eg - ga;
+            if (nnz<D>(i) == 1) ax = e == 1 ? ga : -ga;
+        }
+        const double w = weight<D>(i, r);
+        dst[(int64_t)i * g.stride + k] = w * t - r.dx * w * eg - corr * ax;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// macroscopic output, state conversions
+// ---------------------------------------------------------------------------
+template <int D>
+__global__ void __launch_bounds__(256) k_macro(const double* __restrict__ src,
+                                               double* __restrict__ theta, double* __restrict__ u,
+                                               Geo g, Rates r) {
+    constexpr int Q = Lat<D>::Q;
+    int x, y, z;
+    if (!thread_node<D>(g, x, y, z)) return;
+    const Nbr nb = make_nbr<D>(x, y, z, g);
+    double f[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) f[i] = src[(int64_t)i * g.stride + pull_index<D>(nb, i)];
+    double th = 0.0;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) th += f[i];
+    const int k = node_index(g, x, y, z);
+    if (theta) theta[k] = th;
+    if (u) {
+        const double inv = r.ucoef / th;
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            double j = 0.0;
+#pragma unroll
+            for (int i = 0; i < Q; ++i) j = LBM_SADD(j, Lat<D>::E[i][a], f[i]);
+            u[(int64_t)a * g.V + k] = j * inv;
+        }
+    }
+}
+
+template <int D>
+__global__ void __launch_bounds__(256) k_get_state(const double* __restrict__ src,
+                                                   double* __restrict__ dense, Geo g) {
+    constexpr int Q = Lat<D>::Q;
+    int x, y, z;
+    if (!thread_node<D>(g, x, y, z)) return;
+    const Nbr nb = make_nbr<D>(x, y, z, g);
+    const int k = node_index(g, x, y, z);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) dense[(int64_t)i * g.V + k] = src[(int64_t)i * g.stride + pull_index<D>(nb, i)];
+}
+
+template <int D>
+__global__ void __launch_bounds__(256) k_set_state(const double* __restrict__ dense,
+                                                   double* __restrict__ dst, Geo g) {
+    constexpr int Q = Lat<D>::Q;
+    int x, y, z;
+    if (!thread_node<D>(g, x, y, z)) return;
+    const Nbr nb = make_nbr<D>(x, y, z, g);
+    const int k = node_index(g, x, y, z);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) dst[(int64_t)i * g.stride + k] = dense[(int64_t)i * g.V + push_index<D>(nb, i)];
+}
+
+__global__ void __launch_bounds__(256) k_check_theta(const double* __restrict__ th, int64_t n,
+                                                     int* flag) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const double v = th[i];
+    if (!(v > 0.0) || !isfinite(v)) atomicOr(flag, 1);
+}
+
+// ---------------------------------------------------------------------------
+// adjoint
+// ---------------------------------------------------------------------------
+template <int D>
+__global__ void __launch_bounds__(256) k_macro_adjoint(const double* __restrict__ src,
+                                                       const double* __restrict__ gth,
+                                                       const double* __restrict__ gu,
+                                                       double* __restrict__ lam,
+                                                       double* __restrict__ partials, Geo g,
+                                                       Rates r) {
+    constexpr int Q = Lat<D>::Q;
+    int x, y, z;
+    double ge = 0.0;
+    if (thread_node<D>(g, x, y, z)) {
+        const Nbr nb = make_nbr<D>(x, y, z, g);
+        const int k = node_index(g, x, y, z);
+        double f[Q];
+#pragma unroll
+        for (int i = 0; i < Q; ++i) f[i] = src[(int64_t)i * g.stride + pull_index<D>(nb, i)];
+        double th = 0.0;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) th += f[i];
+        const double inv = 1.0 / th;
+        const double gt = gth ? gth[k] : 0.0;
+        double base = gt, coef[D];
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            double j = 0.0;
+#pragma unroll
+            for (int i = 0; i < Q; ++i) j = LBM_SADD(j, Lat<D>::E[i][a], f[i]);
+            const double ga = gu ? gu[(int64_t)a * g.V + k] : 0.0;
+            const double ua = r.ucoef * j * inv;
+            // d u_a / d f_i = (2 - s1) c e_ia / theta - u_a / theta
+            base -= ga * ua * inv;
+            coef[a] = ga * r.ucoef * inv;
+            // d u_a / d eps = -s1' c j_a / theta
+            ge += ga * (-r.ds1) * r.c * j * inv;
+        }
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            double v = base;
+#pragma unroll
+            for (int a = 0; a < D; ++a) v = LBM_SADD(v, Lat<D>::E[i][a], coef[a]);
+            lam[(int64_t)i * g.stride + k] = v;
+        }
+    }
+    const double s = block_sum(ge);
+    if (threadIdx.x == 0 && threadIdx.y == 0) partials[block_linear()] = s;
+}
+
+// lam_out(x) = C^T mu(x), mu_i(x) = lam_in_i(x + e_i); eps part <mu, C' f^n(x)>.
+template <int D>
+__global__ void __launch_bounds__(256) k_adjoint_step(const double* __restrict__ state,
+                                                      const double* __restrict__ lin,
+                                                      double* __restrict__ lout,
+                                                      double* __restrict__ partials, Geo g,
+                                                      Rates r) {
+    constexpr int Q = Lat<D>::Q;
+    int x, y, z;
+    double ge = 0.0;
+    if (thread_node<D>(g, x, y, z)) {
+        const Nbr nb = make_nbr<D>(x, y, z, g);
+        const int k = node_index(g, x, y, z);
+        double f[Q], mu[Q];
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            f[i] = state[(int64_t)i * g.stride + pull_index<D>(nb, i)];
+            mu[i] = lin[(int64_t)i * g.stride + push_index<D>(nb, i)];
+        }
+        double df[Q];
+        collide_deps<D>(f, r, df);
+#pragma unroll
+        for (int i = 0; i < Q; ++i) ge += mu[i] * df[i];
+        double lam[Q];
+        collide_adjoint<D>(mu, r, lam);
+#pragma unroll
+        for (int i = 0; i < Q; ++i) lout[(int64_t)i * g.stride + k] = lam[i];
+    }
+    const double s = block_sum(ge);
+    if (threadIdx.x == 0 && threadIdx.y == 0) partials[block_linear()] = s;
+}
+
+// h_a(x) = d L / d g_a(x) for the gradient input of the initialisation:
+//   h_a = -dx [ sum_i w_i e_ia lam_i + (1/s1 - 1)(1/6)(lam_{+a} - lam_{-a}) ].
+template <int D>
+__device__ __forceinline__ double init_h(const double* __restrict__ lam, const Geo& g, int k,
+                                         int a, const Rates& r) {
+    constexpr int Q = Lat<D>::Q;
+    double s = 0.0, ax = 0.0;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const int e = Lat<D>::E[i][a];
+        if (e == 0) continue;
+        const double l = lam[(int64_t)i * g.stride + k];
+        const double wl = weight<D>(i, r) * l;
+        s = e == 1 ? s + wl : s - wl;
+        if (nnz<D>(i) == 1) ax = e == 1 ? ax + l : ax - l;
+    }
+    return -r.dx * (s + r.inv_s1_m1 * (1.0 / 6.0) * ax);
+}
+
+template <int D>
+__global__ void __launch_bounds__(256) k_init_adjoint(const double* __restrict__ th0,
+                                                      const double* __restrict__ grad,
+                                                      const double* __restrict__ lam,
+                                                      double* __restrict__ gth,
+                                                      double* __restrict__ ggrad,
+                                                      double* __restrict__ partials, Geo g,
+                                                      Rates r) {
+    constexpr int Q = Lat<D>::Q;
+    int x, y, z;
+    double ge = 0.0;
+    if (thread_node<D>(g, x, y, z)) {
+        const int k = node_index(g, x, y, z);
+        double l[Q];
+#pragma unroll
+        for (int i = 0; i < Q; ++i) l[i] = lam[(int64_t)i * g.stride + k];
+        double gt = 0.0;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) gt += weight<D>(i, r) * l[i];
+        double gv[D];
+#pragma unroll
+        for (int a = 0; a < D; ++a)
+            gv[a] = grad ? grad[(int64_t)a * g.V + k] : fd4<D>(th0, g, x, y, z, a, r.inv12dx);
+        if (grad) {
+            if (ggrad) {
+#pragma unroll
+                for (int a = 0; a < D; ++a) ggrad[(int64_t)a * g.V + k] = init_h<D>(lam, g, k, a, r);
+            }
+        } else {
+            // g_theta0 += sum_a D_a^T h_a, D_a^T h(x) = (-h(x-2) + 8h(x-1) - 8h(x+1) + h(x+2)) / (12 dx)
+            const int c[3] = {x, y, z};
+            const int n[3] = {g.nx, g.ny, g.nz};
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+                const int off[4] = {-2, -1, 1, 2};
+                const double cf[4] = {-1.0, 8.0, -8.0, 1.0};
+                double acc = 0.0;
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    int cc[3] = {c[0], c[1], c[2]};
+                    cc[a] = wrapi(c[a] + off[t], n[a]);
+                    acc += cf[t] * init_h<D>(lam, g, node_index(g, cc[0], cc[1], cc[2]), a, r);
+                }
+                gt += acc * r.inv12dx;
+            }
+        }
+        gth[k] = gt;
+        // d f0_i / d eps = w_i' theta0 - dx w_i' (e_i . g) - (d(1/s1)/deps)(dx/6) (+-g_a on axis i)
+        const double t0 = th0[k];
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            double eg = 0.0, ax = 0.0;
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+                const int e = Lat<D>::E[i][a];
+                if (e == 0) continue;
+                eg = e == 1 ? eg + gv[a] : eg - gv[a];
+                if (nnz<D>(i) == 1) ax = e == 1 ? gv[a] : -gv[a];
+            }
+            const double dw = dweight<D>(i, r);
+            const double df = dw * t0 - r.dx * dw * eg - r.dinv_s1 * r.dx * (1.0 / 6.0) * ax;
+            ge += l[i] * df;
+        }
+    }
+    const double s = block_sum(ge);
+    if (threadIdx.x == 0 && threadIdx.y == 0) partials[block_linear()] = s;
+}
+
+__global__ void __launch_bounds__(256) k_finalize(const double* __restrict__ partials, int64_t n,
+                                                  double* g_eps) {
+    double v = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += 256) v += partials[i];
+    const double s = block_sum(v);
+    if (threadIdx.x == 0) *g_eps += s;
+}
+
+// ---------------------------------------------------------------------------
+// batched 2-D step over a tile table
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_batch_step(const BatchInst* __restrict__ insts,
+                                                    const BatchTile* __restrict__ tiles, int tx,
+                                                    int log2tx, const double* __restrict__ src,
+                                                    double* __restrict__ dst) {
+    constexpr int Q = 9;
+    const BatchTile t = tiles[blockIdx.x];
+    const BatchInst& in = insts[t.inst];
+    const int tid = threadIdx.x;
+    const int x = t.x0 + (tid & (tx - 1));
+    const int y = t.y0 + (tid >> log2tx);
+    if (x >= in.nx || y >= in.ny) return;
+    Geo g;
+    g.nx = in.nx;
+    g.ny = in.ny;
+    g.nz = 1;
+    g.V = (int64_t)in.nx * in.ny;
+    g.stride = in.stride;
+    const Nbr nb = make_nbr<2>(x, y, 0, g);
+    const double* s = src + in.offset;
+    double* d = dst + in.offset;
+    double f[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) f[i] = s[(int64_t)i * g.stride + pull_index<2>(nb, i)];
+    const Rates r = in.r;
+    collide<2>(f, r);
+    const int k = y * g.nx + x;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) __builtin_nontemporal_store(f[i], d + (int64_t)i * g.stride + k);
+}
+
+template <typename F>
+hipError_t dispatch(int d, F&& f) {
+    switch (d) {
+        case 1: return f(std::integral_constant<int, 1>{});
+        case 2: return f(std::integral_constant<int, 2>{});
+        case 3: return f(std::integral_constant<int, 3>{});
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace
+
+Launch launch_shape(int d, const Geo& g) {
+    Launch L;
+    if (d == 1) {
+        L.block = dim3(B1, 1, 1);
+        L.grid = dim3((unsigned)((g.nx + B1 - 1) / B1), 1, 1);
+    } else {
+        L.block = dim3(BX, BY, 1);
+        L.grid = dim3((unsigned)((g.nx + BX - 1) / BX), (unsigned)((g.ny + BY - 1) / BY),
+                      (unsigned)(d == 3 ? g.nz : 1));
+    }
+    L.nblocks = (int64_t)L.grid.x * L.grid.y * L.grid.z;
+    return L;
+}
+
+#define LBM_LAUNCH(kern, ...)                                                     \
+    dispatch(d, [&](auto dc) {                                                    \
+        constexpr int DD = decltype(dc)::value;                                   \
+        const Launch L = launch_shape(DD, g);                                     \
+        hipLaunchKernelGGL(kern<DD>, L.grid, L.block, 0, st, __VA_ARGS__);        \
+        return hipGetLastError();                                                 \
+    })
+
+hipError_t launch_step(int d, const Geo& g, const Rates& r, const double* src, double* dst,
+                       hipStream_t st) {
+    return LBM_LAUNCH(k_step, src, dst, g, r);
+}
+
+hipError_t launch_init(int d, const Geo& g, const Rates& r, const double* theta0,
+                       const double* grad, double* dst, hipStream_t st) {
+    return LBM_LAUNCH(k_init, theta0, grad, dst, g, r);
+}
+
+hipError_t launch_macro(int d, const Geo& g, const Rates& r, const double* state, double* theta,
+                        double* u, hipStream_t st) {
+    return LBM_LAUNCH(k_macro, state, theta, u, g, r);
+}
+
+hipError_t launch_get_state(int d, const Geo& g, const double* state, double* dense,
+                            hipStream_t st) {
+    return LBM_LAUNCH(k_get_state, state, dense, g);
+}
+
+hipError_t launch_set_state(int d, const Geo& g, const double* dense, double* state,
+                            hipStream_t st) {
+    return LBM_LAUNCH(k_set_state, dense, state, g);
+}
+
+hipError_t launch_check_theta(const double* theta, int64_t n, int* flag, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_check_theta, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, theta,
+                       n, flag);
+    return hipGetLastError();
+}
+
+hipError_t launch_macro_adjoint(int d, const Geo& g, const Rates& r, const double* state,
+                                const double* g_theta, const double* g_u, double* lambda,
+                                double* partials, hipStream_t st) {
+    return LBM_LAUNCH(k_macro_adjoint, state, g_theta, g_u, lambda, partials, g, r);
+}
+
+hipError_t launch_adjoint_step(int d, const Geo& g, const Rates& r, const double* state,
+                               const double* lam_in, double* lam_out, double* partials,
+                               hipStream_t st) {
+    return LBM_LAUNCH(k_adjoint_step, state, lam_in, lam_out, partials, g, r);
+}
+
+hipError_t launch_init_adjoint(int d, const Geo& g, const Rates& r, const double* theta0,
+                               const double* grad, const double* lambda0, double* g_theta0,
+                               double* g_grad, double* partials, hipStream_t st) {
+    return LBM_LAUNCH(k_init_adjoint, theta0, grad, lambda0, g_theta0, g_grad, partials, g, r);
+}
+
+hipError_t launch_finalize(const double* partials, int64_t n, double* g_eps, hipStream_t st) {
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, st, partials, n, g_eps);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_step(const BatchInst* insts, const BatchTile* tiles, int64_t ntiles,
+                             int tx, int ty, const double* src, double* dst, hipStream_t st) {
+    (void)ty;
+    int log2tx = 0;
+    while ((1 << log2tx) < tx) ++log2tx;
+    if (ntiles <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_batch_step, dim3((unsigned)ntiles), dim3(256), 0, st, insts, tiles, tx,
+                       log2tx, src, dst);
+    return hipGetLastError();
+}
+
+}  // namespace lbm

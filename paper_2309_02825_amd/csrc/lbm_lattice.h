@@ -1,0 +1,307 @@
+// Device-side lattice definitions and the per-node MRT collision for the
+// Cole-Hopf fourth-order MRT-LB scheme (arXiv:2309.02825, Sec. III).
+//
+// The collision is written in the natural-moment space of Sec. III.A without
+// forming M or M^-1:
+//   * moments kept: theta = sum f, j_a = sum e_a f, P_aa = sum e_a^2 f and
+//     (d > 1) P_ab = sum e_a e_b f (a < b);
+//   * post-collision moments (diagonal S, f^eq = w theta):
+//       j'_a  = (1 - s1) j_a
+//       P'_aa = P_aa - s21 (P_aa - theta/3)    (sum w e_a^2 = 1/3 under Theorem 2)
+//       P'_ab = (1 - s22) P_ab
+//       third- and fourth-order moments take their equilibrium values
+//       (rate 1): sum e_a e_b^2 w theta = 0, sum e_a^2 e_b^2 w theta = 4 w_d theta =: R'
+//   * f* = M^-1 m* in closed form.  Every natural-moment basis used here is a
+//     set of monomials e_a^p e_b^q ..., so M^-1 factorises into the 1-D map
+//     (mu0, mu1, mu2) -> (mu0 - mu2, (mu2 + mu1)/2, (mu2 - mu1)/2) per axis
+//     (moments that involve three axes vanish on D3Q19).  This gives
+//       rest:        theta - sum_a P'_aa + R' * (number of axis pairs)
+//       axis +-a:    (P'_aa +- j'_a)/2 - R' (d - 1)/2
+//       edge (a,b):  (e_a e_b P'_ab + R')/4.
+// The same reconstruction, fed with eps-derivatives of the post-collision
+// moments, gives (dC/deps) f; the transposed collision C^T is evaluated with
+// the dual moments nu = M^-T mu (see collide_adjoint).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lbm {
+
+// Relaxation rates and weights of Theorem 2 plus the derived constants the
+// kernels use.  Filled on the host (lbm_params.cpp).
+struct Rates {
+    double eps;
+    double s1, s21, s22;     // relaxation rates
+    double w0, w1, wd;       // weights of rest, axis and edge velocities
+    double one_m_s1, one_m_s21, one_m_s22;
+    double R4wd;             // 4 w_d (equilibrium of the c_a^2 c_b^2 moments per theta)
+    double ucoef;            // (2 - s1) dx / dt
+    double dx;               // node spacing
+    double inv_s1_m1;        // 1/s1 - 1
+    double inv12dx;          // 1 / (12 dx)
+    // d/deps of the above
+    double ds1, ds21, ds22, dw0, dw1, dwd;
+    double dinv_s1;          // d(1/s1)/deps = 3
+    double c;                // dx / dt
+};
+
+// Velocity tables in the order of Sec. III.A.
+template <int D> struct Lat;
+
+template <> struct Lat<1> {
+    static constexpr int Q = 3;
+    static constexpr int NP = 0;  // axis pairs
+    static constexpr int E[3][3] = {{0, 0, 0}, {1, 0, 0}, {-1, 0, 0}};
+};
+
+template <> struct Lat<2> {
+    static constexpr int Q = 9;
+    static constexpr int NP = 1;
+    static constexpr int E[9][3] = {{0, 0, 0},  {1, 0, 0},  {0, 1, 0},
+                                    {-1, 0, 0}, {0, -1, 0}, {1, 1, 0},
+                                    {-1, 1, 0}, {-1, -1, 0}, {1, -1, 0}};
+};
+
+template <> struct Lat<3> {
+    static constexpr int Q = 19;
+    static constexpr int NP = 3;
+    static constexpr int E[19][3] = {
+        {0, 0, 0},  {1, 0, 0},   {0, 1, 0},   {0, 0, 1},  {-1, 0, 0},
+        {0, -1, 0}, {0, 0, -1},  {1, 1, 0},   {-1, 1, 0}, {-1, -1, 0},
+        {1, -1, 0}, {1, 0, 1},   {-1, 0, 1},  {-1, 0, -1}, {1, 0, -1},
+        {0, 1, 1},  {0, -1, 1},  {0, -1, -1}, {0, 1, -1}};
+};
+
+// Pair index of axes (a, b), a < b: (0,1) -> 0, (0,2) -> 1, (1,2) -> 2.
+__host__ __device__ constexpr int pair_index(int a, int b) { return a == 0 ? b - 1 : 2; }
+
+template <int D> __host__ __device__ constexpr int nnz(int i) {
+    return (Lat<D>::E[i][0] != 0) + (Lat<D>::E[i][1] != 0) + (Lat<D>::E[i][2] != 0);
+}
+template <int D> __host__ __device__ constexpr int first_axis(int i) {
+    return Lat<D>::E[i][0] != 0 ? 0 : (Lat<D>::E[i][1] != 0 ? 1 : 2);
+}
+template <int D> __host__ __device__ constexpr int second_axis(int i) {
+    return Lat<D>::E[i][2] != 0 && first_axis<D>(i) != 2 ? 2 : 1;
+}
+
+// Signed add: acc + s*v for s in {-1, 0, 1} known at compile time.
+#define LBM_SADD(acc, s, v) ((s) == 1 ? (acc) + (v) : ((s) == -1 ? (acc) - (v) : (acc)))
+
+// Moments of a distribution held in registers.
+template <int D> struct Moments {
+    double theta;
+    double j[D];
+    double P[D];
+    double Pab[D == 3 ? 3 : 1];
+};
+
+template <int D>
+__device__ __forceinline__ void moments(const double (&f)[Lat<D>::Q], Moments<D>& m) {
+    constexpr int Q = Lat<D>::Q;
+    double th = 0.0;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) th += f[i];
+    m.theta = th;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        double j = 0.0, p = 0.0;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const int e = Lat<D>::E[i][a];
+            j = LBM_SADD(j, e, f[i]);
+            if (e != 0) p += f[i];
+        }
+        m.j[a] = j;
+        m.P[a] = p;
+    }
+    if constexpr (D > 1) {
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+#pragma unroll
+            for (int b = a + 1; b < D; ++b) {
+                double pab = 0.0;
+#pragma unroll
+                for (int i = 0; i < Q; ++i) {
+                    const int s = Lat<D>::E[i][a] * Lat<D>::E[i][b];
+                    pab = LBM_SADD(pab, s, f[i]);
+                }
+                m.Pab[pair_index(a, b)] = pab;
+            }
+        }
+    } else {
+        m.Pab[0] = 0.0;
+    }
+}
+
+// f = M^-1 m for the moment vector (theta, j, P, Pab, R) with all
+// third-order moments zero and every c_a^2 c_b^2 moment equal to R.
+template <int D>
+__device__ __forceinline__ void reconstruct(double theta, const double (&j)[D], const double (&P)[D],
+                                            const double (&Pab)[D == 3 ? 3 : 1], double R,
+                                            double (&f)[Lat<D>::Q]) {
+    constexpr int Q = Lat<D>::Q;
+    constexpr int NP = Lat<D>::NP;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const int k = nnz<D>(i);
+        if (k == 0) {
+            double sP = 0.0;
+#pragma unroll
+            for (int a = 0; a < D; ++a) sP += P[a];
+            f[i] = (theta - sP) + (NP == 0 ? 0.0 : (NP == 1 ? R : 3.0 * R));
+        } else if (k == 1) {
+            const int a = first_axis<D>(i);
+            const int s = Lat<D>::E[i][a];
+            const double h = 0.5 * (s == 1 ? P[a] + j[a] : P[a] - j[a]);
+            f[i] = (D == 1) ? h : (D == 2 ? h - 0.5 * R : h - R);
+        } else {
+            const int a = first_axis<D>(i);
+            const int b = second_axis<D>(i);
+            const int s = Lat<D>::E[i][a] * Lat<D>::E[i][b];
+            const double pab = Pab[pair_index(a, b)];
+            f[i] = 0.25 * (s == 1 ? R + pab : R - pab);
+        }
+    }
+}
+
+// In-place collision f <- C f (Sec. III.A evolution equation, Theorem 2 rates).
+template <int D>
+__device__ __forceinline__ void collide(double (&f)[Lat<D>::Q], const Rates& r) {
+    Moments<D> m;
+    moments<D>(f, m);
+    const double th3 = m.theta * (1.0 / 3.0);
+    double j[D], P[D], Pab[D == 3 ? 3 : 1];
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        j[a] = r.one_m_s1 * m.j[a];
+        P[a] = m.P[a] - r.s21 * (m.P[a] - th3);
+    }
+#pragma unroll
+    for (int p = 0; p < (D == 3 ? 3 : 1); ++p) Pab[p] = r.one_m_s22 * m.Pab[p];
+    reconstruct<D>(m.theta, j, P, Pab, r.R4wd * m.theta, f);
+}
+
+// df = (dC/deps) f at fixed f.
+template <int D>
+__device__ __forceinline__ void collide_deps(const double (&f)[Lat<D>::Q], const Rates& r,
+                                             double (&df)[Lat<D>::Q]) {
+    Moments<D> m;
+    moments<D>(f, m);
+    const double th3 = m.theta * (1.0 / 3.0);
+    double j[D], P[D], Pab[D == 3 ? 3 : 1];
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        j[a] = -r.ds1 * m.j[a];
+        P[a] = -r.ds21 * (m.P[a] - th3);
+    }
+#pragma unroll
+    for (int p = 0; p < (D == 3 ? 3 : 1); ++p) Pab[p] = -r.ds22 * m.Pab[p];
+    reconstruct<D>(0.0, j, P, Pab, 4.0 * r.dwd * m.theta, df);
+}
+
+// lam = C^T mu.  With C = M^-1 C_m M and C_m = I - S + S (M w) e_0^T,
+// C^T mu = M^T C_m^T nu with the dual moments nu = M^-T mu:
+//   nu_0   = mu_rest
+//   nu_a   = (mu_{+a} - mu_{-a})/2
+//   nu_aa  = -mu_rest + (mu_{+a} + mu_{-a})/2
+//   nu_ab  = sum_{edges in plane ab} e_a e_b mu / 4
+//   nu_aabb= mu_rest - (mu_{+a} + mu_{-a} + mu_{+b} + mu_{-b})/2 + sum_{edges ab} mu / 4
+// C_m^T nu keeps (1-s1) nu_a, (1-s21) nu_aa, (1-s22) nu_ab, zeroes the
+// rate-1 rows and collects nu_0 + (s21/3) sum nu_aa + 4 w_d sum nu_aabb in
+// row 0; M^T maps back to populations.
+template <int D>
+__device__ __forceinline__ void collide_adjoint(const double (&mu)[Lat<D>::Q], const Rates& r,
+                                                double (&lam)[Lat<D>::Q]) {
+    constexpr int Q = Lat<D>::Q;
+    double na[D], naa[D], nab[D == 3 ? 3 : 1], naabb[D == 3 ? 3 : 1];
+    const double rest = mu[0];
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        double dp = 0.0, sp = 0.0;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            if (nnz<D>(i) == 1 && first_axis<D>(i) == a) {
+                dp = LBM_SADD(dp, Lat<D>::E[i][a], mu[i]);
+                sp += mu[i];
+            }
+        }
+        na[a] = 0.5 * dp;
+        naa[a] = 0.5 * sp - rest;
+    }
+    if constexpr (D > 1) {
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+#pragma unroll
+            for (int b = a + 1; b < D; ++b) {
+                double se = 0.0, ss = 0.0;
+#pragma unroll
+                for (int i = 0; i < Q; ++i) {
+                    if (nnz<D>(i) == 2 && Lat<D>::E[i][a] != 0 && Lat<D>::E[i][b] != 0) {
+                        ss = LBM_SADD(ss, Lat<D>::E[i][a] * Lat<D>::E[i][b], mu[i]);
+                        se += mu[i];
+                    }
+                }
+                const int p = pair_index(a, b);
+                nab[p] = 0.25 * ss;
+                // mu_{+a} + mu_{-a} = 2 (naa + rest)
+                naabb[p] = rest - (naa[a] + rest) - (naa[b] + rest) + 0.25 * se;
+            }
+        }
+    }
+    double n0 = rest;
+    double snaa = 0.0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) snaa += naa[a];
+    n0 += r.s21 * (1.0 / 3.0) * snaa;
+    if constexpr (D > 1) {
+        double sb = 0.0;
+#pragma unroll
+        for (int p = 0; p < Lat<D>::NP; ++p) sb += naabb[p];
+        n0 += r.R4wd * sb;
+    }
+    double ta[D], taa[D], tab[D == 3 ? 3 : 1];
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        ta[a] = r.one_m_s1 * na[a];
+        taa[a] = r.one_m_s21 * naa[a];
+    }
+    if constexpr (D > 1) {
+#pragma unroll
+        for (int p = 0; p < Lat<D>::NP; ++p) tab[p] = r.one_m_s22 * nab[p];
+    }
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const int k = nnz<D>(i);
+        if (k == 0) {
+            lam[i] = n0;
+        } else if (k == 1) {
+            const int a = first_axis<D>(i);
+            const double t = Lat<D>::E[i][a] == 1 ? ta[a] : -ta[a];
+            lam[i] = n0 + t + taa[a];
+        } else {
+            const int a = first_axis<D>(i);
+            const int b = second_axis<D>(i);
+            const double t1 = Lat<D>::E[i][a] == 1 ? ta[a] : -ta[a];
+            const double t2 = Lat<D>::E[i][b] == 1 ? ta[b] : -ta[b];
+            const double tp = (Lat<D>::E[i][a] * Lat<D>::E[i][b] == 1) ? tab[pair_index(a, b)]
+                                                                       : -tab[pair_index(a, b)];
+            lam[i] = n0 + t1 + t2 + taa[a] + taa[b] + tp;
+        }
+    }
+}
+
+// Weight of population i.
+template <int D>
+__device__ __forceinline__ double weight(int i, const Rates& r) {
+    const int k = nnz<D>(i);
+    return k == 0 ? r.w0 : (k == 1 ? r.w1 : r.wd);
+}
+template <int D>
+__device__ __forceinline__ double dweight(int i, const Rates& r) {
+    const int k = nnz<D>(i);
+    return k == 0 ? r.dw0 : (k == 1 ? r.dw1 : r.dwd);
+}
+
+}  // namespace lbm

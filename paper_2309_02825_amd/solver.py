@@ -1,0 +1,288 @@
+"""Thin object layer over the C ABI: device buffers (torch), streams, the
+sqrt(T) checkpoint schedule of the adjoint and the batched form.
+
+No arithmetic of the method happens here: every step runs in the HIP
+library.  Tensors follow the conventions of include/lbm.h with the grid
+given x_0-first, ``grid = (n_0, ..., n_{d-1})``; a scalar field is a tensor
+of shape ``(n_{d-1}, ..., n_0)`` and a vector field ``(d, n_{d-1}, ..., n_0)``.
+"""
+from __future__ import annotations
+
+import math
+from typing import List, Optional, Sequence
+
+import torch
+
+from . import lbm as L
+
+F64 = torch.float64
+
+
+def _stream_handle(stream: Optional[torch.cuda.Stream]) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+def _field(x: torch.Tensor, shape, device, name: str) -> torch.Tensor:
+    if not isinstance(x, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if x.dtype != F64 or x.device != device or tuple(x.shape) != tuple(shape):
+        raise ValueError(f"{name}: expected float64 {tuple(shape)} on {device}, got "
+                         f"{x.dtype} {tuple(x.shape)} on {x.device}")
+    return x.contiguous()
+
+
+class Solver:
+    """One periodic problem (Sec. III.A scheme) on one GPU."""
+
+    def __init__(self, grid: Sequence[int], dx: float, dt: float, nu: float,
+                 device: Optional[torch.device] = None,
+                 stream: Optional[torch.cuda.Stream] = None):
+        self.grid = tuple(int(v) for v in grid)
+        self.d = len(self.grid)
+        self.dx, self.dt, self.nu = float(dx), float(dt), float(nu)
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.cfg = L.make_config(self.grid, dx, dt, nu)
+        self.q = L.lb_num_populations(self.d)
+        self.V = math.prod(self.grid)
+        self.shape = tuple(reversed(self.grid))
+        nbytes = L.lb_state_bytes(self.cfg)
+        if nbytes == 0:
+            raise L.LBError(L.LB_ERR_INVALID_ARG, L.lb_last_error())
+        self.stride = L.lb_state_stride(self.cfg)
+        self.state_elems = nbytes // 8
+        self.bufs = [torch.empty(self.state_elems, dtype=F64, device=self.device) for _ in range(2)]
+        self._stream = stream
+        with torch.cuda.device(self.device):
+            self.h = L.lb_create(self.cfg, _stream_handle(stream), self.bufs[0], self.bufs[1])
+        self.params = L.lb_parameters(self.cfg)
+
+    # -- lifetime ---------------------------------------------------------
+    def close(self):
+        if getattr(self, "h", None):
+            L.lb_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- forward ----------------------------------------------------------
+    def new_state(self) -> torch.Tensor:
+        return torch.empty(self.state_elems, dtype=F64, device=self.device)
+
+    def init(self, theta0: torch.Tensor, grad: Optional[torch.Tensor] = None,
+             check: bool = False):
+        theta0 = _field(theta0, self.shape, self.device, "theta0")
+        if grad is not None:
+            grad = _field(grad, (self.d,) + self.shape, self.device, "grad")
+        self._theta0, self._grad = theta0, grad  # keep alive until the kernel ran
+        L.lb_init(self.h, theta0, grad, check)
+
+    def step(self, nsteps: int):
+        L.lb_step(self.h, nsteps)
+
+    def step_buffers(self, src: torch.Tensor, dst: torch.Tensor):
+        L.lb_step_buffers(self.h, src, dst)
+
+    @property
+    def steps(self) -> int:
+        return L.lb_steps_taken(self.h)
+
+    def current(self) -> torch.Tensor:
+        ptr = L.lb_current_state(self.h)
+        return self.bufs[0] if ptr == self.bufs[0].data_ptr() else self.bufs[1]
+
+    def macro(self, state: Optional[torch.Tensor] = None):
+        theta = torch.empty(self.shape, dtype=F64, device=self.device)
+        u = torch.empty((self.d,) + self.shape, dtype=F64, device=self.device)
+        if state is None:
+            L.lb_macro(self.h, theta, u)
+        else:
+            L.lb_macro_buffer(self.h, state, theta, u)
+        return theta, u
+
+    def get_state(self) -> torch.Tensor:
+        out = torch.empty((self.q,) + self.shape, dtype=F64, device=self.device)
+        L.lb_get_state(self.h, out)
+        return out
+
+    def set_state(self, f: torch.Tensor, step: int = 0):
+        f = _field(f, (self.q,) + self.shape, self.device, "f")
+        self._set_src = f
+        L.lb_set_state(self.h, f, step)
+
+    # -- adjoint ----------------------------------------------------------
+    def macro_adjoint(self, state, g_theta, g_u, g_eps):
+        lam = self.new_state()
+        L.lb_macro_adjoint(self.h, state, g_theta, g_u, lam, g_eps)
+        return lam
+
+    def adjoint_step(self, state_n, lam_in, lam_out, g_eps):
+        L.lb_adjoint_step(self.h, state_n, lam_in, lam_out, g_eps)
+
+    def init_adjoint(self, theta0, grad, lam0, g_eps, want_grad: bool = False):
+        g_theta0 = torch.empty(self.shape, dtype=F64, device=self.device)
+        g_grad = (torch.empty((self.d,) + self.shape, dtype=F64, device=self.device)
+                  if (grad is not None and want_grad) else None)
+        L.lb_init_adjoint(self.h, theta0, grad, lam0, g_theta0, g_grad, g_eps)
+        return g_theta0, g_grad
+
+
+def run(grid, dx, dt, nu, theta0, grad, nsteps, device=None):
+    """Initialise, advance nsteps and return (theta, u) on the GPU."""
+    s = Solver(grid, dx, dt, nu, device=device)
+    s.init(theta0, grad)
+    s.step(nsteps)
+    out = s.macro()
+    torch.cuda.current_stream().synchronize()
+    s.close()
+    return out
+
+
+# ---------------------------------------------------------------------------
+# differentiation: torch.autograd.Function with sqrt(T) checkpoints
+# ---------------------------------------------------------------------------
+
+def checkpoint_segments(nsteps: int, nseg: Optional[int] = None) -> List[int]:
+    """Segment start steps for sqrt(T) checkpointing (about sqrt(nsteps) segments)."""
+    if nsteps <= 0:
+        return [0]
+    if nseg is None:
+        nseg = max(1, int(math.ceil(math.sqrt(nsteps))))
+    seg = int(math.ceil(nsteps / nseg))
+    return list(range(0, nsteps, seg))
+
+
+class VelocityFunction(torch.autograd.Function):
+    """u(T) from theta0 and nu: the initial gradient is the fourth-order
+    central difference of theta0, the forward keeps about sqrt(T) state
+    checkpoints and the backward recomputes each segment before running the
+    adjoint kernels over it in reverse.  Gradients: dL/dtheta0 and dL/dnu."""
+
+    @staticmethod
+    def forward(ctx, theta0, nu, grid, dx, dt, nsteps, nseg):
+        nu_f = float(nu.item())
+        s = Solver(grid, dx, dt, nu_f, device=theta0.device)
+        theta0 = theta0.detach().contiguous()
+        s.init(theta0, None)
+        starts = checkpoint_segments(nsteps, nseg)
+        ckpts = []
+        cur = s.bufs[0]
+        other = s.bufs[1]
+        for k, st in enumerate(starts):
+            ckpts.append(cur.clone())
+            end = starts[k + 1] if k + 1 < len(starts) else nsteps
+            for _ in range(st, end):
+                s.step_buffers(cur, other)
+                cur, other = other, cur
+        final = cur
+        _, u = s.macro(final)
+        ctx.solver = s
+        ctx.starts = starts
+        ctx.nsteps = nsteps
+        ctx.ckpts = ckpts
+        ctx.final = final
+        ctx.dt, ctx.dx = dt, dx
+        ctx.save_for_backward(theta0)
+        return u
+
+    @staticmethod
+    def backward(ctx, g_u):
+        (theta0,) = ctx.saved_tensors
+        s: Solver = ctx.solver
+        g_u = g_u.contiguous()
+        g_eps = torch.zeros(1, dtype=F64, device=theta0.device)
+        lam = s.macro_adjoint(ctx.final, None, g_u, g_eps)
+        lam_other = s.new_state()
+        starts, N = ctx.starts, ctx.nsteps
+        for k in range(len(starts) - 1, -1, -1):
+            st = starts[k]
+            end = starts[k + 1] if k + 1 < len(starts) else N
+            states = [ctx.ckpts[k]]
+            for _ in range(st + 1, end):
+                nxt = s.new_state()
+                s.step_buffers(states[-1], nxt)
+                states.append(nxt)
+            for n in range(end - 1, st - 1, -1):
+                s.adjoint_step(states[n - st], lam, lam_other, g_eps)
+                lam, lam_other = lam_other, lam
+            del states
+        g_theta0, _ = s.init_adjoint(theta0, None, lam, g_eps)
+        g_nu = g_eps.reshape(()) * (ctx.dt / (ctx.dx * ctx.dx))
+        s.close()
+        ctx.solver = None
+        ctx.ckpts = None
+        return g_theta0, g_nu, None, None, None, None, None
+
+
+def velocity(theta0: torch.Tensor, nu: torch.Tensor, grid, dx: float, dt: float, nsteps: int,
+             nseg: Optional[int] = None) -> torch.Tensor:
+    """Differentiable u(T) (shape (d, *reversed(grid))) for a periodic problem."""
+    return VelocityFunction.apply(theta0, nu, tuple(grid), float(dx), float(dt), int(nsteps), nseg)
+
+
+# ---------------------------------------------------------------------------
+# batched form
+# ---------------------------------------------------------------------------
+
+class BatchSolver:
+    """Independent 2-D periodic instances of different sizes and viscosities
+    advanced together by one tile-table kernel per step (hipGraph-captured)."""
+
+    def __init__(self, problems: Sequence, device: Optional[torch.device] = None,
+                 stream: Optional[torch.cuda.Stream] = None):
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.cfgs = [L.make_config(p.grid, p.dx, p.dt, p.nu) for p in problems]
+        self.grids = [tuple(p.grid) for p in problems]
+        total, self.offsets, self.strides = L.lb_batch_layout(self.cfgs)
+        self.nodes = [g[0] * g[1] for g in self.grids]
+        self.node_offsets = [0]
+        for n in self.nodes[:-1]:
+            self.node_offsets.append(self.node_offsets[-1] + n)
+        self.total_nodes = sum(self.nodes)
+        self.pools = [torch.empty(total, dtype=F64, device=self.device) for _ in range(2)]
+        with torch.cuda.device(self.device):
+            self.h = L.lb_batch_create(self.cfgs, _stream_handle(stream), self.pools[0],
+                                       self.pools[1])
+
+    def close(self):
+        if getattr(self, "h", None):
+            L.lb_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def pack(self, fields: Sequence[torch.Tensor]) -> torch.Tensor:
+        return torch.cat([f.reshape(-1) for f in fields]).to(self.device, F64).contiguous()
+
+    def init(self, theta0s: Sequence[torch.Tensor], grads: Optional[Sequence[torch.Tensor]] = None):
+        self._th = self.pack(theta0s)
+        self._gr = self.pack(grads) if grads is not None else None
+        L.lb_batch_init(self.h, self._th, self._gr)
+
+    def set_tile(self, tx: int, ty: int):
+        L.lb_batch_set_tile(self.h, tx, ty)
+
+    def autotune(self, steps_per_trial: int = 3):
+        return L.lb_batch_autotune(self.h, steps_per_trial)
+
+    def step(self, nsteps: int, graph: bool = True):
+        L.lb_batch_step(self.h, nsteps, graph)
+
+    def macro(self):
+        theta = torch.empty(self.total_nodes, dtype=F64, device=self.device)
+        u = torch.empty(2 * self.total_nodes, dtype=F64, device=self.device)
+        L.lb_batch_macro(self.h, theta, u)
+        ths, us = [], []
+        for b, (nx, ny) in enumerate(self.grids):
+            o, n = self.node_offsets[b], self.nodes[b]
+            ths.append(theta[o:o + n].view(ny, nx))
+            us.append(u[2 * o:2 * o + 2 * n].view(2, ny, nx))
+        return ths, us

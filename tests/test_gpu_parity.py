@@ -1,0 +1,397 @@
+"""Parity of the HIP path with the CPU oracle (MI355X only).
+
+Every case prints its name before it touches the GPU.  Tolerances (the
+fourth-order scheme in IEEE double on both sides, different summation
+order): max relative error (norm-wise, |a-b|_inf / |b|_inf per field)
+<= 1e-13 on theta and on the distribution, <= 1e-11 on each velocity
+component.
+"""
+import math
+import zlib
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import oracle as O  # noqa: E402
+from oracle import spectral as S  # noqa: E402
+from paper_2309_02825_amd import workloads as W  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+TOL_THETA = 1e-13
+TOL_U = 1e-11
+TOL_F = 1e-13
+
+
+def _dev():
+    return torch.device("cuda", 0)
+
+
+def _say(*a):
+    print("[gpu-case]", *a, flush=True)
+
+
+def _solver_mod():
+    from paper_2309_02825_amd import solver as SV
+    return SV
+
+
+def max_rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+def _gpu_run(grid, dx, dt, nu, theta0, grad, nsteps, want_f=True):
+    SV = _solver_mod()
+    s = SV.Solver(grid, dx, dt, nu, device=_dev())
+    th0 = torch.from_numpy(np.ascontiguousarray(theta0)).to(_dev())
+    gr = None if grad is None else torch.from_numpy(np.ascontiguousarray(grad)).to(_dev())
+    s.init(th0, gr)
+    s.step(nsteps)
+    th, u = s.macro()
+    f = s.get_state() if want_f else None
+    torch.cuda.synchronize()
+    out = (th.cpu().numpy(), u.cpu().numpy(), None if f is None else f.cpu().numpy())
+    s.close()
+    return out
+
+
+CASES = [
+    # name, grid (x-first), nsteps, field kind
+    ("1d_heat_n64", (64,), 256, "heat"),
+    ("1d_ragged_300_random", (300,), 97, "random"),
+    ("1d_n1", (1,), 5, "random"),
+    ("1d_n2", (2,), 7, "random"),
+    ("2d_ragged_100x70_cos", (100, 70), 40, "cos"),
+    ("2d_ragged_130x67_random", (130, 67), 33, "random"),
+    ("2d_degenerate_1x5", (1, 5), 9, "random"),
+    ("2d_degenerate_7x1", (7, 1), 9, "random"),
+    ("2d_ex2_level0", (40, 40), 100, "ex2"),
+    ("3d_ragged_20x17x9", (20, 17, 9), 25, "random"),
+    ("3d_ex3_level0", (20, 20, 20), 50, "ex3"),
+    ("3d_cos_33x5x4", (33, 5, 4), 12, "cos"),
+]
+
+
+def _problem(grid, kind):
+    d = len(grid)
+    rng = np.random.default_rng(zlib.crc32(repr((grid, kind)).encode()))
+    if kind == "heat":
+        wl = W.heat_1d(grid[0])
+        th0, g0 = W.evaluate(wl.modes, wl.grid, wl.dx)
+        return wl.dx, wl.dt, wl.nu, th0, g0
+    if kind == "ex2":
+        wl = W.paper_example2(0, 0.3)
+        th0, g0 = W.evaluate(wl.modes, wl.grid, wl.dx)
+        return wl.dx, wl.dt, wl.nu, th0, g0
+    if kind == "ex3":
+        wl = W.paper_example3(0, 0.15)
+        th0, g0 = W.evaluate(wl.modes, wl.grid, wl.dx)
+        return wl.dx, wl.dt, wl.nu, th0, g0
+    dx = 1.0 / max(grid)
+    nu = 0.01
+    eps = {1: 0.4, 2: 0.23, 3: 0.11}[d]
+    dt = eps * dx * dx / nu
+    if kind == "cos":
+        modes = W.constant(2.0, d) + W.trig_product(["cos"] * d, [1] * d)
+        th0, g0 = W.evaluate(modes, grid, dx)
+        return dx, dt, nu, th0, g0
+    th0 = W.random_smooth_field(rng, tuple(reversed(grid)))
+    return dx, dt, nu, th0, None
+
+
+@pytest.mark.parametrize("name,grid,nsteps,kind", CASES, ids=[c[0] for c in CASES])
+def test_parity_with_direct_oracle(name, grid, nsteps, kind):
+    _say(name, grid, nsteps, kind)
+    dx, dt, nu, th0, g0 = _problem(grid, kind)
+    grad_o = g0 if g0 is not None else O.grad_fd4(th0, dx)
+    f_o = O.run(O.init(th0, grad_o, dx, dt, nu), dx, dt, nu, nsteps)
+    th_o, u_o = O.macro(f_o, dx, dt, nu)
+    th_g, u_g, f_g = _gpu_run(grid, dx, dt, nu, th0, g0, nsteps)
+    assert max_rel(f_g, f_o) <= TOL_F, name
+    assert max_rel(th_g, th_o) <= TOL_THETA, name
+    for a in range(len(grid)):
+        if np.max(np.abs(u_o[a])) > 0:
+            assert max_rel(u_g[a], u_o[a]) <= TOL_U, (name, a)
+
+
+def test_zero_steps_returns_initial_state():
+    _say("zero_steps")
+    grid = (37, 23)
+    dx, dt, nu, th0, g0 = _problem(grid, "cos")
+    f_o = O.init(th0, g0, dx, dt, nu)
+    _, _, f_g = _gpu_run(grid, dx, dt, nu, th0, g0, 0)
+    assert max_rel(f_g, f_o) <= 1e-15
+
+
+def test_fd_gradient_initialisation_matches_oracle():
+    _say("fd_gradient_init")
+    grid = (45, 31, 6)
+    dx, dt, nu, th0, _ = _problem(grid, "random")
+    f_o = O.init(th0, O.grad_fd4(th0, dx), dx, dt, nu)
+    _, _, f_g = _gpu_run(grid, dx, dt, nu, th0, None, 0)
+    assert max_rel(f_g, f_o) <= 1e-14
+
+
+def test_set_state_roundtrip_and_step_buffers():
+    _say("state_roundtrip")
+    SV = _solver_mod()
+    grid = (70, 66)
+    dx, dt, nu, th0, g0 = _problem(grid, "random")
+    s = SV.Solver(grid, dx, dt, nu, device=_dev())
+    s.init(torch.from_numpy(th0).to(_dev()), None)
+    s.step(5)
+    f5 = s.get_state()
+    s.step(3)
+    f8 = s.get_state()
+    s.set_state(f5, 5)
+    assert s.steps == 5
+    s.step(3)
+    f8b = s.get_state()
+    # the same three steps through explicit buffers
+    s.set_state(f5, 5)
+    a, b = s.new_state(), s.new_state()
+    a.copy_(s.current())
+    s.step_buffers(a, b)
+    s.step_buffers(b, a)
+    s.step_buffers(a, b)
+    th_b, u_b = s.macro(b)
+    th_c, u_c = s.macro()
+    torch.cuda.synchronize()
+    assert torch.equal(f8, f8b)
+    s.set_state(f8, 8)
+    th8, u8 = s.macro()
+    assert torch.equal(th8, th_b) and torch.equal(u8, u_b)
+    del th_c, u_c
+    s.close()
+
+
+def test_run_to_run_bitwise_determinism():
+    _say("determinism")
+    grid = (257, 129)
+    dx, dt, nu, th0, _ = _problem(grid, "random")
+    r1 = _gpu_run(grid, dx, dt, nu, th0, None, 50)
+    r2 = _gpu_run(grid, dx, dt, nu, th0, None, 50)
+    for a, b in zip(r1, r2):
+        assert np.array_equal(a, b)
+
+
+def test_theta_check_rejects_nonpositive_and_nonfinite():
+    _say("theta_check")
+    SV = _solver_mod()
+    from paper_2309_02825_amd import lbm as L
+    grid = (32, 16)
+    s = SV.Solver(grid, 1 / 32, 0.2 / 32 ** 2 / 0.01, 0.01, device=_dev())
+    th = torch.full((16, 32), 1.0, dtype=torch.float64, device=_dev())
+    s.init(th, None, check=True)
+    for bad in (0.0, -1.0, float("nan"), float("inf")):
+        th2 = th.clone()
+        th2[3, 5] = bad
+        with pytest.raises(L.LBError) as ei:
+            s.init(th2, None, check=True)
+        assert ei.value.status == L.LB_ERR_NONFINITE
+    with pytest.raises(L.LBError) as ei:
+        SV.Solver((16, 16), 1 / 16, 1 / 256, 0.6 * 256 / 256, device=_dev())
+    assert ei.value.status == L.LB_ERR_UNSTABLE
+    s.close()
+
+
+def test_conservation_on_gpu():
+    _say("conservation 2d 10k steps")
+    grid = (96, 80)
+    dx, dt, nu, th0, _ = _problem(grid, "random")
+    SV = _solver_mod()
+    s = SV.Solver(grid, dx, dt, nu, device=_dev())
+    s.init(torch.from_numpy(th0).to(_dev()), None)
+    f0 = s.get_state().cpu().numpy()
+    s.step(10000)
+    f1 = s.get_state().cpu().numpy()
+    s.close()
+    a, b = math.fsum(f0.ravel()), math.fsum(f1.ravel())
+    assert abs(a - b) / a < 1e-13
+
+
+def test_fourth_order_convergence_on_gpu():
+    _say("convergence 1d sweep")
+    errs = []
+    for n in (16, 32, 64, 128):
+        wl = W.heat_1d(n)
+        th0, g0 = W.evaluate(wl.modes, wl.grid, wl.dx)
+        th, u, _ = _gpu_run(wl.grid, wl.dx, wl.dt, wl.nu, th0, g0, wl.nsteps, want_f=False)
+        te, ue = W.exact(wl, wl.nsteps * wl.dt)
+        errs.append((np.sqrt(np.mean((th - te) ** 2)), np.sqrt(np.mean((u - ue) ** 2))))
+    for v in range(2):
+        crs = [math.log2(errs[i][v] / errs[i + 1][v]) for i in range(3)]
+        assert all(3.85 < c < 4.15 for c in crs), crs
+
+
+# ---------------------------------------------------------------------------
+# full-size workloads against the exact Fourier-mode evaluation (sampled)
+# ---------------------------------------------------------------------------
+
+def _sample_points(grid, count, seed):
+    rng = np.random.default_rng(seed)
+    pts = np.stack([rng.integers(0, n, size=count) for n in grid], axis=1)
+    corners = np.array([[0] * len(grid), [n - 1 for n in grid]])
+    return np.concatenate([pts, corners])
+
+
+def _full_size_case(wl, nsteps, count=20000):
+    SV = _solver_mod()
+    s = SV.Solver(wl.grid, wl.dx, wl.dt, wl.nu, device=_dev())
+    th0, g0 = W.evaluate(wl.modes, wl.grid, wl.dx, xp=torch, device=_dev())
+    s.init(th0, g0)
+    s.step(nsteps)
+    th, u = s.macro()
+    torch.cuda.synchronize()
+    pts = _sample_points(wl.grid, count, 99)
+    idx = tuple(torch.as_tensor(pts[:, a], device=_dev()) for a in reversed(range(wl.d)))
+    th_s = th[idx].cpu().numpy()
+    u_s = np.stack([u[a][idx].cpu().numpy() for a in range(wl.d)])
+    s.close()
+    del th0, g0
+    sol = S.ModeSolution(wl.grid, wl.dx, wl.dt, wl.nu, wl.modes, nsteps)
+    th_x, u_x = sol.macro(pts)
+    th_x = th_x.astype(np.float64)
+    u_x = u_x.astype(np.float64)
+    assert max_rel(th_s, th_x) <= TOL_THETA
+    for a in range(wl.d):
+        assert max_rel(u_s[a], u_x[a]) <= TOL_U, a
+
+
+@pytest.mark.parametrize("n", [1024, 4096])
+def test_full_size_2d(n):
+    _say("full-size 2d", n, "10000 steps")
+    _full_size_case(W.heat_2d(n), 10000)
+
+
+@pytest.mark.parametrize("n", [256, 512])
+def test_full_size_3d(n):
+    _say("full-size 3d", n, "2000 steps")
+    _full_size_case(W.heat_3d(n), 2000)
+
+
+# ---------------------------------------------------------------------------
+# adjoint
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n,steps,nseg", [(32, 8, None), (16, 60, None), (16, 60, 1),
+                                          (24, 37, 5)])
+def test_adjoint_matches_oracle(n, steps, nseg):
+    _say("adjoint", n, steps, nseg)
+    SV = _solver_mod()
+    tgt, gue = W.adjoint_problem(n=n, nsteps=steps)
+    th_t, _ = W.evaluate(tgt.modes, tgt.grid, tgt.dx, with_grad=False)
+    th0, _ = W.evaluate(gue.modes, gue.grid, gue.dx, with_grad=False)
+    dx, dt, nu = gue.dx, gue.dt, gue.nu
+    _, u_t, _ = O.solve(th_t, O.grad_fd4(th_t, dx), dx, dt, nu, steps)
+    L_o, g_o, gnu_o = O.velocity_loss_and_grad(th0, u_t, dx, dt, nu, steps)
+
+    th0_t = torch.from_numpy(th0).to(_dev()).requires_grad_(True)
+    nu_t = torch.tensor(nu, dtype=torch.float64, device=_dev(), requires_grad=True)
+    u = SV.velocity(th0_t, nu_t, gue.grid, dx, dt, steps, nseg)
+    loss = ((u - torch.from_numpy(u_t).to(_dev())) ** 2).sum()
+    loss.backward()
+    torch.cuda.synchronize()
+    assert abs(loss.item() - L_o) <= 1e-12 * L_o
+    assert max_rel(th0_t.grad.cpu().numpy(), g_o) <= 1e-12
+    assert abs(nu_t.grad.item() - gnu_o) <= 1e-11 * abs(gnu_o)
+
+
+def test_adjoint_dot_product_on_gpu():
+    """<lambda, F^k v> = <F^{kT} lambda, v> for the linear step map on the GPU."""
+    _say("adjoint dot product")
+    SV = _solver_mod()
+    grid = (40, 28)
+    dx, nu = 1 / 40, 0.02
+    dt = 0.17 * dx * dx / nu
+    s = SV.Solver(grid, dx, dt, nu, device=_dev())
+    q = 9
+    g = torch.Generator(device="cpu").manual_seed(3)
+    v = torch.randn((q, 28, 40), generator=g, dtype=torch.float64).to(_dev())
+    lam = torch.randn((q, 28, 40), generator=g, dtype=torch.float64).to(_dev())
+    s.set_state(v, 0)
+    st = [s.current().clone()]
+    k = 6
+    for _ in range(k):
+        nxt = s.new_state()
+        s.step_buffers(st[-1], nxt)
+        st.append(nxt)
+    # lambda in the canonical layout with the solver's plane stride
+    lam_c = torch.zeros(s.state_elems, dtype=torch.float64, device=_dev())
+    lam_c.view(-1)[: q * s.stride].view(q, s.stride)[:, : 40 * 28] = lam.reshape(q, -1)
+    g_eps = torch.zeros(1, dtype=torch.float64, device=_dev())
+    cur, other = lam_c, s.new_state()
+    for n in range(k - 1, -1, -1):
+        s.adjoint_step(st[n], cur, other, g_eps)
+        cur, other = other, cur
+    # F^k v in canonical layout
+    s.set_state(v, 0)
+    s.step(k)
+    fk = s.get_state()
+    lhs = float((lam * fk).sum().item())
+    rhs = float((cur.view(q, s.stride)[:, : 40 * 28].reshape(q, 28, 40) * v).sum().item())
+    torch.cuda.synchronize()
+    s.close()
+    assert abs(lhs - rhs) <= 1e-12 * float((lam * fk).abs().sum().item())
+
+
+# ---------------------------------------------------------------------------
+# batched form
+# ---------------------------------------------------------------------------
+
+def test_batch_matches_single_instance_runs():
+    _say("batch vs single (small ragged batch)")
+    SV = _solver_mod()
+    insts = W.batch_instances(count=6, seed=5, lmin=17, lmax=150, nsteps=40)
+    bs = SV.BatchSolver(insts, device=_dev())
+    th0s = [torch.from_numpy(W.evaluate(p.modes, p.grid, p.dx)[0]) for p in insts]
+    grs = [torch.from_numpy(W.evaluate(p.modes, p.grid, p.dx)[1]) for p in insts]
+    bs.init(th0s, grs)
+    for tx, ty in ((64, 4), (256, 1), (16, 16)):
+        bs.set_tile(tx, ty)
+        bs.step(10, graph=(tx != 256))
+    ths, us = bs.macro()
+    torch.cuda.synchronize()
+    for b, p in enumerate(insts):
+        th, u, _ = _gpu_run(p.grid, p.dx, p.dt, p.nu, th0s[b].numpy(), grs[b].numpy(), 30,
+                            want_f=False)
+        assert np.array_equal(ths[b].cpu().numpy(), th), b
+        assert np.array_equal(us[b].cpu().numpy(), u), b
+    bs.close()
+
+
+def test_batch_full_size_against_exact_modes():
+    """The 512-instance ragged batch (L ~ U{64..1024}, nu log-uniform), 1000
+    steps in one graph launch, autotuned tiles; sampled instances against
+    the exact Fourier-mode evaluation."""
+    _say("batch full size 512 x 1000 steps")
+    SV = _solver_mod()
+    insts = W.batch_instances()
+    bs = SV.BatchSolver(insts, device=_dev())
+    th0s, grs = [], []
+    for p in insts:
+        t, g = W.evaluate(p.modes, p.grid, p.dx, xp=torch, device=_dev())
+        th0s.append(t)
+        grs.append(g)
+    bs.init(th0s, grs)
+    del th0s, grs
+    bs.autotune(2)
+    bs.step(1000, graph=True)
+    ths, us = bs.macro()
+    torch.cuda.synchronize()
+    for b in (0, 1, 77, 255, 511):
+        p = insts[b]
+        pts = _sample_points(p.grid, 3000, b)
+        idx = (torch.as_tensor(pts[:, 1], device=_dev()), torch.as_tensor(pts[:, 0], device=_dev()))
+        th_s = ths[b][idx].cpu().numpy()
+        u_s = np.stack([us[b][a][idx].cpu().numpy() for a in range(2)])
+        sol = S.ModeSolution(p.grid, p.dx, p.dt, p.nu, p.modes, 1000)
+        th_x, u_x = sol.macro(pts)
+        assert max_rel(th_s, th_x.astype(np.float64)) <= TOL_THETA, b
+        for a in range(2):
+            assert max_rel(u_s[a], u_x[a].astype(np.float64)) <= TOL_U, (b, a)
+    bs.close()
