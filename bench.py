@@ -244,6 +244,8 @@ def main():
                     help="override the LB time steps per solve (profiling runs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="first run a plain 1 GiB device copy (reference for HBM counters)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -258,6 +260,15 @@ def main():
 
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+    if args.copy_probe:
+        # a plain copy of exactly 1 GiB: its FETCH_SIZE / WRITE_SIZE counters
+        # calibrate the HBM byte counts of the solver kernels
+        a = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     wl = workload(args.workload)
     if args.lb_steps > 0:
         wl.nsteps = args.lb_steps
