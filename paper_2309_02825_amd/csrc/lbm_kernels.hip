@@ -2,8 +2,8 @@
 //
 // Data layout: a state buffer holds q planes of `stride` doubles (structure
 // of arrays, x fastest).  It is kept "stream-shifted": element k of plane i
-// is the post-collision population that arrives at node k + e_i at the next
-// step, so one time step is a pull:
+// is f_i(k + e_i), the population that node k sent along e_i after its last
+// collision, so one time step is a pull:
 //     f_i(x) = src_i(x - e_i)          (pre-collision distribution at x)
 //     dst_i(x) = (C f(x))_i            (collision, Sec. III.A)
 // Every store is aligned and coalesced; the loads of a wavefront are 64
@@ -71,16 +71,36 @@ __device__ __forceinline__ int push_index(const Nbr& nb, int i) {
     return nb.sz[1 - Lat<D>::E[i][2]] + nb.sy[1 - Lat<D>::E[i][1]] + nb.sx[1 - Lat<D>::E[i][0]];
 }
 
+__device__ __forceinline__ int64_t block_linear() {
+    return (int64_t)blockIdx.x + (int64_t)gridDim.x * ((int64_t)blockIdx.y + (int64_t)gridDim.y * blockIdx.z);
+}
+
+// Workgroups are dispatched round-robin over the 8 XCDs of the chip (linear
+// block b runs on XCD b mod 8), each with its own L2.  Neighbouring tiles
+// along x share the cache lines of the x +- 1 halo, so every XCD is given one
+// contiguous range of tiles (x fastest) instead of every eighth tile.
+constexpr unsigned NXCD = 8;
+__device__ __forceinline__ unsigned xcd_remap(unsigned b, unsigned nb) {
+    const unsigned q = nb / NXCD, r = nb % NXCD;
+    const unsigned c = b % NXCD, slot = b / NXCD;
+    return c * q + (c < r ? c : r) + slot;
+}
+
 template <int D>
 __device__ __forceinline__ bool thread_node(const Geo& g, int& x, int& y, int& z) {
+    const unsigned nb = gridDim.x * gridDim.y * gridDim.z;
+    const unsigned b = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+    const unsigned t = xcd_remap(b, nb);
+    const unsigned tx = t % gridDim.x;
+    const unsigned rest = t / gridDim.x;
     if constexpr (D == 1) {
-        x = blockIdx.x * B1 + threadIdx.x;
+        x = (int)(tx * B1 + threadIdx.x);
         y = 0;
         z = 0;
     } else {
-        x = blockIdx.x * BX + threadIdx.x;
-        y = blockIdx.y * BY + threadIdx.y;
-        z = (D == 3) ? (int)blockIdx.z : 0;
+        x = (int)(tx * BX + threadIdx.x);
+        y = (int)((rest % gridDim.y) * BY + threadIdx.y);
+        z = (D == 3) ? (int)(rest / gridDim.y) : 0;
     }
     return x < g.nx && y < g.ny;
 }
@@ -98,10 +118,6 @@ __device__ __forceinline__ double block_sum(double v) {
     if ((tid & 63) == 0) sh[tid >> 6] = v;
     __syncthreads();
     return tid == 0 ? (sh[0] + sh[1]) + (sh[2] + sh[3]) : 0.0;
-}
-
-__device__ __forceinline__ int64_t block_linear() {
-    return (int64_t)blockIdx.x + (int64_t)gridDim.x * ((int64_t)blockIdx.y + (int64_t)gridDim.y * blockIdx.z);
 }
 
 // ---------------------------------------------------------------------------
@@ -428,7 +444,7 @@ __global__ void __launch_bounds__(256) k_batch_step(const BatchInst* __restrict_
                                                     int log2tx, const double* __restrict__ src,
                                                     double* __restrict__ dst) {
     constexpr int Q = 9;
-    const BatchTile t = tiles[blockIdx.x];
+    const BatchTile t = tiles[xcd_remap(blockIdx.x, gridDim.x)];
     const BatchInst& in = insts[t.inst];
     const int tid = threadIdx.x;
     const int x = t.x0 + (tid & (tx - 1));
