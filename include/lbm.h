@@ -26,15 +26,20 @@
  *     c = dx/dt, eps = nu*dt/dx^2.
  *   - Dense fields: theta is V doubles; a vector field (grad theta, u) is
  *     d planes of V doubles (component a = along x_a) back to back.
- *   - State buffers hold q population planes, plane i starting at element
- *     i*lb_state_stride(cfg); elements past V in a plane are padding.
- *     Storage layout ("stream-shifted"): element k of plane i holds
- *     f_i(k + e_i), the pre-collision population of node k + e_i at the
- *     current time (the value node k sent along e_i after its last
- *     collision), so the distribution at node x is f_i(x) = buf_i(x - e_i).
- *   - Distribution-shaped adjoint buffers (lambda) use the same plane stride
- *     but the canonical layout: element k of plane i is d L / d f_i(node k)
- *     for the pre-collision f.
+ *   - State buffers hold the q populations of every node in a chunked
+ *     structure-of-arrays order: node indices are grouped in chunks of
+ *     C = lb_state_chunk() = 4096 consecutive nodes, and inside a chunk the
+ *     q populations follow one another as runs of C doubles, so population i
+ *     of node k is element ((k / C) * q + i) * C + k % C.  V is rounded up to
+ *     whole chunks (lb_state_elements); slots of nodes >= V are never read.
+ *     Storage layout of a state ("stream-shifted"): the slot of population i
+ *     at node k holds f_i(k + e_i), the pre-collision population of node
+ *     k + e_i at the current time (the value node k sent along e_i after its
+ *     last collision), so the distribution at node x is f_i(x) = buf_i(x - e_i).
+ *   - Distribution-shaped adjoint buffers (lambda) use the same chunked order
+ *     with canonical node positions: the slot of population i at node k is
+ *     d L / d f_i(node k) for the pre-collision f.  lb_layout_from_dense and
+ *     lb_layout_to_dense convert such buffers to and from q x V arrays.
  *   - Velocity order (Sec. III.A): D1Q3 (0, +1, -1); D2Q9 (0,0) (1,0) (0,1)
  *     (-1,0) (0,-1) (1,1) (-1,1) (-1,-1) (1,-1); D3Q19 rest, +x, +y, +z, -x,
  *     -y, -z, then the xy, xz, yz edges each as (+,+) (-,+) (-,-) (+,-).
@@ -81,11 +86,14 @@ lb_status lb_parameters(const lb_config* cfg, double* out7);
 /* Number of populations q = 1 + 2 d^2 (3, 9, 19) for cfg->dim. */
 int32_t lb_num_populations(int32_t dim);
 
-/* Elements between consecutive population planes of a state buffer (V
- * rounded up, plus padding that staggers the planes across HBM channels). */
-int64_t lb_state_stride(const lb_config* cfg);
+/* Nodes per chunk of the state layout (4096). */
+int64_t lb_state_chunk(void);
 
-/* Bytes of one state buffer: q * lb_state_stride(cfg) * sizeof(double).
+/* Elements (doubles) of one state buffer: q * ceil(V / 4096) * 4096.
+ * Returns 0 for an invalid config. */
+int64_t lb_state_elements(const lb_config* cfg);
+
+/* Bytes of one state buffer: lb_state_elements(cfg) * sizeof(double).
  * Returns 0 for an invalid config. */
 size_t lb_state_bytes(const lb_config* cfg);
 
@@ -141,6 +149,12 @@ lb_status lb_get_state(lb_solver* s, double* f_out);
  * the step counter to step. */
 lb_status lb_set_state(lb_solver* s, const double* f_in, int64_t step);
 
+/* Copy a dense q x V array (dense[i*V + k] for population i of node k) into
+ * a buffer of lb_state_elements in the chunked order, without any stream
+ * shift, and back.  Used for distribution-shaped adjoint buffers. */
+lb_status lb_layout_from_dense(lb_solver* s, const double* dense, double* buf);
+lb_status lb_layout_to_dense(lb_solver* s, const double* buf, double* dense);
+
 /* ---------------------------------------------------------------------- */
 /* Discrete adjoint (reverse mode).  The forward map is f^{n+1} = P C f^n
  * with the per-node collision C = I - M^-1 S M (I - w 1^T) (Sec. III.A) and
@@ -151,7 +165,7 @@ lb_status lb_set_state(lb_solver* s, const double* f_in, int64_t step);
 
 /* Adjoint of lb_macro_buffer at the state buffer `state`: given g_theta
  * (V, may be NULL) and g_u (d x V, may be NULL) writes lambda = dL/df
- * (canonical, plane stride lb_state_stride) and adds the explicit eps
+ * (canonical node positions, chunked order) and adds the explicit eps
  * dependence of u (through s1) to *g_eps. */
 lb_status lb_macro_adjoint(lb_solver* s, const double* state, const double* g_theta,
                            const double* g_u, double* lambda, double* g_eps);
@@ -178,15 +192,15 @@ lb_status lb_destroy(lb_solver* s);
 
 /* ---------------------------------------------------------------------- */
 /* Batched form: many independent 2-D periodic instances of different sizes
- * and viscosities advanced together.  Instance b occupies q planes of
- * stride_b elements starting at element offset_b of the pool.               */
+ * and viscosities advanced together.  Instance b occupies elems_b elements
+ * (its own chunked state) starting at element offset_b of the pool.         */
 /* ---------------------------------------------------------------------- */
 
 /* Total pool elements (doubles) for count 2-D configs; offsets (count) and
- * strides (count) receive each instance's first element and plane stride.
+ * elems (count) receive each instance's first element and element count.
  * Either output may be NULL.  Returns -1 on an invalid config. */
 int64_t lb_batch_layout(const lb_config* cfgs, int32_t count, int64_t* offsets,
-                        int64_t* strides);
+                        int64_t* elems);
 
 /* Create a batch over two caller-owned pools of lb_batch_layout elements
  * each.  Only dim = 2 configs are accepted. */

@@ -100,7 +100,7 @@ lb_status validate(const lb_config* c) {
         V *= c->n[a];
         if (V > (int64_t)INT_MAX) return fail(LB_ERR_INVALID_ARG, "more than 2^31-1 nodes");
     }
-    if (c->dim >= 2 && (c->n[1] + 3) / 4 > 65535)
+    if (c->dim >= 2 && (c->n[1] + lbm::BLOCK_Y - 1) / lbm::BLOCK_Y > 65535)
         return fail(LB_ERR_INVALID_ARG, "n[1] exceeds the launch-grid limit");
     if (c->dim == 3 && c->n[2] > 65535)
         return fail(LB_ERR_INVALID_ARG, "n[2] exceeds the launch-grid limit");
@@ -116,21 +116,19 @@ lb_status validate(const lb_config* c) {
     return LB_OK;
 }
 
-// Plane stride: whole 2 KiB blocks plus one extra block on large grids, so
-// the q planes do not all start on the same large power-of-two boundary.
-int64_t stride_of(int64_t V) {
-    if (V < 65536) return (V + 63) / 64 * 64;
-    return (V + 255) / 256 * 256 + 256;
-}
-
 Geo make_geo(const lb_config* c) {
     Geo g;
     g.nx = (int)c->n[0];
     g.ny = (int)c->n[1];
     g.nz = (int)c->n[2];
     g.V = (int64_t)g.nx * g.ny * g.nz;
-    g.stride = stride_of(g.V);
     return g;
+}
+
+// Elements of one state buffer: q populations of every node, V rounded up to
+// whole chunks.
+int64_t elements_of(const lb_config* c) {
+    return (int64_t)q_of(c->dim) * lbm::chunks_of(make_geo(c).V) * lbm::CHUNK;
 }
 
 }  // namespace
@@ -172,15 +170,17 @@ lb_status lb_parameters(const lb_config* cfg, double* out7) {
     return LB_OK;
 }
 
-int64_t lb_state_stride(const lb_config* cfg) {
+int64_t lb_state_elements(const lb_config* cfg) {
     if (validate(cfg) == LB_ERR_INVALID_ARG) return 0;
-    return make_geo(cfg).stride;
+    return elements_of(cfg);
 }
 
 size_t lb_state_bytes(const lb_config* cfg) {
     if (validate(cfg) == LB_ERR_INVALID_ARG) return 0;
-    return (size_t)q_of(cfg->dim) * (size_t)make_geo(cfg).stride * sizeof(double);
+    return (size_t)elements_of(cfg) * sizeof(double);
 }
+
+int64_t lb_state_chunk(void) { return lbm::CHUNK; }
 
 lb_status lb_create(const lb_config* cfg, void* hip_stream, double* f_a, double* f_b,
                     lb_solver** out) {
@@ -307,6 +307,18 @@ lb_status lb_set_state(lb_solver* s, const double* f_in, int64_t step) {
     return LB_OK;
 }
 
+lb_status lb_layout_from_dense(lb_solver* s, const double* dense, double* buf) {
+    if (!s || !dense || !buf) return fail(LB_ERR_INVALID_ARG, "NULL argument");
+    LB_HIP(lbm::launch_layout_from_dense(s->d, s->g, dense, buf, s->stream), "layout_from_dense");
+    return LB_OK;
+}
+
+lb_status lb_layout_to_dense(lb_solver* s, const double* buf, double* dense) {
+    if (!s || !dense || !buf) return fail(LB_ERR_INVALID_ARG, "NULL argument");
+    LB_HIP(lbm::launch_layout_to_dense(s->d, s->g, buf, dense, s->stream), "layout_to_dense");
+    return LB_OK;
+}
+
 lb_status lb_macro_adjoint(lb_solver* s, const double* state, const double* g_theta,
                            const double* g_u, double* lambda, double* g_eps) {
     if (!s || !state || !lambda || !g_eps) return fail(LB_ERR_INVALID_ARG, "NULL argument");
@@ -349,7 +361,7 @@ lb_status lb_init_adjoint(lb_solver* s, const double* theta0, const double* grad
 
 struct lb_batch {
     std::vector<lb_config> cfgs;
-    std::vector<int64_t> offsets, strides, node_offsets;
+    std::vector<int64_t> offsets, elems, node_offsets;
     std::vector<BatchInst> insts;
     hipStream_t stream;
     hipStream_t capture;
@@ -396,15 +408,15 @@ static lb_status build_tiles(lb_batch* b, int tx, int ty) {
 extern "C" {
 
 int64_t lb_batch_layout(const lb_config* cfgs, int32_t count, int64_t* offsets,
-                        int64_t* strides) {
+                        int64_t* elems) {
     if (count < 0 || (count > 0 && !cfgs)) return -1;
     int64_t total = 0;
     for (int32_t i = 0; i < count; ++i) {
         if (validate(&cfgs[i]) == LB_ERR_INVALID_ARG || cfgs[i].dim != 2) return -1;
-        const int64_t st = make_geo(&cfgs[i]).stride;
+        const int64_t e = elements_of(&cfgs[i]);
         if (offsets) offsets[i] = total;
-        if (strides) strides[i] = st;
-        total += 9 * st;
+        if (elems) elems[i] = e;
+        total += e;
     }
     return total;
 }
@@ -425,15 +437,14 @@ lb_status lb_batch_create(const lb_config* cfgs, int32_t count, void* hip_stream
     if (!b) return fail(LB_ERR_OOM, "host allocation failed");
     b->cfgs.assign(cfgs, cfgs + count);
     b->offsets.resize(count);
-    b->strides.resize(count);
-    b->pool_elems = lb_batch_layout(cfgs, count, b->offsets.data(), b->strides.data());
+    b->elems.resize(count);
+    b->pool_elems = lb_batch_layout(cfgs, count, b->offsets.data(), b->elems.data());
     int64_t nodes = 0;
     for (int32_t i = 0; i < count; ++i) {
         b->node_offsets.push_back(nodes);
         nodes += cfgs[i].n[0] * cfgs[i].n[1];
         BatchInst in;
         in.offset = b->offsets[i];
-        in.stride = b->strides[i];
         in.nx = (int)cfgs[i].n[0];
         in.ny = (int)cfgs[i].n[1];
         in.r = make_rates(2, cfgs[i].dx, cfgs[i].dt, cfgs[i].nu);

@@ -8,10 +8,32 @@
 
 namespace lbm {
 
+// State layout ("chunked structure of arrays"): node indices are grouped in
+// chunks of CHUNK consecutive nodes; inside a chunk the q populations follow
+// one another as runs of CHUNK doubles.  Population i of node k lives at
+//     ((k / CHUNK) * q + i) * CHUNK + k % CHUNK.
+// With 4096-node chunks (32 KiB runs) the q read and q write streams of a
+// step stay inside a few contiguous regions of HBM, which sustains a higher
+// bandwidth on MI355X than q planes far apart.
+constexpr int LOG2_CHUNK = 12;
+constexpr int64_t CHUNK = int64_t(1) << LOG2_CHUNK;
+
+template <int Q>
+__host__ __device__ __forceinline__ int64_t slot(int i, int64_t k) {
+    return (((k >> LOG2_CHUNK) * Q + i) << LOG2_CHUNK) + (k & (CHUNK - 1));
+}
+
+inline int64_t chunks_of(int64_t V) { return (V + CHUNK - 1) >> LOG2_CHUNK; }
+
+// Launch geometry of the per-node kernels: one node per thread, 256 threads
+// per block laid along x (a block covers 256 consecutive nodes of one row).
+constexpr int BLOCK_X = 256;
+constexpr int BLOCK_Y = 1;
+constexpr int BLOCK_1D = 256;
+
 struct Geo {
     int nx, ny, nz;     // nodes per axis (1 for unused axes)
     int64_t V;          // nx * ny * nz
-    int64_t stride;     // elements between population planes
 };
 
 // Launch shape of the per-node kernels for one grid.
@@ -31,6 +53,10 @@ hipError_t launch_get_state(int d, const Geo& g, const double* state, double* de
                             hipStream_t st);
 hipError_t launch_set_state(int d, const Geo& g, const double* dense, double* state,
                             hipStream_t st);
+hipError_t launch_layout_from_dense(int d, const Geo& g, const double* dense, double* buf,
+                                   hipStream_t st);
+hipError_t launch_layout_to_dense(int d, const Geo& g, const double* buf, double* dense,
+                                 hipStream_t st);
 hipError_t launch_check_theta(const double* theta, int64_t n, int* flag, hipStream_t st);
 
 // Adjoint kernels write one partial sum of the eps-gradient per block into
@@ -48,8 +74,7 @@ hipError_t launch_finalize(const double* partials, int64_t n, double* g_eps, hip
 
 // Batched 2-D form.
 struct BatchInst {
-    int64_t offset;     // first element of plane 0 in the pool
-    int64_t stride;     // plane stride
+    int64_t offset;     // first element of the instance in the pool
     int nx, ny;
     Rates r;
 };

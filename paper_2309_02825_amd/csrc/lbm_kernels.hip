@@ -1,9 +1,10 @@
 // HIP kernels (gfx950) of the Cole-Hopf fourth-order MRT-LB solver.
 //
-// Data layout: a state buffer holds q planes of `stride` doubles (structure
-// of arrays, x fastest).  It is kept "stream-shifted": element k of plane i
-// is f_i(k + e_i), the population that node k sent along e_i after its last
-// collision, so one time step is a pull:
+// Data layout: a state buffer holds the q populations of every node in the
+// chunked structure-of-arrays order of `slot` (lbm_kernels.h).  It is kept
+// "stream-shifted": the slot of population i at node k holds f_i(k + e_i),
+// the population that node k sent along e_i after its last collision, so one
+// time step is a pull:
 //     f_i(x) = src_i(x - e_i)          (pre-collision distribution at x)
 //     dst_i(x) = (C f(x))_i            (collision, Sec. III.A)
 // Every store is aligned and coalesced; the loads of a wavefront are 64
@@ -11,8 +12,8 @@
 // HBM-bound (q*8 bytes read + q*8 written per node and step, a few flops per
 // byte), so no matrix cores are used.
 //
-// Every thread owns one node; blocks are 256 threads (64 x 4 in 2-D/3-D,
-// one wavefront per row segment), z (3-D) runs over grid.z.
+// Every thread owns one node; a block is 256 consecutive nodes of one row;
+// y and (3-D) z run over grid.y and grid.z.
 #include <type_traits>
 
 #include "lbm_kernels.h"
@@ -20,9 +21,9 @@
 namespace lbm {
 namespace {
 
-constexpr int BX = 64;   // threads along x (2-D/3-D)
-constexpr int BY = 4;    // rows per block (2-D/3-D)
-constexpr int B1 = 256;  // threads per block (1-D)
+constexpr int BX = BLOCK_X;
+constexpr int BY = BLOCK_Y;
+constexpr int B1 = BLOCK_1D;
 
 // Offsets of the neighbour x - e (e = -1, 0, +1) along each axis, periodic.
 struct Nbr {
@@ -132,11 +133,11 @@ __global__ void __launch_bounds__(256) k_step(const double* __restrict__ src,
     const Nbr nb = make_nbr<D>(x, y, z, g);
     double f[Q];
 #pragma unroll
-    for (int i = 0; i < Q; ++i) f[i] = src[(int64_t)i * g.stride + pull_index<D>(nb, i)];
+    for (int i = 0; i < Q; ++i) f[i] = src[slot<Q>(i, pull_index<D>(nb, i))];
     collide<D>(f, r);
     const int k = node_index(g, x, y, z);
 #pragma unroll
-    for (int i = 0; i < Q; ++i) __builtin_nontemporal_store(f[i], dst + (int64_t)i * g.stride + k);
+    for (int i = 0; i < Q; ++i) __builtin_nontemporal_store(f[i], dst + slot<Q>(i, k));
 }
 
 // ---------------------------------------------------------------------------
@@ -192,7 +193,7 @@ __global__ void __launch_bounds__(256) k_init(const double* __restrict__ th0,
             if (nnz<D>(i) == 1) ax = e == 1 ? ga : -ga;
         }
         const double w = weight<D>(i, r);
-        dst[(int64_t)i * g.stride + k] = w * t - r.dx * w * eg - corr * ax;
+        dst[slot<Q>(i, k)] = w * t - r.dx * w * eg - corr * ax;
     }
 }
 
@@ -209,7 +210,7 @@ __global__ void __launch_bounds__(256) k_macro(const double* __restrict__ src,
     const Nbr nb = make_nbr<D>(x, y, z, g);
     double f[Q];
 #pragma unroll
-    for (int i = 0; i < Q; ++i) f[i] = src[(int64_t)i * g.stride + pull_index<D>(nb, i)];
+    for (int i = 0; i < Q; ++i) f[i] = src[slot<Q>(i, pull_index<D>(nb, i))];
     double th = 0.0;
 #pragma unroll
     for (int i = 0; i < Q; ++i) th += f[i];
@@ -236,7 +237,7 @@ __global__ void __launch_bounds__(256) k_get_state(const double* __restrict__ sr
     const Nbr nb = make_nbr<D>(x, y, z, g);
     const int k = node_index(g, x, y, z);
 #pragma unroll
-    for (int i = 0; i < Q; ++i) dense[(int64_t)i * g.V + k] = src[(int64_t)i * g.stride + pull_index<D>(nb, i)];
+    for (int i = 0; i < Q; ++i) dense[(int64_t)i * g.V + k] = src[slot<Q>(i, pull_index<D>(nb, i))];
 }
 
 template <int D>
@@ -248,7 +249,31 @@ __global__ void __launch_bounds__(256) k_set_state(const double* __restrict__ de
     const Nbr nb = make_nbr<D>(x, y, z, g);
     const int k = node_index(g, x, y, z);
 #pragma unroll
-    for (int i = 0; i < Q; ++i) dst[(int64_t)i * g.stride + k] = dense[(int64_t)i * g.V + push_index<D>(nb, i)];
+    for (int i = 0; i < Q; ++i) dst[slot<Q>(i, k)] = dense[(int64_t)i * g.V + push_index<D>(nb, i)];
+}
+
+// Canonical (no stream shift) conversions between a dense q x V array and
+// the chunked layout, for distribution-shaped adjoint buffers.
+template <int D>
+__global__ void __launch_bounds__(256) k_layout_from_dense(const double* __restrict__ dense,
+                                                           double* __restrict__ buf, Geo g) {
+    constexpr int Q = Lat<D>::Q;
+    int x, y, z;
+    if (!thread_node<D>(g, x, y, z)) return;
+    const int k = node_index(g, x, y, z);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) buf[slot<Q>(i, k)] = dense[(int64_t)i * g.V + k];
+}
+
+template <int D>
+__global__ void __launch_bounds__(256) k_layout_to_dense(const double* __restrict__ buf,
+                                                         double* __restrict__ dense, Geo g) {
+    constexpr int Q = Lat<D>::Q;
+    int x, y, z;
+    if (!thread_node<D>(g, x, y, z)) return;
+    const int k = node_index(g, x, y, z);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) dense[(int64_t)i * g.V + k] = buf[slot<Q>(i, k)];
 }
 
 __global__ void __launch_bounds__(256) k_check_theta(const double* __restrict__ th, int64_t n,
@@ -277,7 +302,7 @@ __global__ void __launch_bounds__(256) k_macro_adjoint(const double* __restrict_
         const int k = node_index(g, x, y, z);
         double f[Q];
 #pragma unroll
-        for (int i = 0; i < Q; ++i) f[i] = src[(int64_t)i * g.stride + pull_index<D>(nb, i)];
+        for (int i = 0; i < Q; ++i) f[i] = src[slot<Q>(i, pull_index<D>(nb, i))];
         double th = 0.0;
 #pragma unroll
         for (int i = 0; i < Q; ++i) th += f[i];
@@ -302,7 +327,7 @@ __global__ void __launch_bounds__(256) k_macro_adjoint(const double* __restrict_
             double v = base;
 #pragma unroll
             for (int a = 0; a < D; ++a) v = LBM_SADD(v, Lat<D>::E[i][a], coef[a]);
-            lam[(int64_t)i * g.stride + k] = v;
+            lam[slot<Q>(i, k)] = v;
         }
     }
     const double s = block_sum(ge);
@@ -325,8 +350,8 @@ __global__ void __launch_bounds__(256) k_adjoint_step(const double* __restrict__
         double f[Q], mu[Q];
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
-            f[i] = state[(int64_t)i * g.stride + pull_index<D>(nb, i)];
-            mu[i] = lin[(int64_t)i * g.stride + push_index<D>(nb, i)];
+            f[i] = state[slot<Q>(i, pull_index<D>(nb, i))];
+            mu[i] = lin[slot<Q>(i, push_index<D>(nb, i))];
         }
         double df[Q];
         collide_deps<D>(f, r, df);
@@ -335,7 +360,7 @@ __global__ void __launch_bounds__(256) k_adjoint_step(const double* __restrict__
         double lam[Q];
         collide_adjoint<D>(mu, r, lam);
 #pragma unroll
-        for (int i = 0; i < Q; ++i) lout[(int64_t)i * g.stride + k] = lam[i];
+        for (int i = 0; i < Q; ++i) lout[slot<Q>(i, k)] = lam[i];
     }
     const double s = block_sum(ge);
     if (threadIdx.x == 0 && threadIdx.y == 0) partials[block_linear()] = s;
@@ -352,7 +377,7 @@ __device__ __forceinline__ double init_h(const double* __restrict__ lam, const G
     for (int i = 0; i < Q; ++i) {
         const int e = Lat<D>::E[i][a];
         if (e == 0) continue;
-        const double l = lam[(int64_t)i * g.stride + k];
+        const double l = lam[slot<Q>(i, k)];
         const double wl = weight<D>(i, r) * l;
         s = e == 1 ? s + wl : s - wl;
         if (nnz<D>(i) == 1) ax = e == 1 ? ax + l : ax - l;
@@ -375,7 +400,7 @@ __global__ void __launch_bounds__(256) k_init_adjoint(const double* __restrict__
         const int k = node_index(g, x, y, z);
         double l[Q];
 #pragma unroll
-        for (int i = 0; i < Q; ++i) l[i] = lam[(int64_t)i * g.stride + k];
+        for (int i = 0; i < Q; ++i) l[i] = lam[slot<Q>(i, k)];
         double gt = 0.0;
 #pragma unroll
         for (int i = 0; i < Q; ++i) gt += weight<D>(i, r) * l[i];
@@ -455,18 +480,17 @@ __global__ void __launch_bounds__(256) k_batch_step(const BatchInst* __restrict_
     g.ny = in.ny;
     g.nz = 1;
     g.V = (int64_t)in.nx * in.ny;
-    g.stride = in.stride;
     const Nbr nb = make_nbr<2>(x, y, 0, g);
     const double* s = src + in.offset;
     double* d = dst + in.offset;
     double f[Q];
 #pragma unroll
-    for (int i = 0; i < Q; ++i) f[i] = s[(int64_t)i * g.stride + pull_index<2>(nb, i)];
+    for (int i = 0; i < Q; ++i) f[i] = s[slot<Q>(i, pull_index<2>(nb, i))];
     const Rates r = in.r;
     collide<2>(f, r);
     const int k = y * g.nx + x;
 #pragma unroll
-    for (int i = 0; i < Q; ++i) __builtin_nontemporal_store(f[i], d + (int64_t)i * g.stride + k);
+    for (int i = 0; i < Q; ++i) __builtin_nontemporal_store(f[i], d + slot<Q>(i, k));
 }
 
 template <typename F>
@@ -526,6 +550,16 @@ hipError_t launch_get_state(int d, const Geo& g, const double* state, double* de
 hipError_t launch_set_state(int d, const Geo& g, const double* dense, double* state,
                             hipStream_t st) {
     return LBM_LAUNCH(k_set_state, dense, state, g);
+}
+
+hipError_t launch_layout_from_dense(int d, const Geo& g, const double* dense, double* buf,
+                                   hipStream_t st) {
+    return LBM_LAUNCH(k_layout_from_dense, dense, buf, g);
+}
+
+hipError_t launch_layout_to_dense(int d, const Geo& g, const double* buf, double* dense,
+                                 hipStream_t st) {
+    return LBM_LAUNCH(k_layout_to_dense, buf, dense, g);
 }
 
 hipError_t launch_check_theta(const double* theta, int64_t n, int* flag, hipStream_t st) {

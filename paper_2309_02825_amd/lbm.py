@@ -68,7 +68,10 @@ def _load():
     sigs = {
         "lb_parameters": ([_cp, _vp], st),
         "lb_num_populations": ([I32], I32),
-        "lb_state_stride": ([_cp], I64),
+        "lb_state_chunk": ([], I64),
+        "lb_state_elements": ([_cp], I64),
+        "lb_layout_from_dense": ([_vp, _vp, _vp], st),
+        "lb_layout_to_dense": ([_vp, _vp, _vp], st),
         "lb_state_bytes": ([_cp], ctypes.c_size_t),
         "lb_create": ([_cp, _vp, _vp, _vp, ctypes.POINTER(_vp)], st),
         "lb_init": ([_vp, _vp, _vp, I32], st),
@@ -142,8 +145,12 @@ def lb_parameters(cfg: lb_config):
     return dict(zip(["eps", "s1", "s21", "s22", "w0", "w1", "wd"], list(out)))
 
 
-def lb_state_stride(cfg: lb_config) -> int:
-    return _load().lb_state_stride(ctypes.byref(cfg))
+def lb_state_chunk() -> int:
+    return _load().lb_state_chunk()
+
+
+def lb_state_elements(cfg: lb_config) -> int:
+    return _load().lb_state_elements(ctypes.byref(cfg))
 
 
 def lb_state_bytes(cfg: lb_config) -> int:
@@ -192,6 +199,14 @@ def lb_set_state(h: int, f_in, step: int = 0):
     _check(_load().lb_set_state(h, _ptr(f_in), int(step)))
 
 
+def lb_layout_from_dense(h: int, dense, buf):
+    _check(_load().lb_layout_from_dense(h, _ptr(dense), _ptr(buf)))
+
+
+def lb_layout_to_dense(h: int, buf, dense):
+    _check(_load().lb_layout_to_dense(h, _ptr(buf), _ptr(dense)))
+
+
 def lb_macro_adjoint(h: int, state, g_theta, g_u, lam, g_eps):
     _check(_load().lb_macro_adjoint(h, _ptr(state), _ptr(g_theta), _ptr(g_u), _ptr(lam),
                                     _ptr(g_eps)))
@@ -213,11 +228,11 @@ def lb_destroy(h: int):
 def lb_batch_layout(cfgs: Sequence[lb_config]):
     arr = (lb_config * len(cfgs))(*cfgs)
     offs = (ctypes.c_int64 * len(cfgs))()
-    strd = (ctypes.c_int64 * len(cfgs))()
-    total = _load().lb_batch_layout(arr, len(cfgs), ctypes.cast(offs, _vp), ctypes.cast(strd, _vp))
+    elems = (ctypes.c_int64 * len(cfgs))()
+    total = _load().lb_batch_layout(arr, len(cfgs), ctypes.cast(offs, _vp), ctypes.cast(elems, _vp))
     if total < 0:
         raise LBError(LB_ERR_INVALID_ARG, "invalid batch configs")
-    return total, list(offs), list(strd)
+    return total, list(offs), list(elems)
 
 
 def lb_batch_create(cfgs: Sequence[lb_config], stream: int, pool_a, pool_b) -> int:

@@ -49,7 +49,6 @@ class Solver:
         nbytes = L.lb_state_bytes(self.cfg)
         if nbytes == 0:
             raise L.LBError(L.LB_ERR_INVALID_ARG, L.lb_last_error())
-        self.stride = L.lb_state_stride(self.cfg)
         self.state_elems = nbytes // 8
         self.bufs = [torch.empty(self.state_elems, dtype=F64, device=self.device) for _ in range(2)]
         self._stream = stream
@@ -113,6 +112,19 @@ class Solver:
         f = _field(f, (self.q,) + self.shape, self.device, "f")
         self._set_src = f
         L.lb_set_state(self.h, f, step)
+
+    def to_layout(self, dense: torch.Tensor) -> torch.Tensor:
+        """Dense (q, *shape) distribution-shaped array -> chunked buffer (no stream shift)."""
+        dense = _field(dense, (self.q,) + self.shape, self.device, "dense")
+        buf = torch.zeros(self.state_elems, dtype=F64, device=self.device)
+        L.lb_layout_from_dense(self.h, dense, buf)
+        return buf
+
+    def from_layout(self, buf: torch.Tensor) -> torch.Tensor:
+        """Chunked buffer -> dense (q, *shape) array (no stream shift)."""
+        out = torch.empty((self.q,) + self.shape, dtype=F64, device=self.device)
+        L.lb_layout_to_dense(self.h, buf, out)
+        return out
 
     # -- adjoint ----------------------------------------------------------
     def macro_adjoint(self, state, g_theta, g_u, g_eps):
@@ -237,7 +249,7 @@ class BatchSolver:
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         self.cfgs = [L.make_config(p.grid, p.dx, p.dt, p.nu) for p in problems]
         self.grids = [tuple(p.grid) for p in problems]
-        total, self.offsets, self.strides = L.lb_batch_layout(self.cfgs)
+        total, self.offsets, self.elems = L.lb_batch_layout(self.cfgs)
         self.nodes = [g[0] * g[1] for g in self.grids]
         self.node_offsets = [0]
         for n in self.nodes[:-1]:

@@ -46,13 +46,15 @@ def test_parameters_match_oracle(d, eps):
 
 
 def test_state_layout():
+    C = L.lb_state_chunk()
+    assert C == 4096
     for grid in [(1,), (7,), (64, 64), (100, 70), (1024, 1024), (20, 17, 9), (256, 256, 256)]:
         c = L.make_config(grid, 0.1, 0.001, 0.1)
         V = math.prod(grid)
         q = L.lb_num_populations(len(grid))
-        st = L.lb_state_stride(c)
-        assert st >= V and st % 64 == 0
-        assert L.lb_state_bytes(c) == q * st * 8
+        el = L.lb_state_elements(c)
+        assert el == q * ((V + C - 1) // C) * C
+        assert L.lb_state_bytes(c) == 8 * el
     assert L.lb_num_populations(1) == 3 and L.lb_num_populations(2) == 9
     assert L.lb_num_populations(3) == 19 and L.lb_num_populations(4) == 0
 
@@ -99,11 +101,13 @@ def test_unused_axes_must_be_one():
 
 def test_batch_layout():
     cfgs = [L.make_config((n, n + 3), 1 / n, 4 / n ** 2, 0.01) for n in (64, 100, 1024)]
-    total, offs, strides = L.lb_batch_layout(cfgs)
+    total, offs, elems = L.lb_batch_layout(cfgs)
     assert offs[0] == 0
     for i in range(1, 3):
-        assert offs[i] == offs[i - 1] + 9 * strides[i - 1]
-    assert total == offs[-1] + 9 * strides[-1]
+        assert offs[i] == offs[i - 1] + elems[i - 1]
+        assert offs[i] % L.lb_state_chunk() == 0
+    assert total == offs[-1] + elems[-1]
+    assert elems == [L.lb_state_elements(c) for c in cfgs]
     with pytest.raises(L.LBError):
         L.lb_batch_layout([L.make_config((8, 8, 8), 0.1, 0.01, 0.1)])
 

@@ -325,9 +325,8 @@ def test_adjoint_dot_product_on_gpu():
         nxt = s.new_state()
         s.step_buffers(st[-1], nxt)
         st.append(nxt)
-    # lambda in the canonical layout with the solver's plane stride
-    lam_c = torch.zeros(s.state_elems, dtype=torch.float64, device=_dev())
-    lam_c.view(-1)[: q * s.stride].view(q, s.stride)[:, : 40 * 28] = lam.reshape(q, -1)
+    # lambda in the chunked layout with canonical node positions
+    lam_c = s.to_layout(lam)
     g_eps = torch.zeros(1, dtype=torch.float64, device=_dev())
     cur, other = lam_c, s.new_state()
     for n in range(k - 1, -1, -1):
@@ -338,7 +337,7 @@ def test_adjoint_dot_product_on_gpu():
     s.step(k)
     fk = s.get_state()
     lhs = float((lam * fk).sum().item())
-    rhs = float((cur.view(q, s.stride)[:, : 40 * 28].reshape(q, 28, 40) * v).sum().item())
+    rhs = float((s.from_layout(cur) * v).sum().item())
     torch.cuda.synchronize()
     s.close()
     assert abs(lhs - rhs) <= 1e-12 * float((lam * fk).abs().sum().item())
