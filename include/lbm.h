@@ -213,8 +213,10 @@ lb_status lb_batch_create(const lb_config* cfgs, int32_t count, void* hip_stream
  * differences per instance). */
 lb_status lb_batch_init(lb_batch* b, const double* theta0, const double* grad);
 
-/* Tile shape (threads along x, rows per block); tx*ty must be 256 and tx a
- * power of two in [16, 256].  Applies to subsequent steps. */
+/* Tile shape of the batched step: (0, 0) selects linear tiles of 256
+ * consecutive node indices of one instance (crossing row ends; the default),
+ * otherwise a tx x ty rectangle with tx*ty = 256 and tx a power of two in
+ * [16, 256].  Applies to subsequent steps. */
 lb_status lb_batch_set_tile(lb_batch* b, int32_t tx, int32_t ty);
 
 /* Time candidate tile shapes on the real pools (state is restored) and keep

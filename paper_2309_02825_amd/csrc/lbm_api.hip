@@ -386,8 +386,13 @@ static lb_status build_tiles(lb_batch* b, int tx, int ty) {
     std::vector<BatchTile> tiles;
     for (size_t i = 0; i < b->insts.size(); ++i) {
         const BatchInst& in = b->insts[i];
-        for (int y0 = 0; y0 < in.ny; y0 += ty)
-            for (int x0 = 0; x0 < in.nx; x0 += tx) tiles.push_back(BatchTile{(int)i, x0, y0, 0});
+        if (tx == 0) {
+            const int64_t V = (int64_t)in.nx * in.ny;
+            for (int64_t k0 = 0; k0 < V; k0 += 256) tiles.push_back(BatchTile{(int)i, (int)k0, 0, 0});
+        } else {
+            for (int y0 = 0; y0 < in.ny; y0 += ty)
+                for (int x0 = 0; x0 < in.nx; x0 += tx) tiles.push_back(BatchTile{(int)i, x0, y0, 0});
+        }
     }
     if (tiles.size() > (size_t)INT_MAX) return fail(LB_ERR_INVALID_ARG, "too many tiles");
     if (b->d_tiles) (void)hipFree(b->d_tiles);
@@ -470,7 +475,7 @@ lb_status lb_batch_create(const lb_config* cfgs, int32_t count, void* hip_stream
         delete b;
         return hip_fail(e, "batch setup");
     }
-    lb_status st = build_tiles(b, 64, 4);
+    lb_status st = build_tiles(b, 0, 0);
     if (st != LB_OK) {
         lb_batch_destroy(b);
         return st;
@@ -507,8 +512,10 @@ lb_status lb_batch_init(lb_batch* b, const double* theta0, const double* grad) {
 
 lb_status lb_batch_set_tile(lb_batch* b, int32_t tx, int32_t ty) {
     if (!b) return fail(LB_ERR_INVALID_ARG, "batch is NULL");
-    if (tx < 16 || tx > 256 || (tx & (tx - 1)) != 0 || tx * ty != 256)
-        return fail(LB_ERR_INVALID_ARG, "tile must be tx*ty = 256 with tx a power of two in [16,256]");
+    const bool linear = (tx == 0 && ty == 0);
+    if (!linear && (tx < 16 || tx > 256 || (tx & (tx - 1)) != 0 || tx * ty != 256))
+        return fail(LB_ERR_INVALID_ARG,
+                    "tile must be (0,0) or tx*ty = 256 with tx a power of two in [16,256]");
     if (tx == b->tx && ty == b->ty) return LB_OK;
     return build_tiles(b, tx, ty);
 }
@@ -563,7 +570,7 @@ lb_status lb_batch_autotune(lb_batch* b, int32_t steps_per_trial, int32_t* best_
     if (!b) return fail(LB_ERR_INVALID_ARG, "batch is NULL");
     if (!b->inited) return fail(LB_ERR_STATE, "autotune needs an initialised batch");
     if (steps_per_trial < 1) steps_per_trial = 1;
-    static const int cand[][2] = {{256, 1}, {128, 2}, {64, 4}, {32, 8}, {16, 16}};
+    static const int cand[][2] = {{0, 0}, {256, 1}, {128, 2}, {64, 4}, {32, 8}, {16, 16}};
     hipEvent_t e0, e1;
     LB_HIP(hipEventCreate(&e0), "hipEventCreate");
     LB_HIP(hipEventCreate(&e1), "hipEventCreate");

@@ -464,6 +464,9 @@ __global__ void __launch_bounds__(256) k_finalize(const double* __restrict__ par
 // ---------------------------------------------------------------------------
 // batched 2-D step over a tile table
 // ---------------------------------------------------------------------------
+// One block per tile.  tx > 0: a tx x (256/tx) rectangle of one instance at
+// (x0, y0); tx == 0: 256 consecutive node indices of one instance starting at
+// x0, crossing row ends, so no lane idles except at the instance's last tile.
 __global__ void __launch_bounds__(256) k_batch_step(const BatchInst* __restrict__ insts,
                                                     const BatchTile* __restrict__ tiles, int tx,
                                                     int log2tx, const double* __restrict__ src,
@@ -472,9 +475,17 @@ __global__ void __launch_bounds__(256) k_batch_step(const BatchInst* __restrict_
     const BatchTile t = tiles[xcd_remap(blockIdx.x, gridDim.x)];
     const BatchInst& in = insts[t.inst];
     const int tid = threadIdx.x;
-    const int x = t.x0 + (tid & (tx - 1));
-    const int y = t.y0 + (tid >> log2tx);
-    if (x >= in.nx || y >= in.ny) return;
+    int x, y;
+    if (tx == 0) {
+        const int k = t.x0 + tid;
+        if (k >= in.nx * in.ny) return;
+        y = k / in.nx;
+        x = k - y * in.nx;
+    } else {
+        x = t.x0 + (tid & (tx - 1));
+        y = t.y0 + (tid >> log2tx);
+        if (x >= in.nx || y >= in.ny) return;
+    }
     Geo g;
     g.nx = in.nx;
     g.ny = in.ny;
@@ -596,7 +607,7 @@ hipError_t launch_batch_step(const BatchInst* insts, const BatchTile* tiles, int
                              int tx, int ty, const double* src, double* dst, hipStream_t st) {
     (void)ty;
     int log2tx = 0;
-    while ((1 << log2tx) < tx) ++log2tx;
+    while (tx > 0 && (1 << log2tx) < tx) ++log2tx;
     if (ntiles <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_batch_step, dim3((unsigned)ntiles), dim3(256), 0, st, insts, tiles, tx,
                        log2tx, src, dst);
