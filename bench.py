@@ -141,6 +141,34 @@ def kernel_only(torch, SV, W, wl, lb_steps, dev):
     return ms
 
 
+def form_heat1d(torch, SV, W, dev):
+    """1-D convergence sweep (n = 16..128 to t = 0.1): latency-bound solves."""
+    out = {}
+    stream = torch.cuda.current_stream()
+    for n in (16, 32, 64, 128):
+        wl = W.heat_1d(n)
+        s = SV.Solver(wl.grid, wl.dx, wl.dt, wl.nu, device=dev)
+        th0, g0 = W.evaluate(wl.modes, wl.grid, wl.dx, xp=torch, device=dev)
+        for _ in range(2):
+            s.init(th0, g0)
+            s.step(wl.nsteps)
+            s.macro()
+        timer = Timer(torch, stream)
+        reps = 20
+        timer.start()
+        for _ in range(reps):
+            s.init(th0, g0)
+            s.step(wl.nsteps)
+            s.macro()
+        timer.stop()
+        torch.cuda.synchronize()
+        us = timer.total_ms() / reps * 1e3
+        out[f"n{n}"] = {"lb_steps": wl.nsteps, "us_per_solve": round(us, 2),
+                        "mlups": round(n * wl.nsteps / us, 2)}
+        s.close()
+    return out
+
+
 def form_batched(torch, SV, W, dev):
     insts = W.batch_instances()
     bs = SV.BatchSolver(insts, device=dev)
@@ -322,6 +350,8 @@ def main():
                            "mlups": round(ml, 1), "gbs_algorithmic": round(gbs, 1),
                            "frac": round(gbs / HBM_PEAK_GBS, 4), "lb_steps_timed": n}
             log(name, forms[name])
+        forms["heat1d_sweep"] = form_heat1d(torch, SV, W, dev)
+        log("heat1d_sweep", forms["heat1d_sweep"])
         b = form_batched(torch, SV, W, dev)
         plain = V / (kms / 1e3) / 1e6 if d == 2 else None
         if plain:

@@ -258,6 +258,17 @@ lb_status lb_step(lb_solver* s, int64_t nsteps) {
     if (!s) return fail(LB_ERR_INVALID_ARG, "solver is NULL");
     if (nsteps < 0) return fail(LB_ERR_INVALID_ARG, "nsteps must be >= 0");
     if (!s->inited) return fail(LB_ERR_STATE, "lb_step before lb_init/lb_set_state");
+    if (s->d == 1 && s->g.nx <= lbm::RESIDENT_MAX_1D && nsteps >= 2) {
+        // whole run in one launch; the result lands where the per-step
+        // ping-pong would have left it
+        const int dst = s->cur ^ (int)(nsteps & 1);
+        LB_HIP(lbm::launch_step_resident1(s->g, s->r, s->buf[s->cur], s->buf[dst], nsteps,
+                                          s->stream),
+               "resident step launch");
+        s->cur = dst;
+        s->steps += nsteps;
+        return LB_OK;
+    }
     for (int64_t n = 0; n < nsteps; ++n) {
         LB_HIP(lbm::launch_step(s->d, s->g, s->r, s->buf[s->cur], s->buf[1 - s->cur], s->stream),
                "step launch");

@@ -45,6 +45,11 @@ Launch launch_shape(int d, const Geo& g);
 
 hipError_t launch_step(int d, const Geo& g, const Rates& r, const double* src, double* dst,
                        hipStream_t st);
+// 1-D grids up to this many nodes run all their steps in one launch with the
+// state in LDS (3 populations x 8 B x 2048 = 48 KiB).
+constexpr int RESIDENT_MAX_1D = 2048;
+hipError_t launch_step_resident1(const Geo& g, const Rates& r, const double* src, double* dst,
+                                int64_t nsteps, hipStream_t st);
 hipError_t launch_init(int d, const Geo& g, const Rates& r, const double* theta0,
                        const double* grad, double* dst, hipStream_t st);
 hipError_t launch_macro(int d, const Geo& g, const Rates& r, const double* state, double* theta,

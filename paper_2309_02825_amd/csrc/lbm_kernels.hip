@@ -140,6 +140,52 @@ __global__ void __launch_bounds__(256) k_step(const double* __restrict__ src,
     for (int i = 0; i < Q; ++i) __builtin_nontemporal_store(f[i], dst + slot<Q>(i, k));
 }
 
+// Small 1-D grids (n <= RESIDENT_MAX_1D): the whole state lives in LDS and
+// one workgroup advances all nsteps in a single launch, so the run is not
+// bound by one kernel launch per step.  Same collision as k_step<1>.
+constexpr int RES_THREADS = 256;
+
+__global__ void __launch_bounds__(RES_THREADS) k_step_resident1(const double* __restrict__ src,
+                                                                double* __restrict__ dst, int n,
+                                                                int64_t nsteps, Rates r) {
+    __shared__ double lds[3 * RESIDENT_MAX_1D];
+    for (int x = threadIdx.x; x < n; x += RES_THREADS)
+#pragma unroll
+        for (int i = 0; i < 3; ++i) lds[i * RESIDENT_MAX_1D + x] = src[slot<3>(i, x)];
+    __syncthreads();
+    constexpr int PER = (RESIDENT_MAX_1D + RES_THREADS - 1) / RES_THREADS;
+    for (int64_t s = 0; s < nsteps; ++s) {
+        double f[PER][3];
+#pragma unroll
+        for (int p = 0; p < PER; ++p) {
+            const int x = threadIdx.x + p * RES_THREADS;
+            if (x < n) {
+                const int xm = x == 0 ? n - 1 : x - 1;
+                const int xp = x == n - 1 ? 0 : x + 1;
+                double g[3] = {lds[x], lds[RESIDENT_MAX_1D + xm], lds[2 * RESIDENT_MAX_1D + xp]};
+                collide<1>(g, r);
+                f[p][0] = g[0];
+                f[p][1] = g[1];
+                f[p][2] = g[2];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int p = 0; p < PER; ++p) {
+            const int x = threadIdx.x + p * RES_THREADS;
+            if (x < n) {
+                lds[x] = f[p][0];
+                lds[RESIDENT_MAX_1D + x] = f[p][1];
+                lds[2 * RESIDENT_MAX_1D + x] = f[p][2];
+            }
+        }
+        __syncthreads();
+    }
+    for (int x = threadIdx.x; x < n; x += RES_THREADS)
+#pragma unroll
+        for (int i = 0; i < 3; ++i) dst[slot<3>(i, x)] = lds[i * RESIDENT_MAX_1D + x];
+}
+
 // ---------------------------------------------------------------------------
 // initialisation
 // ---------------------------------------------------------------------------
@@ -541,6 +587,14 @@ Launch launch_shape(int d, const Geo& g) {
 hipError_t launch_step(int d, const Geo& g, const Rates& r, const double* src, double* dst,
                        hipStream_t st) {
     return LBM_LAUNCH(k_step, src, dst, g, r);
+}
+
+hipError_t launch_step_resident1(const Geo& g, const Rates& r, const double* src, double* dst,
+                                int64_t nsteps, hipStream_t st) {
+    if (g.nx > RESIDENT_MAX_1D || g.ny != 1 || g.nz != 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_step_resident1, dim3(1), dim3(RES_THREADS), 0, st, src, dst, g.nx, nsteps,
+                       r);
+    return hipGetLastError();
 }
 
 hipError_t launch_init(int d, const Geo& g, const Rates& r, const double* theta0,

@@ -174,6 +174,28 @@ def test_set_state_roundtrip_and_step_buffers():
     s.close()
 
 
+def test_resident_1d_run_equals_per_step_launches():
+    """Small 1-D grids run all steps in one LDS-resident launch; the result is
+    bitwise the one of one launch per step."""
+    _say("1d resident vs per-step")
+    SV = _solver_mod()
+    for n, steps in ((300, 51), (2048, 20), (2049, 6), (1, 4)):
+        dx, dt, nu, th0, _ = _problem((n,), "random")
+        outs = []
+        for per_step in (True, False):
+            s = SV.Solver((n,), dx, dt, nu, device=_dev())
+            s.init(torch.from_numpy(th0).to(_dev()), None)
+            if per_step:
+                for _ in range(steps):
+                    s.step(1)
+            else:
+                s.step(steps)
+            outs.append(s.get_state().cpu().numpy())
+            assert s.steps == steps
+            s.close()
+        assert np.array_equal(outs[0], outs[1]), n
+
+
 def test_run_to_run_bitwise_determinism():
     _say("determinism")
     grid = (257, 129)
