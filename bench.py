@@ -28,7 +28,7 @@ if ROOT not in sys.path:
 
 METRIC = "FP64 MLUPS + HBM GB/s (% roofline); batched and adjoint vs plain step"
 HBM_PEAK_GBS = 8000.0
-BYTES_PER_LU = {1: 48, 2: 144, 3: 304}
+BYTES_PER_LU = {1: 48, 2: 144, 3: 304, 4: 528}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_step.json")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2309_02825_amd", "csrc", n)
                   for n in ("lbm_kernels.hip", "lbm_lattice.h", "lbm_kernels.h")]
@@ -53,6 +53,7 @@ def workload(name: str):
         "heat2d_1024": lambda: W.heat_2d(1024, 10000),
         "heat3d_256": lambda: W.heat_3d(256, 2000),
         "heat3d_512": lambda: W.heat_3d(512, 2000),
+        "heat4d_64": lambda: W.heat_4d(64, 200),
     }
     return table[name]()
 
@@ -267,7 +268,7 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="heat2d_4096",
-                    choices=["heat2d_4096", "heat2d_1024", "heat3d_256", "heat3d_512"])
+                    choices=["heat2d_4096", "heat2d_1024", "heat3d_256", "heat3d_512", "heat4d_64"])
     ap.add_argument("--lb-steps", type=int, default=0,
                     help="override the LB time steps per solve (profiling runs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -310,7 +311,7 @@ def main():
     achieved = BYTES_PER_LU[d] * V / (kms / 1e3) / 1e9
     log(f"{mlups:.1f} MLUPS, kernel {kms * 1e3:.2f} us/step, {achieved:.1f} GB/s")
     traffic = traffic_for(args.workload, wl.nsteps)
-    lattice = {1: "D1Q3", 2: "D2Q9", 3: "D3Q19"}[d]
+    lattice = {1: "D1Q3", 2: "D2Q9", 3: "D3Q19", 4: "D4Q33"}[d]
     rec = {
         "metric": METRIC,
         "value": round(mlups, 1),
@@ -338,15 +339,16 @@ def main():
         rec["cpu_baseline"] = cpu_baseline(wl)
     if not args.no_forms:
         forms = {}
-        for name in ("heat2d_1024", "heat3d_256", "heat3d_512"):
+        for name in ("heat2d_1024", "heat3d_256", "heat3d_512", "heat4d_64"):
             if name == args.workload:
                 continue
             w2 = workload(name)
-            n = 400 if w2.d == 3 else 2000
+            n = {2: 2000, 3: 400, 4: 100}[w2.d]
             ms = kernel_only(torch, SV, W, w2, n, dev)
             ml = w2.nodes / (ms / 1e3) / 1e6
             gbs = BYTES_PER_LU[w2.d] * ml / 1e3
-            forms[name] = {"lattice": {2: "D2Q9", 3: "D3Q19"}[w2.d], "kernel_us_per_step": round(ms * 1e3, 2),
+            forms[name] = {"lattice": {2: "D2Q9", 3: "D3Q19", 4: "D4Q33"}[w2.d],
+                           "kernel_us_per_step": round(ms * 1e3, 2),
                            "mlups": round(ml, 1), "gbs_algorithmic": round(gbs, 1),
                            "frac": round(gbs / HBM_PEAK_GBS, 4), "lb_steps_timed": n}
             log(name, forms[name])

@@ -4,7 +4,7 @@
  *
  * The library advances the transformed diffusion equation theta_t = nu lap theta
  * (Sec. II, Cole-Hopf transformation of the coupled Burgers equations) with the
- * D1Q3 / D2Q9 / D3Q19 natural-moment MRT-LB model of Sec. III.A, using the
+ * D1Q3 / D2Q9 / D3Q19 / D4Q33 natural-moment MRT-LB model of Sec. III.A, using the
  * relaxation rates and weights of Theorem 2 (Sec. III.D) that make the scheme
  * and the velocity u = -2 nu grad(theta)/theta fourth-order accurate.  All
  * arithmetic is IEEE double precision on the GPU; boundaries are periodic.
@@ -20,10 +20,9 @@
  *     partials), allocated at creation and freed by lb_destroy.
  *   - Work is enqueued asynchronously on the HIP stream given at creation
  *     (NULL = the default stream); the host returns before the GPU finishes.
- *   - Grid: n[0] nodes along x_0 (fastest), n[1] along x_1, n[2] along x_2;
- *     unused dimensions must be 1.  Node index k = x0 + n0*(x1 + n1*x2),
- *     V = n0*n1*n2 nodes, node spacing dx, time step dt, lattice speed
- *     c = dx/dt, eps = nu*dt/dx^2.
+ *   - Grid: n[a] nodes along x_a (x_0 fastest); unused dimensions must be 1.
+ *     Node index k = x0 + n0*(x1 + n1*(x2 + n2*x3)), V = n0*n1*n2*n3 nodes,
+ *     node spacing dx, time step dt, lattice speed c = dx/dt, eps = nu*dt/dx^2.
  *   - Dense fields: theta is V doubles; a vector field (grad theta, u) is
  *     d planes of V doubles (component a = along x_a) back to back.
  *   - State buffers hold the q populations of every node in a chunked
@@ -42,7 +41,10 @@
  *     lb_layout_to_dense convert such buffers to and from q x V arrays.
  *   - Velocity order (Sec. III.A): D1Q3 (0, +1, -1); D2Q9 (0,0) (1,0) (0,1)
  *     (-1,0) (0,-1) (1,1) (-1,1) (-1,-1) (1,-1); D3Q19 rest, +x, +y, +z, -x,
- *     -y, -z, then the xy, xz, yz edges each as (+,+) (-,+) (-,-) (+,-).
+ *     -y, -z, then the xy, xz, yz edges each as (+,+) (-,+) (-,-) (+,-);
+ *     D4Q33 (general rule of Sec. III.A for d > 3) rest, +x_0..+x_3,
+ *     -x_0..-x_3, then for every axis pair a < b in lexicographic order
+ *     (e_a, e_b) = (+,+) (-,+) (-,-) (+,-).
  */
 #ifndef LBM_H
 #define LBM_H
@@ -57,8 +59,9 @@ extern "C" {
 typedef enum {
     LB_OK = 0,
     LB_ERR_INVALID_ARG = -1, /* bad dimension/size/spacing, NULL pointer, ... */
-    LB_ERR_UNSTABLE = -2,    /* eps outside the range where the weights stay
-                                non-negative (d = 2: eps < 0.5, d = 3: eps <= 0.25) */
+    LB_ERR_UNSTABLE = -2,    /* eps above the lattice's stability limit (von Neumann
+                                spectral radius > 1): D2Q9 0.48, D3Q19 1/4 and
+                                D4Q33 1/6 (w1 >= 0); D1Q3 has none */
     LB_ERR_NONFINITE = -3,   /* a non-finite or non-positive theta was found */
     LB_ERR_OOM = -4,         /* the library could not allocate its small tables */
     LB_ERR_HIP = -5,         /* a HIP runtime call failed */
@@ -69,9 +72,9 @@ typedef struct lb_solver lb_solver; /* opaque, library-owned host object */
 typedef struct lb_batch lb_batch;   /* opaque, library-owned host object */
 
 typedef struct {
-    int32_t dim;     /* 1, 2 or 3 */
+    int32_t dim;     /* 1, 2, 3 or 4 */
     int32_t flags;   /* reserved, must be 0 */
-    int64_t n[3];    /* nodes per axis, >= 1; n[a] = 1 for a >= dim */
+    int64_t n[4];    /* nodes per axis, >= 1; n[a] = 1 for a >= dim */
     double dx;       /* node spacing, > 0 */
     double dt;       /* time step, > 0 */
     double nu;       /* viscosity of the Burgers equations (Sec. II), > 0 */
@@ -83,7 +86,7 @@ typedef struct {
  * w_{1+2d} = eps/6 (0 for d = 1).  out[0..6] = eps, s1, s21, s22, w0, w1, wd. */
 lb_status lb_parameters(const lb_config* cfg, double* out7);
 
-/* Number of populations q = 1 + 2 d^2 (3, 9, 19) for cfg->dim. */
+/* Number of populations q = 1 + 2 d^2 (3, 9, 19, 33) for dim = 1..4 (0 otherwise). */
 int32_t lb_num_populations(int32_t dim);
 
 /* Nodes per chunk of the state layout (4096). */

@@ -85,14 +85,27 @@ Rates make_rates(int d, double dx, double dt, double nu) {
     return r;
 }
 
-int q_of(int d) { return d == 1 ? 3 : (d == 2 ? 9 : (d == 3 ? 19 : 0)); }
+int q_of(int d) { return (d >= 1 && d <= 4) ? 1 + 2 * d * d : 0; }
+
+// Largest eps for which the scheme is accepted.  d = 3, 4: w1 = 1/6 - (d-1) eps/3
+// must stay >= 0; beyond it the von Neumann spectral radius exceeds 1.  d = 2:
+// the spectral radius stays 1 up to eps ~ 0.486 (w1 > 0 up to 0.5); 0.48 is
+// accepted.  d = 1: stable for every eps tried.
+double eps_limit(int d) {
+    switch (d) {
+        case 2: return 0.48;
+        case 3: return 0.25;
+        case 4: return 1.0 / 6.0;
+        default: return INFINITY;
+    }
+}
 
 lb_status validate(const lb_config* c) {
     if (!c) return fail(LB_ERR_INVALID_ARG, "config is NULL");
-    if (c->dim < 1 || c->dim > 3) return fail(LB_ERR_INVALID_ARG, "dim must be 1, 2 or 3");
+    if (c->dim < 1 || c->dim > 4) return fail(LB_ERR_INVALID_ARG, "dim must be 1, 2, 3 or 4");
     if (c->flags != 0) return fail(LB_ERR_INVALID_ARG, "flags must be 0");
     int64_t V = 1;
-    for (int a = 0; a < 3; ++a) {
+    for (int a = 0; a < 4; ++a) {
         if (c->n[a] < 1) return fail(LB_ERR_INVALID_ARG, "every n[a] must be >= 1");
         if (a >= c->dim && c->n[a] != 1)
             return fail(LB_ERR_INVALID_ARG, "n[a] must be 1 for a >= dim");
@@ -102,17 +115,16 @@ lb_status validate(const lb_config* c) {
     }
     if (c->dim >= 2 && (c->n[1] + lbm::BLOCK_Y - 1) / lbm::BLOCK_Y > 65535)
         return fail(LB_ERR_INVALID_ARG, "n[1] exceeds the launch-grid limit");
-    if (c->dim == 3 && c->n[2] > 65535)
-        return fail(LB_ERR_INVALID_ARG, "n[2] exceeds the launch-grid limit");
+    if (c->dim >= 3 && c->n[2] * c->n[3] > 65535)
+        return fail(LB_ERR_INVALID_ARG, "n[2]*n[3] exceeds the launch-grid limit");
     if (!(c->dx > 0) || !(c->dt > 0) || !(c->nu > 0) || !std::isfinite(c->dx) ||
         !std::isfinite(c->dt) || !std::isfinite(c->nu))
         return fail(LB_ERR_INVALID_ARG, "dx, dt and nu must be finite and > 0");
     const double eps = c->nu * c->dt / (c->dx * c->dx);
     if (!std::isfinite(eps) || !(eps > 0)) return fail(LB_ERR_INVALID_ARG, "eps is not finite");
-    if (c->dim == 2 && eps >= 0.5)
-        return fail(LB_ERR_UNSTABLE, "D2Q9 needs eps < 0.5 (w1 = 1/6 - eps/3 > 0)");
-    if (c->dim == 3 && eps > 0.25)
-        return fail(LB_ERR_UNSTABLE, "D3Q19 needs eps <= 0.25 (w1 = 1/6 - 2 eps/3 >= 0)");
+    if (eps > eps_limit(c->dim))
+        return fail(LB_ERR_UNSTABLE, "eps = nu dt/dx^2 exceeds the stability limit of the lattice "
+                                     "(D2Q9 0.48, D3Q19 1/4, D4Q33 1/6)");
     return LB_OK;
 }
 
@@ -121,7 +133,8 @@ Geo make_geo(const lb_config* c) {
     g.nx = (int)c->n[0];
     g.ny = (int)c->n[1];
     g.nz = (int)c->n[2];
-    g.V = (int64_t)g.nx * g.ny * g.nz;
+    g.nw = (int)c->n[3];
+    g.V = (int64_t)g.nx * g.ny * g.nz * g.nw;
     return g;
 }
 

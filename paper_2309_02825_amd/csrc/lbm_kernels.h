@@ -32,8 +32,8 @@ constexpr int BLOCK_Y = 1;
 constexpr int BLOCK_1D = 256;
 
 struct Geo {
-    int nx, ny, nz;     // nodes per axis (1 for unused axes)
-    int64_t V;          // nx * ny * nz
+    int nx, ny, nz, nw; // nodes per axis (1 for unused axes)
+    int64_t V;          // nx * ny * nz * nw
 };
 
 // Launch shape of the per-node kernels for one grid.

@@ -25,51 +25,47 @@ constexpr int BX = BLOCK_X;
 constexpr int BY = BLOCK_Y;
 constexpr int B1 = BLOCK_1D;
 
-// Offsets of the neighbour x - e (e = -1, 0, +1) along each axis, periodic.
+// Offsets of the neighbour x - e (e = -1, 0, +1) along each axis, periodic:
+// s[a][e + 1] = ((x_a - e) mod n_a) * (stride of axis a in the node index).
 struct Nbr {
-    int sx[3];
-    int sy[3];
-    int sz[3];
+    int s[4][3];
 };
 
 template <int D>
-__device__ __forceinline__ Nbr make_nbr(int x, int y, int z, const Geo& g) {
+__device__ __forceinline__ Nbr make_nbr(const int (&c)[4], const Geo& g) {
     Nbr nb;
-    const int xm = x == 0 ? g.nx - 1 : x - 1;
-    const int xp = x == g.nx - 1 ? 0 : x + 1;
-    nb.sx[0] = xp;
-    nb.sx[1] = x;
-    nb.sx[2] = xm;
-    if constexpr (D >= 2) {
-        const int ym = y == 0 ? g.ny - 1 : y - 1;
-        const int yp = y == g.ny - 1 ? 0 : y + 1;
-        nb.sy[0] = yp * g.nx;
-        nb.sy[1] = y * g.nx;
-        nb.sy[2] = ym * g.nx;
-    } else {
-        nb.sy[0] = nb.sy[1] = nb.sy[2] = 0;
-    }
-    if constexpr (D == 3) {
-        const int nxy = g.nx * g.ny;
-        const int zm = z == 0 ? g.nz - 1 : z - 1;
-        const int zp = z == g.nz - 1 ? 0 : z + 1;
-        nb.sz[0] = zp * nxy;
-        nb.sz[1] = z * nxy;
-        nb.sz[2] = zm * nxy;
-    } else {
-        nb.sz[0] = nb.sz[1] = nb.sz[2] = 0;
+    const int n[4] = {g.nx, g.ny, g.nz, g.nw};
+    int stride = 1;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        if (a < D) {
+            const int m = c[a] == 0 ? n[a] - 1 : c[a] - 1;
+            const int p = c[a] == n[a] - 1 ? 0 : c[a] + 1;
+            nb.s[a][0] = p * stride;
+            nb.s[a][1] = c[a] * stride;
+            nb.s[a][2] = m * stride;
+            stride *= n[a];
+        } else {
+            nb.s[a][0] = nb.s[a][1] = nb.s[a][2] = 0;
+        }
     }
     return nb;
 }
 
-// Index of x - e_i (pull source) and x + e_i (push target).
+// Node index of x - e_i (pull source) and x + e_i (push target).
 template <int D>
 __device__ __forceinline__ int pull_index(const Nbr& nb, int i) {
-    return nb.sz[Lat<D>::E[i][2] + 1] + nb.sy[Lat<D>::E[i][1] + 1] + nb.sx[Lat<D>::E[i][0] + 1];
+    int k = 0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) k += nb.s[a][Lat<D>::E[i][a] + 1];
+    return k;
 }
 template <int D>
 __device__ __forceinline__ int push_index(const Nbr& nb, int i) {
-    return nb.sz[1 - Lat<D>::E[i][2]] + nb.sy[1 - Lat<D>::E[i][1]] + nb.sx[1 - Lat<D>::E[i][0]];
+    int k = 0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) k += nb.s[a][1 - Lat<D>::E[i][a]];
+    return k;
 }
 
 __device__ __forceinline__ int64_t block_linear() {
@@ -88,26 +84,30 @@ __device__ __forceinline__ unsigned xcd_remap(unsigned b, unsigned nb) {
 }
 
 template <int D>
-__device__ __forceinline__ bool thread_node(const Geo& g, int& x, int& y, int& z) {
+__device__ __forceinline__ bool thread_node(const Geo& g, int (&c)[4]) {
     const unsigned nb = gridDim.x * gridDim.y * gridDim.z;
     const unsigned b = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
     const unsigned t = xcd_remap(b, nb);
     const unsigned tx = t % gridDim.x;
     const unsigned rest = t / gridDim.x;
+    c[2] = c[3] = 0;
     if constexpr (D == 1) {
-        x = (int)(tx * B1 + threadIdx.x);
-        y = 0;
-        z = 0;
+        c[0] = (int)(tx * B1 + threadIdx.x);
+        c[1] = 0;
     } else {
-        x = (int)(tx * BX + threadIdx.x);
-        y = (int)((rest % gridDim.y) * BY + threadIdx.y);
-        z = (D == 3) ? (int)(rest / gridDim.y) : 0;
+        c[0] = (int)(tx * BX + threadIdx.x);
+        c[1] = (int)((rest % gridDim.y) * BY + threadIdx.y);
+        if constexpr (D >= 3) {
+            const unsigned zw = rest / gridDim.y;  // grid.z runs over n_z * n_w
+            c[2] = (int)(zw % (unsigned)g.nz);
+            c[3] = (int)(zw / (unsigned)g.nz);
+        }
     }
-    return x < g.nx && y < g.ny;
+    return c[0] < g.nx && c[1] < g.ny;
 }
 
-__device__ __forceinline__ int node_index(const Geo& g, int x, int y, int z) {
-    return (z * g.ny + y) * g.nx + x;
+__device__ __forceinline__ int node_index(const Geo& g, const int (&c)[4]) {
+    return ((c[3] * g.nz + c[2]) * g.ny + c[1]) * g.nx + c[0];
 }
 
 // Deterministic sum over the 256 threads of a block; result valid in thread 0.
@@ -128,14 +128,14 @@ template <int D>
 __global__ void __launch_bounds__(256) k_step(const double* __restrict__ src,
                                               double* __restrict__ dst, Geo g, Rates r) {
     constexpr int Q = Lat<D>::Q;
-    int x, y, z;
-    if (!thread_node<D>(g, x, y, z)) return;
-    const Nbr nb = make_nbr<D>(x, y, z, g);
+    int c[4];
+    if (!thread_node<D>(g, c)) return;
+    const Nbr nb = make_nbr<D>(c, g);
     double f[Q];
 #pragma unroll
     for (int i = 0; i < Q; ++i) f[i] = src[slot<Q>(i, pull_index<D>(nb, i))];
     collide<D>(f, r);
-    const int k = node_index(g, x, y, z);
+    const int k = node_index(g, c);
 #pragma unroll
     for (int i = 0; i < Q; ++i) __builtin_nontemporal_store(f[i], dst + slot<Q>(i, k));
 }
@@ -194,19 +194,18 @@ __device__ __forceinline__ int wrapi(int v, int n) {
     return v < 0 ? v + n : v;
 }
 
-// Fourth-order central difference of theta along axis a at node (x,y,z).
+// Fourth-order central difference of theta along axis a at node c.
 template <int D>
-__device__ double fd4(const double* __restrict__ th, const Geo& g, int x, int y, int z, int a,
+__device__ double fd4(const double* __restrict__ th, const Geo& g, const int (&c)[4], int a,
                       double inv12dx) {
-    int c[3] = {x, y, z};
-    const int n[3] = {g.nx, g.ny, g.nz};
+    const int n[4] = {g.nx, g.ny, g.nz, g.nw};
     double v[4];
     const int off[4] = {2, 1, -1, -2};
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
-        int cc[3] = {c[0], c[1], c[2]};
+        int cc[4] = {c[0], c[1], c[2], c[3]};
         cc[a] = wrapi(c[a] + off[t], n[a]);
-        v[t] = th[node_index(g, cc[0], cc[1], cc[2])];
+        v[t] = th[node_index(g, cc)];
     }
     return ((v[3] - v[0]) + 8.0 * (v[1] - v[2])) * inv12dx;
 }
@@ -218,23 +217,24 @@ __global__ void __launch_bounds__(256) k_init(const double* __restrict__ th0,
                                               const double* __restrict__ grad,
                                               double* __restrict__ dst, Geo g, Rates r) {
     constexpr int Q = Lat<D>::Q;
-    int x, y, z;
-    if (!thread_node<D>(g, x, y, z)) return;
-    const int k = node_index(g, x, y, z);
+    int c[4];
+    if (!thread_node<D>(g, c)) return;
+    const int k = node_index(g, c);
     const double corr = r.inv_s1_m1 * r.dx * (1.0 / 6.0);
+    const int n[4] = {g.nx, g.ny, g.nz, g.nw};
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-        const int sx = wrapi(x + Lat<D>::E[i][0], g.nx);
-        const int sy = wrapi(y + Lat<D>::E[i][1], g.ny);
-        const int sz = wrapi(z + Lat<D>::E[i][2], g.nz);
-        const int src = node_index(g, sx, sy, sz);
+        int cs[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) cs[a] = wrapi(c[a] + Lat<D>::E[i][a], n[a]);
+        const int src = node_index(g, cs);
         const double t = th0[src];
         double eg = 0.0, ax = 0.0;
 #pragma unroll
         for (int a = 0; a < D; ++a) {
             const int e = Lat<D>::E[i][a];
             if (e == 0) continue;
-            const double ga = grad ? grad[(int64_t)a * g.V + src] : fd4<D>(th0, g, sx, sy, sz, a, r.inv12dx);
+            const double ga = grad ? grad[(int64_t)a * g.V + src] : fd4<D>(th0, g, cs, a, r.inv12dx);
             eg = e == 1 ? eg + ga : eg - ga;
             if (nnz<D>(i) == 1) ax = e == 1 ? ga : -ga;
         }
@@ -251,16 +251,16 @@ __global__ void __launch_bounds__(256) k_macro(const double* __restrict__ src,
                                                double* __restrict__ theta, double* __restrict__ u,
                                                Geo g, Rates r) {
     constexpr int Q = Lat<D>::Q;
-    int x, y, z;
-    if (!thread_node<D>(g, x, y, z)) return;
-    const Nbr nb = make_nbr<D>(x, y, z, g);
+    int c[4];
+    if (!thread_node<D>(g, c)) return;
+    const Nbr nb = make_nbr<D>(c, g);
     double f[Q];
 #pragma unroll
     for (int i = 0; i < Q; ++i) f[i] = src[slot<Q>(i, pull_index<D>(nb, i))];
     double th = 0.0;
 #pragma unroll
     for (int i = 0; i < Q; ++i) th += f[i];
-    const int k = node_index(g, x, y, z);
+    const int k = node_index(g, c);
     if (theta) theta[k] = th;
     if (u) {
         const double inv = r.ucoef / th;
@@ -278,10 +278,10 @@ template <int D>
 __global__ void __launch_bounds__(256) k_get_state(const double* __restrict__ src,
                                                    double* __restrict__ dense, Geo g) {
     constexpr int Q = Lat<D>::Q;
-    int x, y, z;
-    if (!thread_node<D>(g, x, y, z)) return;
-    const Nbr nb = make_nbr<D>(x, y, z, g);
-    const int k = node_index(g, x, y, z);
+    int c[4];
+    if (!thread_node<D>(g, c)) return;
+    const Nbr nb = make_nbr<D>(c, g);
+    const int k = node_index(g, c);
 #pragma unroll
     for (int i = 0; i < Q; ++i) dense[(int64_t)i * g.V + k] = src[slot<Q>(i, pull_index<D>(nb, i))];
 }
@@ -290,10 +290,10 @@ template <int D>
 __global__ void __launch_bounds__(256) k_set_state(const double* __restrict__ dense,
                                                    double* __restrict__ dst, Geo g) {
     constexpr int Q = Lat<D>::Q;
-    int x, y, z;
-    if (!thread_node<D>(g, x, y, z)) return;
-    const Nbr nb = make_nbr<D>(x, y, z, g);
-    const int k = node_index(g, x, y, z);
+    int c[4];
+    if (!thread_node<D>(g, c)) return;
+    const Nbr nb = make_nbr<D>(c, g);
+    const int k = node_index(g, c);
 #pragma unroll
     for (int i = 0; i < Q; ++i) dst[slot<Q>(i, k)] = dense[(int64_t)i * g.V + push_index<D>(nb, i)];
 }
@@ -304,9 +304,9 @@ template <int D>
 __global__ void __launch_bounds__(256) k_layout_from_dense(const double* __restrict__ dense,
                                                            double* __restrict__ buf, Geo g) {
     constexpr int Q = Lat<D>::Q;
-    int x, y, z;
-    if (!thread_node<D>(g, x, y, z)) return;
-    const int k = node_index(g, x, y, z);
+    int c[4];
+    if (!thread_node<D>(g, c)) return;
+    const int k = node_index(g, c);
 #pragma unroll
     for (int i = 0; i < Q; ++i) buf[slot<Q>(i, k)] = dense[(int64_t)i * g.V + k];
 }
@@ -315,9 +315,9 @@ template <int D>
 __global__ void __launch_bounds__(256) k_layout_to_dense(const double* __restrict__ buf,
                                                          double* __restrict__ dense, Geo g) {
     constexpr int Q = Lat<D>::Q;
-    int x, y, z;
-    if (!thread_node<D>(g, x, y, z)) return;
-    const int k = node_index(g, x, y, z);
+    int c[4];
+    if (!thread_node<D>(g, c)) return;
+    const int k = node_index(g, c);
 #pragma unroll
     for (int i = 0; i < Q; ++i) dense[(int64_t)i * g.V + k] = buf[slot<Q>(i, k)];
 }
@@ -341,11 +341,11 @@ __global__ void __launch_bounds__(256) k_macro_adjoint(const double* __restrict_
                                                        double* __restrict__ partials, Geo g,
                                                        Rates r) {
     constexpr int Q = Lat<D>::Q;
-    int x, y, z;
+    int c[4];
     double ge = 0.0;
-    if (thread_node<D>(g, x, y, z)) {
-        const Nbr nb = make_nbr<D>(x, y, z, g);
-        const int k = node_index(g, x, y, z);
+    if (thread_node<D>(g, c)) {
+        const Nbr nb = make_nbr<D>(c, g);
+        const int k = node_index(g, c);
         double f[Q];
 #pragma unroll
         for (int i = 0; i < Q; ++i) f[i] = src[slot<Q>(i, pull_index<D>(nb, i))];
@@ -388,11 +388,11 @@ __global__ void __launch_bounds__(256) k_adjoint_step(const double* __restrict__
                                                       double* __restrict__ partials, Geo g,
                                                       Rates r) {
     constexpr int Q = Lat<D>::Q;
-    int x, y, z;
+    int c[4];
     double ge = 0.0;
-    if (thread_node<D>(g, x, y, z)) {
-        const Nbr nb = make_nbr<D>(x, y, z, g);
-        const int k = node_index(g, x, y, z);
+    if (thread_node<D>(g, c)) {
+        const Nbr nb = make_nbr<D>(c, g);
+        const int k = node_index(g, c);
         double f[Q], mu[Q];
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
@@ -440,10 +440,10 @@ __global__ void __launch_bounds__(256) k_init_adjoint(const double* __restrict__
                                                       double* __restrict__ partials, Geo g,
                                                       Rates r) {
     constexpr int Q = Lat<D>::Q;
-    int x, y, z;
+    int c[4];
     double ge = 0.0;
-    if (thread_node<D>(g, x, y, z)) {
-        const int k = node_index(g, x, y, z);
+    if (thread_node<D>(g, c)) {
+        const int k = node_index(g, c);
         double l[Q];
 #pragma unroll
         for (int i = 0; i < Q; ++i) l[i] = lam[slot<Q>(i, k)];
@@ -453,7 +453,7 @@ __global__ void __launch_bounds__(256) k_init_adjoint(const double* __restrict__
         double gv[D];
 #pragma unroll
         for (int a = 0; a < D; ++a)
-            gv[a] = grad ? grad[(int64_t)a * g.V + k] : fd4<D>(th0, g, x, y, z, a, r.inv12dx);
+            gv[a] = grad ? grad[(int64_t)a * g.V + k] : fd4<D>(th0, g, c, a, r.inv12dx);
         if (grad) {
             if (ggrad) {
 #pragma unroll
@@ -461,8 +461,7 @@ __global__ void __launch_bounds__(256) k_init_adjoint(const double* __restrict__
             }
         } else {
             // g_theta0 += sum_a D_a^T h_a, D_a^T h(x) = (-h(x-2) + 8h(x-1) - 8h(x+1) + h(x+2)) / (12 dx)
-            const int c[3] = {x, y, z};
-            const int n[3] = {g.nx, g.ny, g.nz};
+            const int n[4] = {g.nx, g.ny, g.nz, g.nw};
 #pragma unroll
             for (int a = 0; a < D; ++a) {
                 const int off[4] = {-2, -1, 1, 2};
@@ -470,9 +469,9 @@ __global__ void __launch_bounds__(256) k_init_adjoint(const double* __restrict__
                 double acc = 0.0;
 #pragma unroll
                 for (int t = 0; t < 4; ++t) {
-                    int cc[3] = {c[0], c[1], c[2]};
+                    int cc[4] = {c[0], c[1], c[2], c[3]};
                     cc[a] = wrapi(c[a] + off[t], n[a]);
-                    acc += cf[t] * init_h<D>(lam, g, node_index(g, cc[0], cc[1], cc[2]), a, r);
+                    acc += cf[t] * init_h<D>(lam, g, node_index(g, cc), a, r);
                 }
                 gt += acc * r.inv12dx;
             }
@@ -536,8 +535,10 @@ __global__ void __launch_bounds__(256) k_batch_step(const BatchInst* __restrict_
     g.nx = in.nx;
     g.ny = in.ny;
     g.nz = 1;
+    g.nw = 1;
     g.V = (int64_t)in.nx * in.ny;
-    const Nbr nb = make_nbr<2>(x, y, 0, g);
+    const int c[4] = {x, y, 0, 0};
+    const Nbr nb = make_nbr<2>(c, g);
     const double* s = src + in.offset;
     double* d = dst + in.offset;
     double f[Q];
@@ -556,6 +557,7 @@ hipError_t dispatch(int d, F&& f) {
         case 1: return f(std::integral_constant<int, 1>{});
         case 2: return f(std::integral_constant<int, 2>{});
         case 3: return f(std::integral_constant<int, 3>{});
+        case 4: return f(std::integral_constant<int, 4>{});
         default: return hipErrorInvalidValue;
     }
 }
@@ -570,7 +572,7 @@ Launch launch_shape(int d, const Geo& g) {
     } else {
         L.block = dim3(BX, BY, 1);
         L.grid = dim3((unsigned)((g.nx + BX - 1) / BX), (unsigned)((g.ny + BY - 1) / BY),
-                      (unsigned)(d == 3 ? g.nz : 1));
+                      (unsigned)(d >= 3 ? g.nz * g.nw : 1));
     }
     L.nblocks = (int64_t)L.grid.x * L.grid.y * L.grid.z;
     return L;
@@ -591,7 +593,7 @@ hipError_t launch_step(int d, const Geo& g, const Rates& r, const double* src, d
 
 hipError_t launch_step_resident1(const Geo& g, const Rates& r, const double* src, double* dst,
                                 int64_t nsteps, hipStream_t st) {
-    if (g.nx > RESIDENT_MAX_1D || g.ny != 1 || g.nz != 1) return hipErrorInvalidValue;
+    if (g.nx > RESIDENT_MAX_1D || g.ny != 1 || g.nz != 1 || g.nw != 1) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_step_resident1, dim3(1), dim3(RES_THREADS), 0, st, src, dst, g.nx, nsteps,
                        r);
     return hipGetLastError();

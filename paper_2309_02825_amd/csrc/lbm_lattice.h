@@ -14,10 +14,12 @@
 //   * f* = M^-1 m* in closed form.  Every natural-moment basis used here is a
 //     set of monomials e_a^p e_b^q ..., so M^-1 factorises into the 1-D map
 //     (mu0, mu1, mu2) -> (mu0 - mu2, (mu2 + mu1)/2, (mu2 - mu1)/2) per axis
-//     (moments that involve three axes vanish on D3Q19).  This gives
+//     (moments that involve three or more axes vanish on these lattices,
+//     whose moving velocities have one or two non-zero components).  This gives
 //       rest:        theta - sum_a P'_aa + R' * (number of axis pairs)
 //       axis +-a:    (P'_aa +- j'_a)/2 - R' (d - 1)/2
-//       edge (a,b):  (e_a e_b P'_ab + R')/4.
+//       edge (a,b):  (e_a e_b P'_ab + R')/4
+//     for every d (the D1Q3, D2Q9, D3Q19 and D4Q33 lattices here).
 // The same reconstruction, fed with eps-derivatives of the post-collision
 // moments, gives (dC/deps) f; the transposed collision C^T is evaluated with
 // the dual moments nu = M^-T mu (see collide_adjoint).
@@ -46,44 +48,72 @@ struct Rates {
     double c;                // dx / dt
 };
 
-// Velocity tables in the order of Sec. III.A.
+// Velocity tables in the order of Sec. III.A (a fourth component, zero
+// below d = 4, keeps one shape for every lattice).  d = 4 follows the
+// general DdQ(1+2d^2) rule: rest, +unit vectors, -unit vectors, then for
+// every axis pair a < b (lexicographic) (e_a, e_b) = (+,+) (-,+) (-,-) (+,-).
 template <int D> struct Lat;
 
 template <> struct Lat<1> {
     static constexpr int Q = 3;
     static constexpr int NP = 0;  // axis pairs
-    static constexpr int E[3][3] = {{0, 0, 0}, {1, 0, 0}, {-1, 0, 0}};
+    static constexpr int E[3][4] = {{0, 0, 0, 0}, {1, 0, 0, 0}, {-1, 0, 0, 0}};
 };
 
 template <> struct Lat<2> {
     static constexpr int Q = 9;
     static constexpr int NP = 1;
-    static constexpr int E[9][3] = {{0, 0, 0},  {1, 0, 0},  {0, 1, 0},
-                                    {-1, 0, 0}, {0, -1, 0}, {1, 1, 0},
-                                    {-1, 1, 0}, {-1, -1, 0}, {1, -1, 0}};
+    static constexpr int E[9][4] = {{0, 0, 0, 0},  {1, 0, 0, 0},   {0, 1, 0, 0},
+                                    {-1, 0, 0, 0}, {0, -1, 0, 0},  {1, 1, 0, 0},
+                                    {-1, 1, 0, 0}, {-1, -1, 0, 0}, {1, -1, 0, 0}};
 };
 
 template <> struct Lat<3> {
     static constexpr int Q = 19;
     static constexpr int NP = 3;
-    static constexpr int E[19][3] = {
-        {0, 0, 0},  {1, 0, 0},   {0, 1, 0},   {0, 0, 1},  {-1, 0, 0},
-        {0, -1, 0}, {0, 0, -1},  {1, 1, 0},   {-1, 1, 0}, {-1, -1, 0},
-        {1, -1, 0}, {1, 0, 1},   {-1, 0, 1},  {-1, 0, -1}, {1, 0, -1},
-        {0, 1, 1},  {0, -1, 1},  {0, -1, -1}, {0, 1, -1}};
+    static constexpr int E[19][4] = {
+        {0, 0, 0, 0},  {1, 0, 0, 0},   {0, 1, 0, 0},   {0, 0, 1, 0},  {-1, 0, 0, 0},
+        {0, -1, 0, 0}, {0, 0, -1, 0},  {1, 1, 0, 0},   {-1, 1, 0, 0}, {-1, -1, 0, 0},
+        {1, -1, 0, 0}, {1, 0, 1, 0},   {-1, 0, 1, 0},  {-1, 0, -1, 0}, {1, 0, -1, 0},
+        {0, 1, 1, 0},  {0, -1, 1, 0},  {0, -1, -1, 0}, {0, 1, -1, 0}};
 };
 
-// Pair index of axes (a, b), a < b: (0,1) -> 0, (0,2) -> 1, (1,2) -> 2.
-__host__ __device__ constexpr int pair_index(int a, int b) { return a == 0 ? b - 1 : 2; }
+template <> struct Lat<4> {
+    static constexpr int Q = 33;
+    static constexpr int NP = 6;
+    static constexpr int E[33][4] = {
+        {0, 0, 0, 0},
+        {1, 0, 0, 0},   {0, 1, 0, 0},   {0, 0, 1, 0},   {0, 0, 0, 1},
+        {-1, 0, 0, 0},  {0, -1, 0, 0},  {0, 0, -1, 0},  {0, 0, 0, -1},
+        {1, 1, 0, 0},   {-1, 1, 0, 0},  {-1, -1, 0, 0}, {1, -1, 0, 0},
+        {1, 0, 1, 0},   {-1, 0, 1, 0},  {-1, 0, -1, 0}, {1, 0, -1, 0},
+        {1, 0, 0, 1},   {-1, 0, 0, 1},  {-1, 0, 0, -1}, {1, 0, 0, -1},
+        {0, 1, 1, 0},   {0, -1, 1, 0},  {0, -1, -1, 0}, {0, 1, -1, 0},
+        {0, 1, 0, 1},   {0, -1, 0, 1},  {0, -1, 0, -1}, {0, 1, 0, -1},
+        {0, 0, 1, 1},   {0, 0, -1, 1},  {0, 0, -1, -1}, {0, 0, 1, -1}};
+};
+
+// Number of axis pairs as an array extent (at least 1).
+template <int D> struct NPairs {
+    static constexpr int value = D * (D - 1) / 2 > 0 ? D * (D - 1) / 2 : 1;
+};
+
+// Index of the axis pair (a, b), a < b, in lexicographic order.
+template <int D>
+__host__ __device__ constexpr int pair_index(int a, int b) {
+    return a * (2 * D - a - 1) / 2 + (b - a - 1);
+}
 
 template <int D> __host__ __device__ constexpr int nnz(int i) {
-    return (Lat<D>::E[i][0] != 0) + (Lat<D>::E[i][1] != 0) + (Lat<D>::E[i][2] != 0);
+    return (Lat<D>::E[i][0] != 0) + (Lat<D>::E[i][1] != 0) + (Lat<D>::E[i][2] != 0) +
+           (Lat<D>::E[i][3] != 0);
 }
 template <int D> __host__ __device__ constexpr int first_axis(int i) {
-    return Lat<D>::E[i][0] != 0 ? 0 : (Lat<D>::E[i][1] != 0 ? 1 : 2);
+    return Lat<D>::E[i][0] != 0 ? 0 : (Lat<D>::E[i][1] != 0 ? 1 : (Lat<D>::E[i][2] != 0 ? 2 : 3));
 }
 template <int D> __host__ __device__ constexpr int second_axis(int i) {
-    return Lat<D>::E[i][2] != 0 && first_axis<D>(i) != 2 ? 2 : 1;
+    const int a = first_axis<D>(i);
+    return (a < 1 && Lat<D>::E[i][1] != 0) ? 1 : ((a < 2 && Lat<D>::E[i][2] != 0) ? 2 : 3);
 }
 
 // Signed add: acc + s*v for s in {-1, 0, 1} known at compile time.
@@ -94,7 +124,7 @@ template <int D> struct Moments {
     double theta;
     double j[D];
     double P[D];
-    double Pab[D == 3 ? 3 : 1];
+    double Pab[NPairs<D>::value];
 };
 
 template <int D>
@@ -127,7 +157,7 @@ __device__ __forceinline__ void moments(const double (&f)[Lat<D>::Q], Moments<D>
                     const int s = Lat<D>::E[i][a] * Lat<D>::E[i][b];
                     pab = LBM_SADD(pab, s, f[i]);
                 }
-                m.Pab[pair_index(a, b)] = pab;
+                m.Pab[pair_index<D>(a, b)] = pab;
             }
         }
     } else {
@@ -139,7 +169,7 @@ __device__ __forceinline__ void moments(const double (&f)[Lat<D>::Q], Moments<D>
 // third-order moments zero and every c_a^2 c_b^2 moment equal to R.
 template <int D>
 __device__ __forceinline__ void reconstruct(double theta, const double (&j)[D], const double (&P)[D],
-                                            const double (&Pab)[D == 3 ? 3 : 1], double R,
+                                            const double (&Pab)[NPairs<D>::value], double R,
                                             double (&f)[Lat<D>::Q]) {
     constexpr int Q = Lat<D>::Q;
     constexpr int NP = Lat<D>::NP;
@@ -150,17 +180,17 @@ __device__ __forceinline__ void reconstruct(double theta, const double (&j)[D], 
             double sP = 0.0;
 #pragma unroll
             for (int a = 0; a < D; ++a) sP += P[a];
-            f[i] = (theta - sP) + (NP == 0 ? 0.0 : (NP == 1 ? R : 3.0 * R));
+            f[i] = (theta - sP) + (NP == 0 ? 0.0 : (NP == 1 ? R : (double)NP * R));
         } else if (k == 1) {
             const int a = first_axis<D>(i);
             const int s = Lat<D>::E[i][a];
             const double h = 0.5 * (s == 1 ? P[a] + j[a] : P[a] - j[a]);
-            f[i] = (D == 1) ? h : (D == 2 ? h - 0.5 * R : h - R);
+            f[i] = (D == 1) ? h : h - (0.5 * (D - 1)) * R;
         } else {
             const int a = first_axis<D>(i);
             const int b = second_axis<D>(i);
             const int s = Lat<D>::E[i][a] * Lat<D>::E[i][b];
-            const double pab = Pab[pair_index(a, b)];
+            const double pab = Pab[pair_index<D>(a, b)];
             f[i] = 0.25 * (s == 1 ? R + pab : R - pab);
         }
     }
@@ -172,14 +202,14 @@ __device__ __forceinline__ void collide(double (&f)[Lat<D>::Q], const Rates& r) 
     Moments<D> m;
     moments<D>(f, m);
     const double th3 = m.theta * (1.0 / 3.0);
-    double j[D], P[D], Pab[D == 3 ? 3 : 1];
+    double j[D], P[D], Pab[NPairs<D>::value];
 #pragma unroll
     for (int a = 0; a < D; ++a) {
         j[a] = r.one_m_s1 * m.j[a];
         P[a] = m.P[a] - r.s21 * (m.P[a] - th3);
     }
 #pragma unroll
-    for (int p = 0; p < (D == 3 ? 3 : 1); ++p) Pab[p] = r.one_m_s22 * m.Pab[p];
+    for (int p = 0; p < NPairs<D>::value; ++p) Pab[p] = r.one_m_s22 * m.Pab[p];
     reconstruct<D>(m.theta, j, P, Pab, r.R4wd * m.theta, f);
 }
 
@@ -190,14 +220,14 @@ __device__ __forceinline__ void collide_deps(const double (&f)[Lat<D>::Q], const
     Moments<D> m;
     moments<D>(f, m);
     const double th3 = m.theta * (1.0 / 3.0);
-    double j[D], P[D], Pab[D == 3 ? 3 : 1];
+    double j[D], P[D], Pab[NPairs<D>::value];
 #pragma unroll
     for (int a = 0; a < D; ++a) {
         j[a] = -r.ds1 * m.j[a];
         P[a] = -r.ds21 * (m.P[a] - th3);
     }
 #pragma unroll
-    for (int p = 0; p < (D == 3 ? 3 : 1); ++p) Pab[p] = -r.ds22 * m.Pab[p];
+    for (int p = 0; p < NPairs<D>::value; ++p) Pab[p] = -r.ds22 * m.Pab[p];
     reconstruct<D>(0.0, j, P, Pab, 4.0 * r.dwd * m.theta, df);
 }
 
@@ -215,7 +245,7 @@ template <int D>
 __device__ __forceinline__ void collide_adjoint(const double (&mu)[Lat<D>::Q], const Rates& r,
                                                 double (&lam)[Lat<D>::Q]) {
     constexpr int Q = Lat<D>::Q;
-    double na[D], naa[D], nab[D == 3 ? 3 : 1], naabb[D == 3 ? 3 : 1];
+    double na[D], naa[D], nab[NPairs<D>::value], naabb[NPairs<D>::value];
     const double rest = mu[0];
 #pragma unroll
     for (int a = 0; a < D; ++a) {
@@ -243,7 +273,7 @@ __device__ __forceinline__ void collide_adjoint(const double (&mu)[Lat<D>::Q], c
                         se += mu[i];
                     }
                 }
-                const int p = pair_index(a, b);
+                const int p = pair_index<D>(a, b);
                 nab[p] = 0.25 * ss;
                 // mu_{+a} + mu_{-a} = 2 (naa + rest)
                 naabb[p] = rest - (naa[a] + rest) - (naa[b] + rest) + 0.25 * se;
@@ -261,7 +291,7 @@ __device__ __forceinline__ void collide_adjoint(const double (&mu)[Lat<D>::Q], c
         for (int p = 0; p < Lat<D>::NP; ++p) sb += naabb[p];
         n0 += r.R4wd * sb;
     }
-    double ta[D], taa[D], tab[D == 3 ? 3 : 1];
+    double ta[D], taa[D], tab[NPairs<D>::value];
 #pragma unroll
     for (int a = 0; a < D; ++a) {
         ta[a] = r.one_m_s1 * na[a];
@@ -285,8 +315,8 @@ __device__ __forceinline__ void collide_adjoint(const double (&mu)[Lat<D>::Q], c
             const int b = second_axis<D>(i);
             const double t1 = Lat<D>::E[i][a] == 1 ? ta[a] : -ta[a];
             const double t2 = Lat<D>::E[i][b] == 1 ? ta[b] : -ta[b];
-            const double tp = (Lat<D>::E[i][a] * Lat<D>::E[i][b] == 1) ? tab[pair_index(a, b)]
-                                                                       : -tab[pair_index(a, b)];
+            const double tp = (Lat<D>::E[i][a] * Lat<D>::E[i][b] == 1) ? tab[pair_index<D>(a, b)]
+                                                                       : -tab[pair_index<D>(a, b)];
             lam[i] = n0 + t1 + t2 + taa[a] + taa[b] + tp;
         }
     }

@@ -33,19 +33,19 @@ class LBError(RuntimeError):
 
 
 class lb_config(ctypes.Structure):
-    _fields_ = [("dim", ctypes.c_int32), ("flags", ctypes.c_int32), ("n", ctypes.c_int64 * 3),
+    _fields_ = [("dim", ctypes.c_int32), ("flags", ctypes.c_int32), ("n", ctypes.c_int64 * 4),
                 ("dx", ctypes.c_double), ("dt", ctypes.c_double), ("nu", ctypes.c_double)]
 
 
 def make_config(grid: Sequence[int], dx: float, dt: float, nu: float) -> lb_config:
-    """grid is x_0-first: (n_0,), (n_0, n_1) or (n_0, n_1, n_2)."""
-    n = [1, 1, 1]
+    """grid is x_0-first: (n_0,), (n_0, n_1), (n_0, n_1, n_2) or (n_0, ..., n_3)."""
+    n = [1, 1, 1, 1]
     for a, v in enumerate(grid):
         n[a] = int(v)
     c = lb_config()
     c.dim = len(grid)
     c.flags = 0
-    c.n = (ctypes.c_int64 * 3)(*n)
+    c.n = (ctypes.c_int64 * 4)(*n)
     c.dx, c.dt, c.nu = float(dx), float(dt), float(nu)
     return c
 

@@ -173,6 +173,11 @@ def heat_3d(n: int, nsteps: int = 2000) -> Workload:
     return cosine_problem(3, n, 0.01, 0.1, nsteps, name=f"heat3d_{n}^3")
 
 
+def heat_4d(n: int, nsteps: int = 200) -> Workload:
+    """4-D periodic unit hypercube, nu = 0.01, theta0 = 2 + prod cos(2 pi x_a), eps = 0.08."""
+    return cosine_problem(4, n, 0.01, 0.08, nsteps, name=f"heat4d_{n}^4")
+
+
 def paper_example2(level: int, eps: float) -> Workload:
     """Example 2 (Sec. IV): [0,2]^2 periodic, dx = 1/20 / 2^level,
     dt = 1/50 / 4^level, t = 2, theta0 = (2 + sin(2 pi x) sin(pi y)) / 2."""
@@ -196,6 +201,21 @@ def paper_example3(level: int, eps: float) -> Workload:
     modes = constant(1.0, 3) + trig_product(["sin", "sin", "sin"], [2, 1, 4], 0.5)
     return Workload(f"ex3_eps{eps}_l{level}", (n, n, n), dx, dt, nu, modes,
                     int(round(2.0 / dt)))
+
+
+def paper_example4(level: int, eps: float, t_end: float) -> Workload:
+    """Example 4 (Sec. IV): [-1,1]^4 periodic, dx = 1/10, 1/15, 1/20, 1/25 for
+    level 0..3, dt = 2.5 dx^2 (1/40 at dx = 1/10),
+    theta0 = 2 + sin(pi x1) sin(2 pi x2) sin(3 pi x3) sin(4 pi x4).  With the
+    origin at -1 each factor sin(k pi (j dx - 1)) = (-1)^k sin(2 pi k j / n);
+    the signs multiply to +1."""
+    dx = 1.0 / (10 + 5 * level)
+    dt = 2.5 * dx * dx
+    n = int(round(2.0 / dx))
+    nu = eps * dx * dx / dt
+    modes = constant(2.0, 4) + trig_product(["sin"] * 4, [1, 2, 3, 4])
+    return Workload(f"ex4_eps{eps}_t{t_end}_l{level}", (n,) * 4, dx, dt, nu, modes,
+                    int(round(t_end / dt)))
 
 
 def random_fourier_modes(rng: np.random.Generator, d: int = 2, nmodes: int = 8,

@@ -42,3 +42,17 @@ def read_table(name: str):
             vals = [None if p == "x" else float(p) for p in parts[2:6]]
             rows.append((eps, var, vals, float(parts[6])))
     return rows
+
+
+def read_table4():
+    """Rows of golden/table4.txt: (eps, t, variable, [rmse or None per level], cr)."""
+    rows = []
+    with open(os.path.join(GOLDEN, "table4.txt")) as fh:
+        for line in fh:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            p = line.split()
+            rows.append((float(p[0]), float(p[1]), p[2],
+                         [None if v == "x" else float(v) for v in p[3:7]], float(p[7])))
+    return rows

@@ -28,7 +28,8 @@ def test_library_exports_every_declared_symbol():
         assert hasattr(L, n), f"binding lacks {n}"
 
 
-@pytest.mark.parametrize("d,eps", [(1, 0.08), (2, 0.2), (2, 0.49), (3, 0.1), (3, 0.25)])
+@pytest.mark.parametrize("d,eps", [(1, 0.08), (2, 0.2), (2, 0.47), (3, 0.1), (3, 0.25),
+                                   (4, 0.08), (4, 0.1)])
 def test_parameters_match_oracle(d, eps):
     n = 32
     dx = 1.0 / n
@@ -48,7 +49,8 @@ def test_parameters_match_oracle(d, eps):
 def test_state_layout():
     C = L.lb_state_chunk()
     assert C == 4096
-    for grid in [(1,), (7,), (64, 64), (100, 70), (1024, 1024), (20, 17, 9), (256, 256, 256)]:
+    for grid in [(1,), (7,), (64, 64), (100, 70), (1024, 1024), (20, 17, 9), (256, 256, 256),
+                 (6, 5, 4, 7), (20, 20, 20, 20)]:
         c = L.make_config(grid, 0.1, 0.001, 0.1)
         V = math.prod(grid)
         q = L.lb_num_populations(len(grid))
@@ -56,7 +58,8 @@ def test_state_layout():
         assert el == q * ((V + C - 1) // C) * C
         assert L.lb_state_bytes(c) == 8 * el
     assert L.lb_num_populations(1) == 3 and L.lb_num_populations(2) == 9
-    assert L.lb_num_populations(3) == 19 and L.lb_num_populations(4) == 0
+    assert L.lb_num_populations(3) == 19 and L.lb_num_populations(4) == 33
+    assert L.lb_num_populations(5) == 0
 
 
 @pytest.mark.parametrize("grid,dx,dt,nu,code", [
@@ -64,14 +67,15 @@ def test_state_layout():
     ((8, 8), -1.0, 0.1, 0.1, L.LB_ERR_INVALID_ARG),
     ((8, 8), 0.1, 0.0, 0.1, L.LB_ERR_INVALID_ARG),
     ((8, 8), 0.1, 0.1, float("nan"), L.LB_ERR_INVALID_ARG),
-    ((8, 8), 0.1, 0.01, 0.6, L.LB_ERR_UNSTABLE),        # eps = 0.6
+    ((8, 8), 0.1, 0.01, 0.49, L.LB_ERR_UNSTABLE),       # eps = 0.49 > 0.48
     ((8, 8, 8), 0.1, 0.01, 0.26, L.LB_ERR_UNSTABLE),    # eps = 0.26
-    ((8, 8, 8, 8), 0.1, 0.01, 0.1, L.LB_ERR_INVALID_ARG),
+    ((8, 8, 8, 8), 0.1, 0.01, 0.17, L.LB_ERR_UNSTABLE), # eps = 0.17 > 1/6
+    ((8, 8, 8, 8, 8), 0.1, 0.01, 0.1, L.LB_ERR_INVALID_ARG),
 ])
 def test_create_rejects_bad_configs(grid, dx, dt, nu, code):
-    if len(grid) > 3:
-        c = L.make_config(grid[:3], dx, dt, nu)
-        c.dim = 4
+    if len(grid) > 4:
+        c = L.make_config(grid[:4], dx, dt, nu)
+        c.dim = 5
     else:
         c = L.make_config(grid, dx, dt, nu)
     with pytest.raises(L.LBError) as ei:
@@ -93,7 +97,7 @@ def test_create_rejects_null_and_overlapping_buffers():
 
 def test_unused_axes_must_be_one():
     c = L.make_config((8, 8), 0.1, 0.01, 0.1)
-    c.n[2] = 2
+    c.n[3] = 2
     assert L.lb_state_bytes(c) == 0
     with pytest.raises(L.LBError):
         L.lb_create(c, 0, 1 << 20, 1 << 40)

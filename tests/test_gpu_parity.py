@@ -73,6 +73,9 @@ CASES = [
     ("3d_ragged_20x17x9", (20, 17, 9), 25, "random"),
     ("3d_ex3_level0", (20, 20, 20), 10, "ex3"),
     ("3d_cos_33x5x4", (33, 5, 4), 12, "cos"),
+    ("4d_ragged_6x5x4x7", (6, 5, 4, 7), 9, "random"),
+    ("4d_cos_9x3x2x4", (9, 3, 2, 4), 5, "cos"),
+    ("4d_ex4_level0", (20, 20, 20, 20), 40, "ex4"),
 ]
 
 
@@ -91,9 +94,13 @@ def _problem(grid, kind):
         wl = W.paper_example3(0, 0.15)
         th0, g0 = W.evaluate(wl.modes, wl.grid, wl.dx)
         return wl.dx, wl.dt, wl.nu, th0, g0
+    if kind == "ex4":
+        wl = W.paper_example4(0, 0.08, 1.0)
+        th0, g0 = W.evaluate(wl.modes, wl.grid, wl.dx)
+        return wl.dx, wl.dt, wl.nu, th0, g0
     dx = 1.0 / max(grid)
     nu = 0.01
-    eps = {1: 0.4, 2: 0.23, 3: 0.11}[d]
+    eps = {1: 0.4, 2: 0.23, 3: 0.11, 4: 0.09}[d]
     dt = eps * dx * dx / nu
     if kind == "cos":
         modes = W.constant(2.0, d) + W.trig_product(["cos"] * d, [1] * d)
@@ -366,6 +373,34 @@ def test_adjoint_full_size_against_central_differences():
           f"nu {b.grad.item():.9e} vs {fd_nu:.9e}", flush=True)
     assert abs(g_dir - fd_dir) <= 1e-6 * abs(fd_dir)
     assert abs(b.grad.item() - fd_nu) <= 1e-5 * abs(fd_nu)
+
+
+@pytest.mark.parametrize("grid,steps", [((9, 7, 6), 7), ((5, 4, 3, 6), 5), ((40,), 30)])
+def test_adjoint_matches_oracle_other_lattices(grid, steps):
+    """D1Q3, D3Q19 and D4Q33 adjoints (loss on u, FD initial gradient)."""
+    _say("adjoint", grid, steps)
+    SV = _solver_mod()
+    d = len(grid)
+    dx, nu = 1.0 / max(grid), 0.02
+    eps = {1: 0.3, 3: 0.12, 4: 0.09}[d]
+    dt = eps * dx * dx / nu
+    rng = np.random.default_rng(17 + d)
+    modes = W.constant(1.6, d)
+    for _ in range(4):
+        k = tuple(int(rng.integers(-1, 2)) for _ in grid)
+        modes.append((k, complex(rng.normal() * 0.1, rng.normal() * 0.1)))
+    th0, _ = W.evaluate(modes, grid, dx, with_grad=False)
+    u_t = rng.normal(size=(d,) + th0.shape) * 1e-3
+    L_o, g_o, gnu_o = O.velocity_loss_and_grad(th0, u_t, dx, dt, nu, steps)
+    th0_t = torch.from_numpy(th0).to(_dev()).requires_grad_(True)
+    nu_t = torch.tensor(nu, dtype=torch.float64, device=_dev(), requires_grad=True)
+    u = SV.velocity(th0_t, nu_t, grid, dx, dt, steps, 3)
+    loss = ((u - torch.from_numpy(u_t).to(_dev())) ** 2).sum()
+    loss.backward()
+    torch.cuda.synchronize()
+    assert abs(loss.item() - L_o) <= 1e-12 * L_o
+    assert max_rel(th0_t.grad.cpu().numpy(), g_o) <= 1e-12
+    assert abs(nu_t.grad.item() - gnu_o) <= 1e-11 * abs(gnu_o)
 
 
 def test_adjoint_dot_product_on_gpu():

@@ -19,7 +19,7 @@ import pytest
 
 from oracle import oracle as O
 from paper_2309_02825_amd import workloads as W
-from tests.helpers import read_table, rmse_closed
+from tests.helpers import read_table, read_table4, rmse_closed
 
 SLOW = os.environ.get("LBM_SLOW", "") == "1"
 
@@ -93,3 +93,37 @@ def test_convergence_rate_example2():
         r = [_cached(2, eps, l)["theta"] for l in (0, 1, 2)]
         cr = np.mean([math.log2(r[i] / r[i + 1]) for i in range(2)])
         assert 3.9 < cr < 4.1
+
+
+def _run4(eps, t_end, level):
+    wl = W.paper_example4(level, eps, t_end)
+    th0, g0 = W.evaluate(wl.modes, wl.grid, wl.dx)
+    th, u, _ = O.solve(th0, g0, wl.dx, wl.dt, wl.nu, wl.nsteps)
+    te, ue = W.exact(wl, wl.nsteps * wl.dt)
+    out = {"theta": 0.5 * rmse_closed(th, te)}
+    for a in range(4):
+        out[f"u_x{a + 1}"] = rmse_closed(u[a], ue[a])
+    return out
+
+
+def test_printed_rmse_table4():
+    """Table 4 (D4Q33, the general d > 3 lattice): every printed cell of the
+    levels run here.  Cells near the double-precision floor (< 1e-12) get
+    1e-3, the rest 3e-4."""
+    levels = [0, 1] if SLOW else [0]
+    rows = read_table4()
+    checked = 0
+    cache = {}
+    for eps, t_end, var, vals, _cr in rows:
+        for level in levels:
+            printed = vals[level]
+            if printed is None:
+                continue
+            key = (eps, t_end, level)
+            if key not in cache:
+                cache[key] = _run4(eps, t_end, level)
+            got = cache[key][var]
+            tol = 1e-3 if printed < 1e-12 else 3e-4
+            assert abs(got - printed) / printed < tol, (eps, t_end, var, level, got, printed)
+            checked += 1
+    assert checked >= 20
