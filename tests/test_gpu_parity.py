@@ -74,8 +74,8 @@ CASES = [
     ("3d_ex3_level0", (20, 20, 20), 10, "ex3"),
     ("3d_cos_33x5x4", (33, 5, 4), 12, "cos"),
     ("4d_ragged_6x5x4x7", (6, 5, 4, 7), 9, "random"),
-    ("4d_cos_9x3x2x4", (9, 3, 2, 4), 5, "cos"),
-    ("4d_ex4_level0", (20, 20, 20, 20), 40, "ex4"),
+    ("4d_cos_9x5x6x5", (9, 5, 6, 5), 5, "cos"),
+    ("4d_ex4_level0", (20, 20, 20, 20), 8, "ex4"),
 ]
 
 
