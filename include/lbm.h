@@ -119,6 +119,20 @@ lb_status lb_create(const lb_config* cfg, void* hip_stream, double* f_a, double*
 lb_status lb_init(lb_solver* s, const double* theta0, const double* grad_theta0,
                   int32_t check_theta);
 
+/* Burgers front end: theta0 (V) and, if grad != NULL, grad theta0 (d x V)
+ * from the initial velocity u0 (d x V) of the coupled Burgers equations, by
+ * the inverse of the Cole-Hopf transformation u = -2 nu grad(theta)/theta
+ * (Sec. II): theta0 = exp(-phi/(2 nu)) with grad(phi) = u0 and phi = 0 at the
+ * origin, so theta0(origin) = 1 (theta is defined up to a constant factor,
+ * which does not change u).  phi is integrated along x_0 at x_1 = .. = 0, then
+ * along x_1 at x_2 = .. = 0, and so on, each cell with the four-node cubic
+ * rule dx (-u_{j-1} + 13 u_j + 13 u_{j+1} - u_{j+2})/24 (fourth order);
+ * grad theta0 = -u0 theta0/(2 nu) exactly.  u0 must be a periodic gradient
+ * field (the potential symmetry of Sec. II) whose line integrals over a
+ * period vanish; otherwise theta0 is not periodic.  Allocates and frees a
+ * workspace of about V doubles and synchronises the stream. */
+lb_status lb_theta_from_velocity(lb_solver* s, const double* u0, double* theta0, double* grad);
+
 /* Advance nsteps >= 0 time steps (evolution equation of Sec. III.A: collide in
  * moment space, then stream), alternating the two buffers. */
 lb_status lb_step(lb_solver* s, int64_t nsteps);

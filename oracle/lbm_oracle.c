@@ -704,3 +704,43 @@ int oracle_init_adjoint(int d, const int64_t* n, double dx, double dt, double nu
     if (g_eps) *g_eps += ge;
     return 0;
 }
+
+/* Inverse Cole-Hopf transformation (Sec. II, u = -2 nu grad(theta)/theta):
+ * theta0 = exp(-phi/(2 nu)) with grad(phi) = u0, phi = 0 at the origin.
+ * phi at node c is the line integral along x_0 (at x_1 = .. = 0) from 0 to
+ * c_0, then along x_1 (at x_2 = .. = 0) from 0 to c_1, and so on; each cell
+ * [x_j, x_j+1] uses the integral of the cubic through the four nodes
+ * j-1..j+2 (periodic):  dx (-u_{j-1} + 13 u_j + 13 u_{j+1} - u_{j+2}) / 24.
+ * grad theta0 = -u0 theta0 / (2 nu).  u0 is d x V; grad may be NULL. */
+int oracle_theta_from_velocity(int d, const int64_t* n, double dx, double nu, const double* u0,
+                               double* theta0, double* grad) {
+    or_grid G;
+    if (make_grid(d, n, &G) != 0 || !(dx > 0) || !(nu > 0)) return -1;
+    const int64_t V = G.V;
+    for (int64_t k = 0; k < V; ++k) {
+        int64_t c[OR_MAXD] = {0, 0, 0, 0}, rem = k;
+        for (int a = 0; a < d; ++a) { c[a] = rem % G.n[a]; rem /= G.n[a]; }
+        double phi = 0.0;
+        for (int a = 0; a < d; ++a) {
+            for (int64_t j = 0; j < c[a]; ++j) {
+                double uu[4];
+                for (int t = 0; t < 4; ++t) {
+                    int64_t p[OR_MAXD] = {0, 0, 0, 0};
+                    for (int b = 0; b < a; ++b) p[b] = c[b];
+                    int64_t jj = (j - 1 + t) % G.n[a];
+                    if (jj < 0) jj += G.n[a];
+                    p[a] = jj;
+                    int64_t idx = 0, stride = 1;
+                    for (int b = 0; b < d; ++b) { idx += p[b] * stride; stride *= G.n[b]; }
+                    uu[t] = u0[a * V + idx];
+                }
+                phi += dx * ((13.0 * (uu[1] + uu[2]) - (uu[0] + uu[3])) / 24.0);
+            }
+        }
+        const double th = exp(-phi / (2.0 * nu));
+        theta0[k] = th;
+        if (grad)
+            for (int a = 0; a < d; ++a) grad[a * V + k] = -u0[a * V + k] * th / (2.0 * nu);
+    }
+    return 0;
+}

@@ -49,6 +49,7 @@ def _load():
         "oracle_macro_adjoint": ([I, _i64p, D, D, D, _dp, _dp, _dp, _dp, _dp], I),
         "oracle_adjoint_run": ([I, _i64p, D, D, D, _dp, I64, _dp, _dp], I),
         "oracle_init_adjoint": ([I, _i64p, D, D, D, _dp, _dp, _dp, _dp, _dp, _dp], I),
+        "oracle_theta_from_velocity": ([I, _i64p, D, D, _dp, _dp, _dp], I),
     }
     for name, (args, res) in sigs.items():
         fn = getattr(lib, name)
@@ -227,6 +228,18 @@ def init_adjoint(theta0, grad, lam0, dx, dt, nu):
     _check(_load().oracle_init_adjoint(d, n, dx, dt, nu, _ptr(theta0), _ptr(grad), _ptr(lam0),
                                        _ptr(gt), _ptr(gg), ctypes.byref(ge)), "init_adjoint")
     return gt, gg, ge.value
+
+
+def theta_from_velocity(u0: np.ndarray, dx: float, nu: float):
+    """Inverse Cole-Hopf: (theta0, grad theta0) from u0 of shape (d, *grid)."""
+    u0 = np.ascontiguousarray(u0, dtype=np.float64)
+    shape = u0.shape[1:]
+    d, n = _dims(shape)
+    th = np.zeros(shape)
+    g = np.zeros((d,) + shape)
+    _check(_load().oracle_theta_from_velocity(d, n, dx, nu, _ptr(u0), _ptr(th), _ptr(g)),
+           "theta_from_velocity")
+    return th, g
 
 
 def velocity_loss_and_grad(theta0, u_target, dx, dt, nu, nsteps):

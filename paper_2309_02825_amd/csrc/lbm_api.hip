@@ -343,6 +343,20 @@ lb_status lb_layout_to_dense(lb_solver* s, const double* buf, double* dense) {
     return LB_OK;
 }
 
+lb_status lb_theta_from_velocity(lb_solver* s, const double* u0, double* theta0, double* grad) {
+    if (!s || !u0 || !theta0) return fail(LB_ERR_INVALID_ARG, "NULL argument");
+    const int64_t nw = lbm::potential_workspace(s->d, s->g);
+    double* work = nullptr;
+    LB_HIP(hipMalloc((void**)&work, sizeof(double) * (size_t)nw), "hipMalloc potential workspace");
+    hipError_t e = lbm::launch_theta_from_velocity(s->d, s->g, s->cfg.dx, s->cfg.nu, u0, work,
+                                                   theta0, grad, s->stream);
+    hipError_t e2 = hipStreamSynchronize(s->stream);
+    (void)hipFree(work);
+    if (e != hipSuccess) return hip_fail(e, "theta_from_velocity launch");
+    if (e2 != hipSuccess) return hip_fail(e2, "hipStreamSynchronize");
+    return LB_OK;
+}
+
 lb_status lb_macro_adjoint(lb_solver* s, const double* state, const double* g_theta,
                            const double* g_u, double* lambda, double* g_eps) {
     if (!s || !state || !lambda || !g_eps) return fail(LB_ERR_INVALID_ARG, "NULL argument");

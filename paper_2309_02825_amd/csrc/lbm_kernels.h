@@ -62,6 +62,12 @@ hipError_t launch_layout_from_dense(int d, const Geo& g, const double* dense, do
                                    hipStream_t st);
 hipError_t launch_layout_to_dense(int d, const Geo& g, const double* buf, double* dense,
                                  hipStream_t st);
+// Burgers front end (inverse Cole-Hopf).  work holds potential_workspace
+// doubles.
+int64_t potential_workspace(int d, const Geo& g);
+hipError_t launch_theta_from_velocity(int d, const Geo& g, double dx, double nu, const double* u0,
+                                      double* work, double* theta, double* grad,
+                                      hipStream_t st);
 hipError_t launch_check_theta(const double* theta, int64_t n, int* flag, hipStream_t st);
 
 // Adjoint kernels write one partial sum of the eps-gradient per block into

@@ -507,6 +507,75 @@ __global__ void __launch_bounds__(256) k_finalize(const double* __restrict__ par
 }
 
 // ---------------------------------------------------------------------------
+// Burgers front end: theta0 from the initial velocity u0 (inverse Cole-Hopf
+// transformation, Sec. II: u = -2 nu grad(theta)/theta, so theta0 =
+// exp(-phi/(2 nu)) with grad(phi) = u0).  phi is integrated along the path
+// that runs along x_0 at x_1 = .. = 0, then along x_1 at x_2 = .. = 0, and so
+// on; each cell integral uses the cubic through four nodes,
+//     int_{x_j}^{x_j+1} u = dx (-u_{j-1} + 13 u_j + 13 u_{j+1} - u_{j+2}) / 24,
+// (periodic indices).  phi = 0 at the origin.
+// ---------------------------------------------------------------------------
+
+// Pass for axis a: one thread per line (c_0..c_{a-1}, *, 0..0); writes the
+// running integral along x_a into part_a[c_0 + n_0 (c_1 + ... n_{a-1} c_a)]
+// (the index of the node restricted to its first a + 1 coordinates).
+__global__ void __launch_bounds__(256) k_potential_axis(const double* __restrict__ u_a,
+                                                        double* __restrict__ part, Geo g, int a,
+                                                        int64_t nlines, double dx) {
+    const int64_t line = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (line >= nlines) return;
+    const int n[4] = {g.nx, g.ny, g.nz, g.nw};
+    int c[4] = {0, 0, 0, 0};
+    int64_t rem = line;
+    for (int b = 0; b < a; ++b) {
+        c[b] = (int)(rem % n[b]);
+        rem /= n[b];
+    }
+    const int na = n[a];
+    int64_t lead = 1;  // stride of axis a in the restricted index
+    for (int b = 0; b < a; ++b) lead *= n[b];
+    auto u_at = [&](int j) {
+        int cc[4] = {c[0], c[1], c[2], c[3]};
+        cc[a] = wrapi(j, na);
+        return u_a[node_index(g, cc)];
+    };
+    double phi = 0.0;
+    part[line] = 0.0;
+    for (int j = 0; j + 1 < na; ++j) {
+        phi += dx * ((13.0 * (u_at(j) + u_at(j + 1)) - (u_at(j - 1) + u_at(j + 2))) / 24.0);
+        part[line + lead * (j + 1)] = phi;
+    }
+}
+
+// theta0 = exp(-(sum_a part_a)/(2 nu)); grad theta0 = -u0 theta0/(2 nu).
+template <int D>
+__global__ void __launch_bounds__(256) k_theta_from_potential(const double* __restrict__ u0,
+                                                              const double* __restrict__ parts,
+                                                              double* __restrict__ theta,
+                                                              double* __restrict__ grad, Geo g,
+                                                              double inv2nu) {
+    int c[4];
+    if (!thread_node<D>(g, c)) return;
+    const int n[4] = {g.nx, g.ny, g.nz, g.nw};
+    double phi = 0.0;
+    int64_t off = 0, restricted = 0, stride = 1;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        restricted += stride * c[a];
+        stride *= n[a];
+        phi += parts[off + restricted];
+        off += stride;
+    }
+    const int k = node_index(g, c);
+    const double th = exp(-phi * inv2nu);
+    theta[k] = th;
+    if (grad) {
+#pragma unroll
+        for (int a = 0; a < D; ++a) grad[(int64_t)a * g.V + k] = -u0[(int64_t)a * g.V + k] * th * inv2nu;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // batched 2-D step over a tile table
 // ---------------------------------------------------------------------------
 // One block per tile.  tx > 0: a tx x (256/tx) rectangle of one instance at
@@ -627,6 +696,33 @@ hipError_t launch_layout_from_dense(int d, const Geo& g, const double* dense, do
 hipError_t launch_layout_to_dense(int d, const Geo& g, const double* buf, double* dense,
                                  hipStream_t st) {
     return LBM_LAUNCH(k_layout_to_dense, buf, dense, g);
+}
+
+int64_t potential_workspace(int d, const Geo& g) {
+    const int n[4] = {g.nx, g.ny, g.nz, g.nw};
+    int64_t total = 0, prod = 1;
+    for (int a = 0; a < d; ++a) {
+        prod *= n[a];
+        total += prod;
+    }
+    return total;
+}
+
+hipError_t launch_theta_from_velocity(int d, const Geo& g, double dx, double nu, const double* u0,
+                                      double* work, double* theta, double* grad,
+                                      hipStream_t st) {
+    const int n[4] = {g.nx, g.ny, g.nz, g.nw};
+    int64_t off = 0, nlines = 1;
+    for (int a = 0; a < d; ++a) {
+        hipLaunchKernelGGL(k_potential_axis, dim3((unsigned)((nlines + 255) / 256)), dim3(256), 0,
+                           st, u0 + (int64_t)a * g.V, work + off, g, a, nlines, dx);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        nlines *= n[a];
+        off += nlines;
+    }
+    const double inv2nu = 1.0 / (2.0 * nu);
+    return LBM_LAUNCH(k_theta_from_potential, u0, work, theta, grad, g, inv2nu);
 }
 
 hipError_t launch_check_theta(const double* theta, int64_t n, int* flag, hipStream_t st) {

@@ -83,6 +83,7 @@ def _load():
         "lb_macro_buffer": ([_vp, _vp, _vp, _vp], st),
         "lb_get_state": ([_vp, _vp], st),
         "lb_set_state": ([_vp, _vp, I64], st),
+        "lb_theta_from_velocity": ([_vp, _vp, _vp, _vp], st),
         "lb_macro_adjoint": ([_vp, _vp, _vp, _vp, _vp, _vp], st),
         "lb_adjoint_step": ([_vp, _vp, _vp, _vp, _vp], st),
         "lb_init_adjoint": ([_vp, _vp, _vp, _vp, _vp, _vp, _vp], st),
@@ -205,6 +206,10 @@ def lb_layout_from_dense(h: int, dense, buf):
 
 def lb_layout_to_dense(h: int, buf, dense):
     _check(_load().lb_layout_to_dense(h, _ptr(buf), _ptr(dense)))
+
+
+def lb_theta_from_velocity(h: int, u0, theta0, grad=None):
+    _check(_load().lb_theta_from_velocity(h, _ptr(u0), _ptr(theta0), _ptr(grad)))
 
 
 def lb_macro_adjoint(h: int, state, g_theta, g_u, lam, g_eps):

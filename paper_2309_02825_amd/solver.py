@@ -80,6 +80,20 @@ class Solver:
         self._theta0, self._grad = theta0, grad  # keep alive until the kernel ran
         L.lb_init(self.h, theta0, grad, check)
 
+    def theta_from_velocity(self, u0: torch.Tensor):
+        """Inverse Cole-Hopf front end: (theta0, grad theta0) from u0 (d, *shape)."""
+        u0 = _field(u0, (self.d,) + self.shape, self.device, "u0")
+        theta0 = torch.empty(self.shape, dtype=F64, device=self.device)
+        grad = torch.empty((self.d,) + self.shape, dtype=F64, device=self.device)
+        L.lb_theta_from_velocity(self.h, u0, theta0, grad)
+        return theta0, grad
+
+    def init_from_velocity(self, u0: torch.Tensor):
+        """Initialise from the Burgers initial velocity u0 (d, *shape)."""
+        theta0, grad = self.theta_from_velocity(u0)
+        self.init(theta0, grad)
+        return theta0
+
     def step(self, nsteps: int):
         L.lb_step(self.h, nsteps)
 

@@ -130,6 +130,30 @@ def test_parity_with_direct_oracle(name, grid, nsteps, kind):
         assert np.max(np.abs(u_g[a] - u_o[a])) <= TOL_U * den, (name, a)
 
 
+@pytest.mark.parametrize("example,level", [(2, 1), (3, 0), (4, 0)])
+def test_theta_from_velocity_matches_oracle(example, level):
+    """Burgers front end on the GPU (inverse Cole-Hopf from the paper's initial
+    velocities) against the oracle, then one solve from it."""
+    _say("theta_from_velocity", example, level)
+    SV = _solver_mod()
+    wl = {2: lambda: W.paper_example2(level, 0.3), 3: lambda: W.paper_example3(level, 0.15),
+          4: lambda: W.paper_example4(level, 0.08, 1.0)}[example]()
+    _, u0 = W.exact(wl, 0.0)
+    th_o, g_o = O.theta_from_velocity(u0, wl.dx, wl.nu)
+    s = SV.Solver(wl.grid, wl.dx, wl.dt, wl.nu, device=_dev())
+    th_g, g_g = s.theta_from_velocity(torch.from_numpy(u0).to(_dev()))
+    assert max_rel(th_g.cpu().numpy(), th_o) <= 1e-14
+    assert max_rel(g_g.cpu().numpy(), g_o) <= 1e-14
+    steps = 6
+    s.init(th_g, g_g)
+    s.step(steps)
+    th, u = s.macro()
+    th_r, u_r, _ = O.solve(th_o, g_o, wl.dx, wl.dt, wl.nu, steps)
+    assert max_rel(th.cpu().numpy(), th_r) <= TOL_THETA
+    assert max_rel(u.cpu().numpy(), u_r) <= TOL_U
+    s.close()
+
+
 def test_zero_steps_returns_initial_state():
     _say("zero_steps")
     grid = (37, 23)
