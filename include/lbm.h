@@ -137,6 +137,14 @@ lb_status lb_theta_from_velocity(lb_solver* s, const double* u0, double* theta0,
  * moment space, then stream), alternating the two buffers. */
 lb_status lb_step(lb_solver* s, int64_t nsteps);
 
+/* Options of a solver (lb_set_option).
+ * LB_OPT_FUSE_STEPS (default 1): on D2Q9, lb_step advances pairs of time
+ * steps with one pass over the state (temporal blocking: both steps are done
+ * on LDS-resident row strips); the result is bitwise that of single steps.
+ * 0 makes every step a separate launch. */
+enum { LB_OPT_FUSE_STEPS = 1 };
+lb_status lb_set_option(lb_solver* s, int32_t option, int32_t value);
+
 /* One time step from an explicit source buffer to an explicit destination
  * buffer (both in the storage layout, lb_state_bytes each, not overlapping).
  * Does not touch the solver's own buffers or step counter. */

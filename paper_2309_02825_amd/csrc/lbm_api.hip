@@ -159,6 +159,7 @@ struct lb_solver {
     double* partials;
     int64_t npartials;
     int* flag;
+    int fuse_steps;  // LB_OPT_FUSE_STEPS
 };
 
 extern "C" {
@@ -219,6 +220,7 @@ lb_status lb_create(const lb_config* cfg, void* hip_stream, double* f_a, double*
     s->cur = 0;
     s->steps = 0;
     s->inited = false;
+    s->fuse_steps = 1;
     s->npartials = lbm::launch_shape(s->d, s->g).nblocks;
     s->partials = nullptr;
     s->flag = nullptr;
@@ -282,13 +284,33 @@ lb_status lb_step(lb_solver* s, int64_t nsteps) {
         s->steps += nsteps;
         return LB_OK;
     }
-    for (int64_t n = 0; n < nsteps; ++n) {
+    int64_t n = 0;
+    if (s->d == 2 && s->fuse_steps) {
+        for (; n + 2 <= nsteps; n += 2) {
+            LB_HIP(lbm::launch_step2(s->g, s->r, s->buf[s->cur], s->buf[1 - s->cur], s->stream),
+                   "two-step launch");
+            s->cur ^= 1;
+            s->steps += 2;
+        }
+    }
+    for (; n < nsteps; ++n) {
         LB_HIP(lbm::launch_step(s->d, s->g, s->r, s->buf[s->cur], s->buf[1 - s->cur], s->stream),
                "step launch");
         s->cur ^= 1;
         ++s->steps;
     }
     return LB_OK;
+}
+
+lb_status lb_set_option(lb_solver* s, int32_t option, int32_t value) {
+    if (!s) return fail(LB_ERR_INVALID_ARG, "solver is NULL");
+    switch (option) {
+        case LB_OPT_FUSE_STEPS:
+            s->fuse_steps = value ? 1 : 0;
+            return LB_OK;
+        default:
+            return fail(LB_ERR_INVALID_ARG, "unknown option");
+    }
 }
 
 lb_status lb_step_buffers(lb_solver* s, const double* src, double* dst) {

@@ -45,6 +45,10 @@ Launch launch_shape(int d, const Geo& g);
 
 hipError_t launch_step(int d, const Geo& g, const Rates& r, const double* src, double* dst,
                        hipStream_t st);
+// Two D2Q9 steps in one pass (temporal blocking); bitwise equal to two
+// launch_step calls.
+hipError_t launch_step2(const Geo& g, const Rates& r, const double* src, double* dst,
+                        hipStream_t st);
 // 1-D grids up to this many nodes run all their steps in one launch with the
 // state in LDS (3 populations x 8 B x 2048 = 48 KiB).
 constexpr int RESIDENT_MAX_1D = 2048;

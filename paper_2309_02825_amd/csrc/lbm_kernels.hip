@@ -186,14 +186,118 @@ __global__ void __launch_bounds__(RES_THREADS) k_step_resident1(const double* __
         for (int i = 0; i < 3; ++i) dst[slot<3>(i, x)] = lds[i * RESIDENT_MAX_1D + x];
 }
 
-// ---------------------------------------------------------------------------
-// initialisation
-// ---------------------------------------------------------------------------
 __device__ __forceinline__ int wrapi(int v, int n) {
     v %= n;
     return v < 0 ? v + n : v;
 }
 
+// ---------------------------------------------------------------------------
+// Two D2Q9 time steps per pass over HBM (temporal blocking).  A block owns a
+// strip of TB_W columns and a segment of rows.  It marches down the segment
+// one input row at a time: input rows (the stored state, TB_W + 4 columns)
+// and step-1 results (TB_W + 2 columns) live in 3-row rings in LDS; when
+// input row y arrives, step 1 is done for row y-1 and step 2 for row y-2,
+// whose result is stored.  Each stored value is read from HBM once per two
+// steps (plus a 2-column and 2-row halo), and the arithmetic is the one of
+// k_step<2> twice, so the result is bitwise that of two single steps.
+// ---------------------------------------------------------------------------
+constexpr int TB_W = 128;               // output columns per strip
+constexpr int TB_THREADS = 128;
+constexpr int TB_IN = TB_W + 4;         // input columns (2-column halo)
+constexpr int TB_S1 = TB_W + 2;         // step-1 columns (1-column halo)
+constexpr int TB_PREFETCH = 2;          // input rows in flight per block
+constexpr int TB_NL = (9 * TB_IN + TB_THREADS - 1) / TB_THREADS;
+
+__global__ void __launch_bounds__(TB_THREADS) k_step2_d2q9(const double* __restrict__ src,
+                                                           double* __restrict__ dst, Geo g,
+                                                           Rates r, int ly, int nstrips) {
+    constexpr int Q = 9;
+    __shared__ double ring_in[3][Q][TB_IN];
+    __shared__ double ring_s1[3][Q][TB_S1];
+    const unsigned t = xcd_remap(blockIdx.x, gridDim.x);
+    const int strip = (int)(t % (unsigned)nstrips);
+    const int seg = (int)(t / (unsigned)nstrips);
+    const int nx = g.nx, ny = g.ny;
+    const int x0 = strip * TB_W;
+    const int ys = seg * ly;
+    const int ye = min(ys + ly, ny);
+    const int tid = threadIdx.x;
+    // the (population, column) items of one input row this thread loads
+    int ipop[TB_NL], icol[TB_NL], igx[TB_NL];
+#pragma unroll
+    for (int p = 0; p < TB_NL; ++p) {
+        const int item = tid + p * TB_THREADS;
+        ipop[p] = item / TB_IN;
+        icol[p] = item % TB_IN;
+        igx[p] = wrapi(x0 - 2 + icol[p], nx);
+    }
+    const int kend = ye - ys + 3;  // input rows ys-2 .. ye+1
+    double pre[TB_PREFETCH][TB_NL];
+#pragma unroll
+    for (int d = 0; d < TB_PREFETCH; ++d) {
+        if (d <= kend) {
+            const int base = wrapi(ys - 2 + d, ny) * nx;
+#pragma unroll
+            for (int p = 0; p < TB_NL; ++p)
+                if (tid + p * TB_THREADS < Q * TB_IN) pre[d][p] = src[slot<Q>(ipop[p], base + igx[p])];
+        }
+    }
+    for (int k = 0; k <= kend; ++k) {
+        const int yi = ys - 2 + k;
+        const int sl = k % 3;
+        const int pd = k % TB_PREFETCH;
+#pragma unroll
+        for (int d = 0; d < TB_PREFETCH; ++d) {
+            if (d != pd) continue;
+#pragma unroll
+            for (int p = 0; p < TB_NL; ++p)
+                if (tid + p * TB_THREADS < Q * TB_IN) ring_in[sl][ipop[p]][icol[p]] = pre[d][p];
+            if (k + TB_PREFETCH <= kend) {
+                const int base = wrapi(yi + TB_PREFETCH, ny) * nx;
+#pragma unroll
+                for (int p = 0; p < TB_NL; ++p)
+                    if (tid + p * TB_THREADS < Q * TB_IN)
+                        pre[d][p] = src[slot<Q>(ipop[p], base + igx[p])];
+            }
+        }
+        __syncthreads();
+        if (k >= 2) {
+            // step 1 at row yi - 1: pull from input rows yi-2 (e_y = +1), yi-1 (0), yi (-1)
+            const int sey[3] = {k % 3, (k + 2) % 3, (k + 1) % 3};
+            const int s1 = (k + 1) % 3;
+            for (int c = tid; c < TB_S1; c += TB_THREADS) {
+                double f[Q];
+#pragma unroll
+                for (int i = 0; i < Q; ++i)
+                    f[i] = ring_in[sey[Lat<2>::E[i][1] + 1]][i][c + 1 - Lat<2>::E[i][0]];
+                collide<2>(f, r);
+#pragma unroll
+                for (int i = 0; i < Q; ++i) ring_s1[s1][i][c] = f[i];
+            }
+        }
+        __syncthreads();
+        if (k >= 4) {
+            // step 2 at row yi - 2 from step-1 rows yi-3 (+1), yi-2 (0), yi-1 (-1)
+            const int sey[3] = {(k + 1) % 3, k % 3, (k + 2) % 3};
+            const int row = wrapi(yi - 2, ny) * nx;
+            for (int c = tid; c < TB_W; c += TB_THREADS) {
+                const int x = x0 + c;
+                if (x >= nx) break;
+                double f[Q];
+#pragma unroll
+                for (int i = 0; i < Q; ++i)
+                    f[i] = ring_s1[sey[Lat<2>::E[i][1] + 1]][i][c + 1 - Lat<2>::E[i][0]];
+                collide<2>(f, r);
+#pragma unroll
+                for (int i = 0; i < Q; ++i) __builtin_nontemporal_store(f[i], dst + slot<Q>(i, row + x));
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// initialisation
+// ---------------------------------------------------------------------------
 // Fourth-order central difference of theta along axis a at node c.
 template <int D>
 __device__ double fd4(const double* __restrict__ th, const Geo& g, const int (&c)[4], int a,
@@ -665,6 +769,26 @@ hipError_t launch_step_resident1(const Geo& g, const Rates& r, const double* src
     if (g.nx > RESIDENT_MAX_1D || g.ny != 1 || g.nz != 1 || g.nw != 1) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_step_resident1, dim3(1), dim3(RES_THREADS), 0, st, src, dst, g.nx, nsteps,
                        r);
+    return hipGetLastError();
+}
+
+// Segment length: about two blocks per CU in one wave (512 blocks), at least
+// 8 rows so the 4-row halo stays a small fraction.
+static int step2_rows(const Geo& g, int nstrips) {
+    const int64_t target = 512;
+    int64_t ly = ((int64_t)g.ny * nstrips + target - 1) / target;
+    if (ly < 8) ly = 8;
+    if (ly > g.ny) ly = g.ny;
+    return (int)ly;
+}
+
+hipError_t launch_step2(const Geo& g, const Rates& r, const double* src, double* dst,
+                        hipStream_t st) {
+    const int nstrips = (g.nx + TB_W - 1) / TB_W;
+    const int ly = step2_rows(g, nstrips);
+    const int nseg = (g.ny + ly - 1) / ly;
+    hipLaunchKernelGGL(k_step2_d2q9, dim3((unsigned)(nstrips * nseg)), dim3(TB_THREADS), 0, st, src,
+                       dst, g, r, ly, nstrips);
     return hipGetLastError();
 }
 

@@ -22,6 +22,7 @@ LB_ERR_NONFINITE = -3
 LB_ERR_OOM = -4
 LB_ERR_HIP = -5
 LB_ERR_STATE = -6
+LB_OPT_FUSE_STEPS = 1
 _NAMES = {0: "LB_OK", -1: "LB_ERR_INVALID_ARG", -2: "LB_ERR_UNSTABLE", -3: "LB_ERR_NONFINITE",
           -4: "LB_ERR_OOM", -5: "LB_ERR_HIP", -6: "LB_ERR_STATE"}
 
@@ -76,6 +77,7 @@ def _load():
         "lb_create": ([_cp, _vp, _vp, _vp, ctypes.POINTER(_vp)], st),
         "lb_init": ([_vp, _vp, _vp, I32], st),
         "lb_step": ([_vp, I64], st),
+        "lb_set_option": ([_vp, I32, I32], st),
         "lb_step_buffers": ([_vp, _vp, _vp], st),
         "lb_current_state": ([_vp], _vp),
         "lb_steps_taken": ([_vp], I64),
@@ -170,6 +172,10 @@ def lb_init(h: int, theta0, grad=None, check_theta: bool = False):
 
 def lb_step(h: int, nsteps: int):
     _check(_load().lb_step(h, int(nsteps)))
+
+
+def lb_set_option(h: int, option: int, value: int):
+    _check(_load().lb_set_option(h, int(option), int(value)))
 
 
 def lb_step_buffers(h: int, src, dst):

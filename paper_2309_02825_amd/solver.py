@@ -97,6 +97,10 @@ class Solver:
     def step(self, nsteps: int):
         L.lb_step(self.h, nsteps)
 
+    def set_fused(self, on: bool):
+        """D2Q9: advance pairs of steps per pass (default on) or one step per launch."""
+        L.lb_set_option(self.h, L.LB_OPT_FUSE_STEPS, int(bool(on)))
+
     def step_buffers(self, src: torch.Tensor, dst: torch.Tensor):
         L.lb_step_buffers(self.h, src, dst)
 

@@ -227,6 +227,27 @@ def test_resident_1d_run_equals_per_step_launches():
         assert np.array_equal(outs[0], outs[1]), n
 
 
+@pytest.mark.parametrize("grid,steps", [((4096, 64), 6), ((1000, 333), 5), ((130, 67), 9),
+                                         ((128, 8), 4), ((7, 1), 6), ((1, 5), 4), ((300, 2), 8)])
+def test_fused_two_step_pass_equals_single_steps(grid, steps):
+    """D2Q9 lb_step advances pairs of steps in one pass (temporal blocking);
+    the state is bitwise that of one launch per step, for ragged strips and
+    segments, odd step counts and degenerate grids."""
+    _say("fused vs single", grid, steps)
+    SV = _solver_mod()
+    dx, dt, nu, th0, _ = _problem(grid, "random")
+    outs = []
+    for fused in (True, False):
+        s = SV.Solver(grid, dx, dt, nu, device=_dev())
+        s.set_fused(fused)
+        s.init(torch.from_numpy(th0).to(_dev()), None)
+        s.step(steps)
+        outs.append(s.get_state().cpu().numpy())
+        assert s.steps == steps
+        s.close()
+    assert np.array_equal(outs[0], outs[1])
+
+
 def test_run_to_run_bitwise_determinism():
     _say("determinism")
     grid = (257, 129)
