@@ -124,10 +124,11 @@ def solve_timed(torch, SV, W, wl, steps, warmup, dev):
     return wall, kms
 
 
-def kernel_only(torch, SV, W, wl, lb_steps, dev):
+def kernel_only(torch, SV, W, wl, lb_steps, dev, fused=True):
     """Average duration of one LB step on a resident state (HIP events)."""
     stream = torch.cuda.current_stream()
     s = SV.Solver(wl.grid, wl.dx, wl.dt, wl.nu, device=dev)
+    s.set_fused(fused)
     th0, g0 = W.evaluate(wl.modes, wl.grid, wl.dx, xp=torch, device=dev)
     s.init(th0, g0)
     del th0, g0
@@ -312,6 +313,11 @@ def main():
     log(f"{mlups:.1f} MLUPS, kernel {kms * 1e3:.2f} us/step, {achieved:.1f} GB/s")
     traffic = traffic_for(args.workload, wl.nsteps)
     lattice = {1: "D1Q3", 2: "D2Q9", 3: "D3Q19", 4: "D4Q33"}[d]
+    # D2Q9 runs two LB steps per launch (temporal blocking); the algorithmic
+    # bytes of a launch are 144 B per lattice update times its 2V updates
+    per_launch = 2 if d == 2 else 1
+    kernel = "k_step2_d2q9" if d == 2 else f"k_step<{d}>"
+    launch_us = kms * 1e3 * per_launch
     rec = {
         "metric": METRIC,
         "value": round(mlups, 1),
@@ -330,15 +336,27 @@ def main():
                    "theta0": "2 + prod cos(2 pi x_a)", "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic, "kernel": f"k_step<{d}>",
-                     "kernel_us_per_launch": round(kms * 1e3, 3),
-                     "bytes_per_lu": BYTES_PER_LU[d]},
+                     "traffic": traffic, "kernel": kernel,
+                     "lb_steps_per_launch": per_launch,
+                     "kernel_us_per_launch": round(launch_us, 3),
+                     "bytes_per_lu": BYTES_PER_LU[d],
+                     "hbm_frac_measured": (round(traffic / (launch_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)
+                                           if traffic else None)},
     }
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         rec["cpu_baseline"] = cpu_baseline(wl)
     if not args.no_forms:
         forms = {}
+        if d == 2:
+            # the same workload with one launch per LB step
+            ms = kernel_only(torch, SV, W, wl, 400, dev, fused=False)
+            ml = V / (ms / 1e3) / 1e6
+            forms[wl.name + "_single_step"] = {
+                "kernel": "k_step<2>", "kernel_us_per_step": round(ms * 1e3, 2),
+                "mlups": round(ml, 1), "gbs_algorithmic": round(BYTES_PER_LU[2] * ml / 1e3, 1),
+                "frac": round(BYTES_PER_LU[2] * ml / 1e3 / HBM_PEAK_GBS, 4), "lb_steps_timed": 400}
+            log("single step", forms[wl.name + "_single_step"])
         for name in ("heat2d_1024", "heat3d_256", "heat3d_512", "heat4d_64"):
             if name == args.workload:
                 continue
