@@ -197,7 +197,8 @@ def form_batched(torch, SV, W, dev):
     bs.close()
     mlups = nodes * 1000 / (ms / 1e3) / 1e6
     return {"instances": len(insts), "total_nodes": nodes, "lb_steps": 1000,
-            "launch": "one hipGraph of 1000 tile-table kernels", "tile": list(tile),
+            "launch": "one hipGraph of tile-table kernels (two steps per launch for tile "
+                      "(-1, rows))", "tile": list(tile),
             "graph_ms": round(ms, 3), "wall_s": round(wall, 4), "mlups": round(mlups, 1),
             "gbs_algorithmic": round(mlups * 144 / 1e3, 1)}
 

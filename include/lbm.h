@@ -238,14 +238,24 @@ lb_status lb_batch_create(const lb_config* cfgs, int32_t count, void* hip_stream
  * differences per instance). */
 lb_status lb_batch_init(lb_batch* b, const double* theta0, const double* grad);
 
-/* Tile shape of the batched step: (0, 0) selects linear tiles of 256
- * consecutive node indices of one instance (crossing row ends; the default),
- * otherwise a tx x ty rectangle with tx*ty = 256 and tx a power of two in
- * [16, 256].  Applies to subsequent steps. */
+/* Tile shape of the batched step (Sec. III.A scheme, the same arithmetic in
+ * every mode, so all modes give bitwise identical states):
+ *   (-1, rows)  two steps per pass over each instance: tiles of 128 columns x
+ *               rows rows (1 <= rows <= 65535) that keep the intermediate
+ *               step in LDS; an odd step count ends with one linear-tile
+ *               step.  (-1, 64) is the default of a new batch;
+ *   (0, 0)      one step per pass, linear tiles of 256 consecutive node
+ *               indices of one instance (crossing row ends);
+ *   (tx, ty)    one step per pass, tx x ty rectangles with tx*ty = 256 and tx
+ *               a power of two in [16, 256].
+ * Applies to subsequent steps; cached graphs are dropped.  Anything else is
+ * LB_ERR_INVALID_ARG. */
 lb_status lb_batch_set_tile(lb_batch* b, int32_t tx, int32_t ty);
 
-/* Time candidate tile shapes on the real pools (state is restored) and keep
- * the fastest; best_tx/best_ty receive the choice (may be NULL). */
+/* Time candidate tile shapes, one-step and two-step, per step on the real
+ * pools (the current state is left as it was; the other pool is used as
+ * scratch) and keep the fastest; best_tx/best_ty receive the choice (may be
+ * NULL). */
 lb_status lb_batch_autotune(lb_batch* b, int32_t steps_per_trial, int32_t* best_tx,
                             int32_t* best_ty);
 

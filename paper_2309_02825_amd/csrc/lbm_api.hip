@@ -419,6 +419,9 @@ lb_status lb_init_adjoint(lb_solver* s, const double* theta0, const double* grad
 // batched form
 // ---------------------------------------------------------------------------
 
+// Rows per two-step tile of a new batch (autotuning may change it).
+constexpr int kDefaultStripRows = 64;
+
 struct lb_batch {
     std::vector<lb_config> cfgs;
     std::vector<int64_t> offsets, elems, node_offsets;
@@ -433,6 +436,8 @@ struct lb_batch {
     BatchInst* d_insts;
     BatchTile* d_tiles;
     int64_t ntiles;
+    BatchTile* d_lin;  // linear tiles, for the odd step of a two-step mode
+    int64_t nlin;
     int tx, ty;
     std::map<std::pair<int64_t, int>, hipGraphExec_t> graphs;
 };
@@ -442,28 +447,46 @@ static void drop_graphs(lb_batch* b) {
     b->graphs.clear();
 }
 
-static lb_status build_tiles(lb_batch* b, int tx, int ty) {
+// Tile tables.  tx == 0: 256 consecutive node indices of one instance;
+// tx == -1: two-step tiles of STRIP_W columns x ty rows (y1 in .pad), ordered
+// strip-fastest within an instance so that neighbouring strips share an XCD;
+// otherwise tx x ty rectangles.
+static std::vector<BatchTile> tile_list(const lb_batch* b, int tx, int ty) {
     std::vector<BatchTile> tiles;
     for (size_t i = 0; i < b->insts.size(); ++i) {
         const BatchInst& in = b->insts[i];
         if (tx == 0) {
             const int64_t V = (int64_t)in.nx * in.ny;
             for (int64_t k0 = 0; k0 < V; k0 += 256) tiles.push_back(BatchTile{(int)i, (int)k0, 0, 0});
+        } else if (tx < 0) {
+            for (int y0 = 0; y0 < in.ny; y0 += ty)
+                for (int x0 = 0; x0 < in.nx; x0 += lbm::STRIP_W)
+                    tiles.push_back(BatchTile{(int)i, x0, y0, std::min(y0 + ty, in.ny)});
         } else {
             for (int y0 = 0; y0 < in.ny; y0 += ty)
                 for (int x0 = 0; x0 < in.nx; x0 += tx) tiles.push_back(BatchTile{(int)i, x0, y0, 0});
         }
     }
+    return tiles;
+}
+
+static lb_status upload_tiles(const std::vector<BatchTile>& tiles, BatchTile** d, int64_t* n) {
     if (tiles.size() > (size_t)INT_MAX) return fail(LB_ERR_INVALID_ARG, "too many tiles");
-    if (b->d_tiles) (void)hipFree(b->d_tiles);
-    b->d_tiles = nullptr;
+    if (*d) (void)hipFree(*d);
+    *d = nullptr;
+    *n = 0;
     if (!tiles.empty()) {
-        LB_HIP(hipMalloc((void**)&b->d_tiles, sizeof(BatchTile) * tiles.size()), "hipMalloc tiles");
-        LB_HIP(hipMemcpy(b->d_tiles, tiles.data(), sizeof(BatchTile) * tiles.size(),
-                         hipMemcpyHostToDevice),
+        LB_HIP(hipMalloc((void**)d, sizeof(BatchTile) * tiles.size()), "hipMalloc tiles");
+        LB_HIP(hipMemcpy(*d, tiles.data(), sizeof(BatchTile) * tiles.size(), hipMemcpyHostToDevice),
                "hipMemcpy tiles");
     }
-    b->ntiles = (int64_t)tiles.size();
+    *n = (int64_t)tiles.size();
+    return LB_OK;
+}
+
+static lb_status build_tiles(lb_batch* b, int tx, int ty) {
+    lb_status st = upload_tiles(tile_list(b, tx, ty), &b->d_tiles, &b->ntiles);
+    if (st != LB_OK) return st;
     b->tx = tx;
     b->ty = ty;
     drop_graphs(b);
@@ -525,6 +548,8 @@ lb_status lb_batch_create(const lb_config* cfgs, int32_t count, void* hip_stream
     b->d_insts = nullptr;
     b->d_tiles = nullptr;
     b->ntiles = 0;
+    b->d_lin = nullptr;
+    b->nlin = 0;
     hipError_t e = hipMalloc((void**)&b->d_insts, sizeof(BatchInst) * b->insts.size());
     if (e == hipSuccess)
         e = hipMemcpy(b->d_insts, b->insts.data(), sizeof(BatchInst) * b->insts.size(),
@@ -535,7 +560,8 @@ lb_status lb_batch_create(const lb_config* cfgs, int32_t count, void* hip_stream
         delete b;
         return hip_fail(e, "batch setup");
     }
-    lb_status st = build_tiles(b, 0, 0);
+    lb_status st = upload_tiles(tile_list(b, 0, 0), &b->d_lin, &b->nlin);
+    if (st == LB_OK) st = build_tiles(b, -1, kDefaultStripRows);
     if (st != LB_OK) {
         lb_batch_destroy(b);
         return st;
@@ -548,6 +574,7 @@ lb_status lb_batch_destroy(lb_batch* b) {
     if (!b) return LB_OK;
     drop_graphs(b);
     if (b->d_tiles) (void)hipFree(b->d_tiles);
+    if (b->d_lin) (void)hipFree(b->d_lin);
     if (b->d_insts) (void)hipFree(b->d_insts);
     if (b->capture) (void)hipStreamDestroy(b->capture);
     delete b;
@@ -573,20 +600,43 @@ lb_status lb_batch_init(lb_batch* b, const double* theta0, const double* grad) {
 lb_status lb_batch_set_tile(lb_batch* b, int32_t tx, int32_t ty) {
     if (!b) return fail(LB_ERR_INVALID_ARG, "batch is NULL");
     const bool linear = (tx == 0 && ty == 0);
-    if (!linear && (tx < 16 || tx > 256 || (tx & (tx - 1)) != 0 || tx * ty != 256))
+    const bool two_step = (tx == -1 && ty >= 1 && ty <= 65535);
+    if (!linear && !two_step &&
+        (tx < 16 || tx > 256 || (tx & (tx - 1)) != 0 || tx * ty != 256))
         return fail(LB_ERR_INVALID_ARG,
-                    "tile must be (0,0) or tx*ty = 256 with tx a power of two in [16,256]");
+                    "tile must be (0,0), (-1, rows) with rows in [1,65535], or tx*ty = 256 "
+                    "with tx a power of two in [16,256]");
     if (tx == b->tx && ty == b->ty) return LB_OK;
     return build_tiles(b, tx, ty);
 }
 
-static lb_status batch_launch_plain(lb_batch* b, int64_t nsteps, hipStream_t st, int cur) {
-    for (int64_t n = 0; n < nsteps; ++n) {
-        LB_HIP(lbm::launch_batch_step(b->d_insts, b->d_tiles, b->ntiles, b->tx, b->ty, b->pool[cur],
-                                      b->pool[1 - cur], st),
-               "batch step launch");
-        cur ^= 1;
+// Enqueue nsteps steps starting from pool[cur]; *cur_out receives the pool
+// that then holds the state.  A two-step tile mode advances pairs of steps
+// per launch and takes the odd step with the linear tiles.
+static lb_status batch_launch_plain(lb_batch* b, int64_t nsteps, hipStream_t st, int cur,
+                                    int* cur_out) {
+    if (b->tx < 0) {
+        for (int64_t n = 0; n + 1 < nsteps; n += 2) {
+            LB_HIP(lbm::launch_batch_step2(b->d_insts, b->d_tiles, b->ntiles, b->pool[cur],
+                                           b->pool[1 - cur], st),
+                   "batch two-step launch");
+            cur ^= 1;
+        }
+        if (nsteps & 1) {
+            LB_HIP(lbm::launch_batch_step(b->d_insts, b->d_lin, b->nlin, 0, 0, b->pool[cur],
+                                          b->pool[1 - cur], st),
+                   "batch step launch");
+            cur ^= 1;
+        }
+    } else {
+        for (int64_t n = 0; n < nsteps; ++n) {
+            LB_HIP(lbm::launch_batch_step(b->d_insts, b->d_tiles, b->ntiles, b->tx, b->ty,
+                                          b->pool[cur], b->pool[1 - cur], st),
+                   "batch step launch");
+            cur ^= 1;
+        }
     }
+    if (cur_out) *cur_out = cur;
     return LB_OK;
 }
 
@@ -595,8 +645,9 @@ lb_status lb_batch_step(lb_batch* b, int64_t nsteps, int32_t use_graph) {
     if (nsteps < 0) return fail(LB_ERR_INVALID_ARG, "nsteps must be >= 0");
     if (!b->inited) return fail(LB_ERR_STATE, "lb_batch_step before lb_batch_init");
     if (nsteps == 0) return LB_OK;
+    int next = b->cur;
     if (!use_graph) {
-        lb_status st = batch_launch_plain(b, nsteps, b->stream, b->cur);
+        lb_status st = batch_launch_plain(b, nsteps, b->stream, b->cur, &next);
         if (st != LB_OK) return st;
     } else {
         auto key = std::make_pair(nsteps, b->cur);
@@ -605,7 +656,7 @@ lb_status lb_batch_step(lb_batch* b, int64_t nsteps, int32_t use_graph) {
             hipGraph_t graph = nullptr;
             LB_HIP(hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal),
                    "hipStreamBeginCapture");
-            lb_status st = batch_launch_plain(b, nsteps, b->capture, b->cur);
+            lb_status st = batch_launch_plain(b, nsteps, b->capture, b->cur, nullptr);
             hipError_t e = hipStreamEndCapture(b->capture, &graph);
             if (st != LB_OK) {
                 if (graph) (void)hipGraphDestroy(graph);
@@ -619,8 +670,10 @@ lb_status lb_batch_step(lb_batch* b, int64_t nsteps, int32_t use_graph) {
             it = b->graphs.emplace(key, exec).first;
         }
         LB_HIP(hipGraphLaunch(it->second, b->stream), "hipGraphLaunch");
+        const int64_t launches = b->tx < 0 ? nsteps / 2 + (nsteps & 1) : nsteps;
+        next = b->cur ^ (int)(launches & 1);
     }
-    if (nsteps & 1) b->cur ^= 1;
+    b->cur = next;
     b->steps += nsteps;
     return LB_OK;
 }
@@ -630,7 +683,8 @@ lb_status lb_batch_autotune(lb_batch* b, int32_t steps_per_trial, int32_t* best_
     if (!b) return fail(LB_ERR_INVALID_ARG, "batch is NULL");
     if (!b->inited) return fail(LB_ERR_STATE, "autotune needs an initialised batch");
     if (steps_per_trial < 1) steps_per_trial = 1;
-    static const int cand[][2] = {{0, 0}, {256, 1}, {128, 2}, {64, 4}, {32, 8}, {16, 16}};
+    static const int cand[][2] = {{0, 0},   {256, 1}, {128, 2}, {64, 4},  {32, 8},
+                                  {16, 16}, {-1, 16}, {-1, 32}, {-1, 64}, {-1, 128}};
     hipEvent_t e0, e1;
     LB_HIP(hipEventCreate(&e0), "hipEventCreate");
     LB_HIP(hipEventCreate(&e1), "hipEventCreate");
@@ -640,13 +694,20 @@ lb_status lb_batch_autotune(lb_batch* b, int32_t steps_per_trial, int32_t* best_
     for (const auto& c : cand) {
         st = build_tiles(b, c[0], c[1]);
         if (st != LB_OK) break;
-        // Trials always step pool[cur] -> pool[1-cur]: the current state is
-        // untouched and the other pool is scratch.
+        // Trials always launch pool[cur] -> pool[1-cur]: the current state
+        // is untouched and the other pool is scratch.  Times are per step.
+        const int per_launch = c[0] < 0 ? 2 : 1;
         auto trial = [&](int reps) -> lb_status {
-            for (int r = 0; r < reps; ++r)
-                LB_HIP(lbm::launch_batch_step(b->d_insts, b->d_tiles, b->ntiles, b->tx, b->ty,
-                                              b->pool[b->cur], b->pool[1 - b->cur], b->stream),
-                       "batch step launch");
+            for (int r = 0; r < reps; ++r) {
+                if (c[0] < 0)
+                    LB_HIP(lbm::launch_batch_step2(b->d_insts, b->d_tiles, b->ntiles,
+                                                   b->pool[b->cur], b->pool[1 - b->cur], b->stream),
+                           "batch two-step launch");
+                else
+                    LB_HIP(lbm::launch_batch_step(b->d_insts, b->d_tiles, b->ntiles, b->tx, b->ty,
+                                                  b->pool[b->cur], b->pool[1 - b->cur], b->stream),
+                           "batch step launch");
+            }
             return LB_OK;
         };
         if ((st = trial(1)) != LB_OK) break;
@@ -656,6 +717,7 @@ lb_status lb_batch_autotune(lb_batch* b, int32_t steps_per_trial, int32_t* best_
         if (hipEventSynchronize(e1) != hipSuccess) { st = fail(LB_ERR_HIP, "event sync"); break; }
         float ms = 0.f;
         (void)hipEventElapsedTime(&ms, e0, e1);
+        ms /= (float)per_launch;
         if (ms < best) {
             best = ms;
             bx = c[0];

@@ -96,9 +96,13 @@ struct BatchInst {
 struct BatchTile {
     int inst;           // instance index
     int x0, y0;         // tile origin
-    int pad;
+    int pad;            // two-step tiles: end row of the segment
 };
 hipError_t launch_batch_step(const BatchInst* insts, const BatchTile* tiles, int64_t ntiles,
                              int tx, int ty, const double* src, double* dst, hipStream_t st);
+// Two steps per pass; tiles (inst, x0, y0, y1) cover STRIP_W-column strips.
+constexpr int STRIP_W = 128;
+hipError_t launch_batch_step2(const BatchInst* insts, const BatchTile* tiles, int64_t ntiles,
+                              const double* src, double* dst, hipStream_t st);
 
 }  // namespace lbm

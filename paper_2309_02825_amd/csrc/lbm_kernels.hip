@@ -208,19 +208,15 @@ constexpr int TB_S1 = TB_W + 2;         // step-1 columns (1-column halo)
 constexpr int TB_PREFETCH = 2;          // input rows in flight per block
 constexpr int TB_NL = (9 * TB_IN + TB_THREADS - 1) / TB_THREADS;
 
-__global__ void __launch_bounds__(TB_THREADS) k_step2_d2q9(const double* __restrict__ src,
-                                                           double* __restrict__ dst, Geo g,
-                                                           Rates r, int ly, int nstrips) {
+// Advance rows [ys, ye) of the columns [x0, x0 + TB_W) of one D2Q9 grid by
+// two steps (the strip reads rows ys-2 .. ye+1 and columns x0-2 .. x0+TB_W+1,
+// wrapped periodically).
+__device__ __forceinline__ void step2_tile(const double* __restrict__ src,
+                                           double* __restrict__ dst, int nx, int ny,
+                                           const Rates& r, int x0, int ys, int ye,
+                                           double (&ring_in)[3][9][TB_IN],
+                                           double (&ring_s1)[3][9][TB_S1]) {
     constexpr int Q = 9;
-    __shared__ double ring_in[3][Q][TB_IN];
-    __shared__ double ring_s1[3][Q][TB_S1];
-    const unsigned t = xcd_remap(blockIdx.x, gridDim.x);
-    const int strip = (int)(t % (unsigned)nstrips);
-    const int seg = (int)(t / (unsigned)nstrips);
-    const int nx = g.nx, ny = g.ny;
-    const int x0 = strip * TB_W;
-    const int ys = seg * ly;
-    const int ye = min(ys + ly, ny);
     const int tid = threadIdx.x;
     // the (population, column) items of one input row this thread loads
     int ipop[TB_NL], icol[TB_NL], igx[TB_NL];
@@ -293,6 +289,18 @@ __global__ void __launch_bounds__(TB_THREADS) k_step2_d2q9(const double* __restr
             }
         }
     }
+}
+
+__global__ void __launch_bounds__(TB_THREADS) k_step2_d2q9(const double* __restrict__ src,
+                                                           double* __restrict__ dst, Geo g,
+                                                           Rates r, int ly, int nstrips) {
+    __shared__ double ring_in[3][9][TB_IN];
+    __shared__ double ring_s1[3][9][TB_S1];
+    const unsigned t = xcd_remap(blockIdx.x, gridDim.x);
+    const int strip = (int)(t % (unsigned)nstrips);
+    const int seg = (int)(t / (unsigned)nstrips);
+    const int ys = seg * ly;
+    step2_tile(src, dst, g.nx, g.ny, r, strip * TB_W, ys, min(ys + ly, g.ny), ring_in, ring_s1);
 }
 
 // ---------------------------------------------------------------------------
@@ -724,6 +732,21 @@ __global__ void __launch_bounds__(256) k_batch_step(const BatchInst* __restrict_
     for (int i = 0; i < Q; ++i) __builtin_nontemporal_store(f[i], d + slot<Q>(i, k));
 }
 
+// Batched two-step pass: tile (inst, x0, y0, y1) = rows [y0, y1) of the
+// strip at x0 of one instance.
+__global__ void __launch_bounds__(TB_THREADS) k_batch_step2(const BatchInst* __restrict__ insts,
+                                                            const BatchTile* __restrict__ tiles,
+                                                            const double* __restrict__ src,
+                                                            double* __restrict__ dst) {
+    __shared__ double ring_in[3][9][TB_IN];
+    __shared__ double ring_s1[3][9][TB_S1];
+    const BatchTile t = tiles[xcd_remap(blockIdx.x, gridDim.x)];
+    const BatchInst& in = insts[t.inst];
+    const Rates r = in.r;
+    step2_tile(src + in.offset, dst + in.offset, in.nx, in.ny, r, t.x0, t.y0, t.pad, ring_in,
+               ring_s1);
+}
+
 template <typename F>
 hipError_t dispatch(int d, F&& f) {
     switch (d) {
@@ -876,6 +899,14 @@ hipError_t launch_init_adjoint(int d, const Geo& g, const Rates& r, const double
 
 hipError_t launch_finalize(const double* partials, int64_t n, double* g_eps, hipStream_t st) {
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, st, partials, n, g_eps);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_step2(const BatchInst* insts, const BatchTile* tiles, int64_t ntiles,
+                              const double* src, double* dst, hipStream_t st) {
+    if (ntiles <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_batch_step2, dim3((unsigned)ntiles), dim3(TB_THREADS), 0, st, insts, tiles,
+                       src, dst);
     return hipGetLastError();
 }
 

@@ -497,16 +497,53 @@ def test_batch_matches_single_instance_runs():
     th0s = [torch.from_numpy(W.evaluate(p.modes, p.grid, p.dx)[0]) for p in insts]
     grs = [torch.from_numpy(W.evaluate(p.modes, p.grid, p.dx)[1]) for p in insts]
     bs.init(th0s, grs)
-    for tx, ty in ((64, 4), (256, 1), (16, 16), (0, 0)):
+    # one-step tiles, then two-step tiles (strips wider than some instances,
+    # segments taller than some, odd counts that end on a linear-tile step)
+    plan = ((64, 4, 10, True), (256, 1, 10, False), (16, 16, 10, True), (0, 0, 10, True),
+            (-1, 16, 7, True), (-1, 5, 6, False), (-1, 64, 3, True), (-1, 1, 5, False))
+    for tx, ty, n, graph in plan:
         bs.set_tile(tx, ty)
-        bs.step(10, graph=(tx != 256))
+        bs.step(n, graph=graph)
+    total = sum(n for *_, n, _g in plan)
     ths, us = bs.macro()
     torch.cuda.synchronize()
     for b, p in enumerate(insts):
-        th, u, _ = _gpu_run(p.grid, p.dx, p.dt, p.nu, th0s[b].numpy(), grs[b].numpy(), 40,
+        th, u, _ = _gpu_run(p.grid, p.dx, p.dt, p.nu, th0s[b].numpy(), grs[b].numpy(), total,
                             want_f=False)
         assert np.array_equal(ths[b].cpu().numpy(), th), b
         assert np.array_equal(us[b].cpu().numpy(), u), b
+    bs.close()
+
+
+def test_batch_two_step_degenerate_shapes():
+    """Two-step tiles on instances narrower than a strip, with one or two
+    rows, one column, or a ragged last strip and segment; rough fields and
+    difference-gradient init; bitwise equal to single-instance runs."""
+    _say("batch two-step degenerate shapes")
+    SV = _solver_mod()
+    rng = np.random.Generator(np.random.PCG64(11))
+    shapes = [(1, 5), (7, 1), (2, 2), (130, 3), (129, 1), (257, 129), (128, 64), (1, 1)]
+    probs = []
+    for i, (nx, ny) in enumerate(shapes):
+        nu = float(rng.uniform(0.005, 0.05))
+        dx = 1.0 / max(nx, ny)
+        eps = float(rng.uniform(0.05, 0.45))
+        probs.append(W.Workload(f"deg{i}", (nx, ny), dx, eps * dx * dx / nu, nu, []))
+    th0s = [torch.from_numpy(W.random_smooth_field(rng, (ny, nx))) for nx, ny in shapes]
+    bs = SV.BatchSolver(probs, device=_dev())
+    bs.init(th0s, None)
+    total = 0
+    for ty, n in ((64, 9), (2, 4), (200, 5)):
+        bs.set_tile(-1, ty)
+        bs.step(n, graph=True)
+        total += n
+    ths, us = bs.macro()
+    torch.cuda.synchronize()
+    for b, p in enumerate(probs):
+        th, u, _ = _gpu_run(p.grid, p.dx, p.dt, p.nu, th0s[b].numpy(), None, total,
+                            want_f=False)
+        assert np.array_equal(ths[b].cpu().numpy(), th), p.grid
+        assert np.array_equal(us[b].cpu().numpy(), u), p.grid
     bs.close()
 
 
