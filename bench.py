@@ -1,8 +1,8 @@
 """Benchmark of the Cole-Hopf MRT-LB hot path on one MI355X.
 
 One benchmark step is one complete solve of the workload: initialise from
-theta0 and its analytic gradient, advance all LB time steps (fused
-collide-stream kernel), and form theta and u.  Default workload: D2Q9 on a
+theta0 and its analytic gradient, advance all LB time steps (D2Q9: eight
+time steps per pass over HBM, temporal blocking), and form theta and u.  Default workload: D2Q9 on a
 4096 x 4096 periodic unit square, nu = 0.01, eps = 0.2, 10,000 time steps
 (theta0 = 2 + cos 2pi x cos 2pi y).  The timed region holds exactly
 --steps solves between two device synchronisations; inputs are resident in
@@ -29,6 +29,11 @@ if ROOT not in sys.path:
 METRIC = "FP64 MLUPS + HBM GB/s (% roofline); batched and adjoint vs plain step"
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_LU = {1: 48, 2: 144, 3: 304, 4: 528}
+# double-precision operations of one D2Q9 collision (collide_d2q9: 26 add/sub,
+# 6 mul, 3 fma counted twice)
+FLOPS_PER_LU_D2Q9 = 38
+FP64_PEAK_TFLOPS = 78.6
+D2_STEPS_PER_PASS = 8
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_step.json")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2309_02825_amd", "csrc", n)
                   for n in ("lbm_kernels.hip", "lbm_lattice.h", "lbm_kernels.h")]
@@ -124,11 +129,11 @@ def solve_timed(torch, SV, W, wl, steps, warmup, dev):
     return wall, kms
 
 
-def kernel_only(torch, SV, W, wl, lb_steps, dev, fused=True):
+def kernel_only(torch, SV, W, wl, lb_steps, dev, steps_per_pass=D2_STEPS_PER_PASS):
     """Average duration of one LB step on a resident state (HIP events)."""
     stream = torch.cuda.current_stream()
     s = SV.Solver(wl.grid, wl.dx, wl.dt, wl.nu, device=dev)
-    s.set_fused(fused)
+    s.set_steps_per_pass(steps_per_pass)
     th0, g0 = W.evaluate(wl.modes, wl.grid, wl.dx, xp=torch, device=dev)
     s.init(th0, g0)
     del th0, g0
@@ -197,8 +202,8 @@ def form_batched(torch, SV, W, dev):
     bs.close()
     mlups = nodes * 1000 / (ms / 1e3) / 1e6
     return {"instances": len(insts), "total_nodes": nodes, "lb_steps": 1000,
-            "launch": "one hipGraph of tile-table kernels (two steps per launch for tile "
-                      "(-1, rows))", "tile": list(tile),
+            "launch": "one hipGraph of tile-table kernels (S steps per launch for tile "
+                      "(-S, rows))", "tile": list(tile),
             "graph_ms": round(ms, 3), "wall_s": round(wall, 4), "mlups": round(mlups, 1),
             "gbs_algorithmic": round(mlups * 144 / 1e3, 1)}
 
@@ -314,10 +319,11 @@ def main():
     log(f"{mlups:.1f} MLUPS, kernel {kms * 1e3:.2f} us/step, {achieved:.1f} GB/s")
     traffic = traffic_for(args.workload, wl.nsteps)
     lattice = {1: "D1Q3", 2: "D2Q9", 3: "D3Q19", 4: "D4Q33"}[d]
-    # D2Q9 runs two LB steps per launch (temporal blocking); the algorithmic
-    # bytes of a launch are 144 B per lattice update times its 2V updates
-    per_launch = 2 if d == 2 else 1
-    kernel = "k_step2_d2q9" if d == 2 else f"k_step<{d}>"
+    # D2Q9 runs eight LB steps per launch (temporal blocking); the algorithmic
+    # bytes of a launch are 144 B per lattice update times its 8V updates,
+    # while the pass itself reads and writes the state once (see "traffic")
+    per_launch = D2_STEPS_PER_PASS if d == 2 else 1
+    kernel = f"k_steps_d2q9<{D2_STEPS_PER_PASS}>" if d == 2 else f"k_step<{d}>"
     launch_us = kms * 1e3 * per_launch
     rec = {
         "metric": METRIC,
@@ -344,20 +350,30 @@ def main():
                      "hbm_frac_measured": (round(traffic / (launch_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)
                                            if traffic else None)},
     }
+    if d == 2:
+        tf = FLOPS_PER_LU_D2Q9 * V / (kms / 1e3) / 1e12
+        rec["roofline"]["fp64"] = {"flops_per_lu": FLOPS_PER_LU_D2Q9,
+                                   "achieved_tflops": round(tf, 2), "peak_tflops": FP64_PEAK_TFLOPS,
+                                   "frac": round(tf / FP64_PEAK_TFLOPS, 4)}
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         rec["cpu_baseline"] = cpu_baseline(wl)
     if not args.no_forms:
         forms = {}
         if d == 2:
-            # the same workload with one launch per LB step
-            ms = kernel_only(torch, SV, W, wl, 400, dev, fused=False)
-            ml = V / (ms / 1e3) / 1e6
-            forms[wl.name + "_single_step"] = {
-                "kernel": "k_step<2>", "kernel_us_per_step": round(ms * 1e3, 2),
-                "mlups": round(ml, 1), "gbs_algorithmic": round(BYTES_PER_LU[2] * ml / 1e3, 1),
-                "frac": round(BYTES_PER_LU[2] * ml / 1e3 / HBM_PEAK_GBS, 4), "lb_steps_timed": 400}
-            log("single step", forms[wl.name + "_single_step"])
+            # the same workload with at most 1, 2 and 4 steps per launch
+            sweep = {}
+            for spp in (1, 2, 4):
+                ms = kernel_only(torch, SV, W, wl, 400, dev, steps_per_pass=spp)
+                ml = V / (ms / 1e3) / 1e6
+                sweep[f"steps_per_pass_{spp}"] = {
+                    "kernel": "k_step<2>" if spp == 1 else f"k_steps_d2q9<{spp}>",
+                    "kernel_us_per_step": round(ms * 1e3, 2), "mlups": round(ml, 1),
+                    "gbs_algorithmic": round(BYTES_PER_LU[2] * ml / 1e3, 1),
+                    "frac": round(BYTES_PER_LU[2] * ml / 1e3 / HBM_PEAK_GBS, 4),
+                    "lb_steps_timed": 400}
+            forms[wl.name + "_steps_per_pass"] = sweep
+            log("steps per pass", sweep)
         for name in ("heat2d_1024", "heat3d_256", "heat3d_512", "heat4d_64"):
             if name == args.workload:
                 continue

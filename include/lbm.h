@@ -138,11 +138,15 @@ lb_status lb_theta_from_velocity(lb_solver* s, const double* u0, double* theta0,
 lb_status lb_step(lb_solver* s, int64_t nsteps);
 
 /* Options of a solver (lb_set_option).
- * LB_OPT_FUSE_STEPS (default 1): on D2Q9, lb_step advances pairs of time
- * steps with one pass over the state (temporal blocking: both steps are done
- * on LDS-resident row strips); the result is bitwise that of single steps.
- * 0 makes every step a separate launch. */
-enum { LB_OPT_FUSE_STEPS = 1 };
+ * LB_OPT_STEPS_PER_PASS (default 8): on D2Q9, the most time steps lb_step
+ * advances with one pass over the state in HBM (temporal blocking: row strips
+ * march through LDS and registers, all steps on chip).  A run of nsteps is
+ * split greedily into passes of 8, 4 and 2 steps (within the limit) and
+ * single steps; the result is bitwise that of single steps.  Values below 2
+ * make every step a separate launch; others are rounded down to 2, 4 or 8.
+ * Other lattices always take single steps.  Unknown options are
+ * LB_ERR_INVALID_ARG. */
+enum { LB_OPT_STEPS_PER_PASS = 1 };
 lb_status lb_set_option(lb_solver* s, int32_t option, int32_t value);
 
 /* One time step from an explicit source buffer to an explicit destination

@@ -82,6 +82,10 @@ Rates make_rates(int d, double dx, double dt, double nu) {
     r.dwd = dwd;
     r.dw0 = -2.0 * d * dw1 - 2.0 * d * (d - 1) * dwd;
     r.dinv_s1 = 3.0;
+    r.d2_cj = 0.5 * (1.0 - r.s1);
+    r.d2_cp = 0.5 * (1.0 - r.s21);
+    r.d2_ct = r.s21 / 6.0 - 2.0 * r.wd;
+    r.d2_cq = 0.25 * (1.0 - r.s22);
     return r;
 }
 
@@ -159,7 +163,7 @@ struct lb_solver {
     double* partials;
     int64_t npartials;
     int* flag;
-    int fuse_steps;  // LB_OPT_FUSE_STEPS
+    int steps_per_pass;  // LB_OPT_STEPS_PER_PASS: 1, 2, 4 or 8
 };
 
 extern "C" {
@@ -220,7 +224,7 @@ lb_status lb_create(const lb_config* cfg, void* hip_stream, double* f_a, double*
     s->cur = 0;
     s->steps = 0;
     s->inited = false;
-    s->fuse_steps = 1;
+    s->steps_per_pass = lbm::MAX_STEPS_PER_PASS;
     s->npartials = lbm::launch_shape(s->d, s->g).nblocks;
     s->partials = nullptr;
     s->flag = nullptr;
@@ -285,12 +289,15 @@ lb_status lb_step(lb_solver* s, int64_t nsteps) {
         return LB_OK;
     }
     int64_t n = 0;
-    if (s->d == 2 && s->fuse_steps) {
-        for (; n + 2 <= nsteps; n += 2) {
-            LB_HIP(lbm::launch_step2(s->g, s->r, s->buf[s->cur], s->buf[1 - s->cur], s->stream),
-                   "two-step launch");
-            s->cur ^= 1;
-            s->steps += 2;
+    if (s->d == 2) {
+        for (int pass = s->steps_per_pass; pass >= 2; pass /= 2) {
+            for (; n + pass <= nsteps; n += pass) {
+                LB_HIP(lbm::launch_steps(pass, s->g, s->r, s->buf[s->cur], s->buf[1 - s->cur],
+                                         s->stream),
+                       "multi-step launch");
+                s->cur ^= 1;
+                s->steps += pass;
+            }
         }
     }
     for (; n < nsteps; ++n) {
@@ -305,9 +312,12 @@ lb_status lb_step(lb_solver* s, int64_t nsteps) {
 lb_status lb_set_option(lb_solver* s, int32_t option, int32_t value) {
     if (!s) return fail(LB_ERR_INVALID_ARG, "solver is NULL");
     switch (option) {
-        case LB_OPT_FUSE_STEPS:
-            s->fuse_steps = value ? 1 : 0;
+        case LB_OPT_STEPS_PER_PASS: {
+            int p = 1;
+            while (p * 2 <= value && p * 2 <= lbm::MAX_STEPS_PER_PASS) p *= 2;
+            s->steps_per_pass = p;
             return LB_OK;
+        }
         default:
             return fail(LB_ERR_INVALID_ARG, "unknown option");
     }
@@ -419,7 +429,8 @@ lb_status lb_init_adjoint(lb_solver* s, const double* theta0, const double* grad
 // batched form
 // ---------------------------------------------------------------------------
 
-// Rows per two-step tile of a new batch (autotuning may change it).
+// Tile mode of a new batch: 8-step tiles of 64 rows (autotuning may change it).
+constexpr int kDefaultPassSteps = 8;
 constexpr int kDefaultStripRows = 64;
 
 struct lb_batch {
@@ -436,7 +447,7 @@ struct lb_batch {
     BatchInst* d_insts;
     BatchTile* d_tiles;
     int64_t ntiles;
-    BatchTile* d_lin;  // linear tiles, for the odd step of a two-step mode
+    BatchTile* d_lin;  // linear tiles, for the steps a multi-step mode leaves over
     int64_t nlin;
     int tx, ty;
     std::map<std::pair<int64_t, int>, hipGraphExec_t> graphs;
@@ -448,9 +459,9 @@ static void drop_graphs(lb_batch* b) {
 }
 
 // Tile tables.  tx == 0: 256 consecutive node indices of one instance;
-// tx == -1: two-step tiles of STRIP_W columns x ty rows (y1 in .pad), ordered
-// strip-fastest within an instance so that neighbouring strips share an XCD;
-// otherwise tx x ty rectangles.
+// tx == -S: S-step tiles of strip_width(S) columns x ty rows (y1 in .pad),
+// ordered strip-fastest within an instance so that neighbouring strips share
+// an XCD; otherwise tx x ty rectangles.
 static std::vector<BatchTile> tile_list(const lb_batch* b, int tx, int ty) {
     std::vector<BatchTile> tiles;
     for (size_t i = 0; i < b->insts.size(); ++i) {
@@ -460,7 +471,7 @@ static std::vector<BatchTile> tile_list(const lb_batch* b, int tx, int ty) {
             for (int64_t k0 = 0; k0 < V; k0 += 256) tiles.push_back(BatchTile{(int)i, (int)k0, 0, 0});
         } else if (tx < 0) {
             for (int y0 = 0; y0 < in.ny; y0 += ty)
-                for (int x0 = 0; x0 < in.nx; x0 += lbm::STRIP_W)
+                for (int x0 = 0; x0 < in.nx; x0 += lbm::strip_width(-tx))
                     tiles.push_back(BatchTile{(int)i, x0, y0, std::min(y0 + ty, in.ny)});
         } else {
             for (int y0 = 0; y0 < in.ny; y0 += ty)
@@ -561,7 +572,7 @@ lb_status lb_batch_create(const lb_config* cfgs, int32_t count, void* hip_stream
         return hip_fail(e, "batch setup");
     }
     lb_status st = upload_tiles(tile_list(b, 0, 0), &b->d_lin, &b->nlin);
-    if (st == LB_OK) st = build_tiles(b, -1, kDefaultStripRows);
+    if (st == LB_OK) st = build_tiles(b, -kDefaultPassSteps, kDefaultStripRows);
     if (st != LB_OK) {
         lb_batch_destroy(b);
         return st;
@@ -600,29 +611,38 @@ lb_status lb_batch_init(lb_batch* b, const double* theta0, const double* grad) {
 lb_status lb_batch_set_tile(lb_batch* b, int32_t tx, int32_t ty) {
     if (!b) return fail(LB_ERR_INVALID_ARG, "batch is NULL");
     const bool linear = (tx == 0 && ty == 0);
-    const bool two_step = (tx == -1 && ty >= 1 && ty <= 65535);
-    if (!linear && !two_step &&
+    const bool multi_step = ((tx == -2 || tx == -4 || tx == -8) && ty >= 1 && ty <= 65535);
+    if (!linear && !multi_step &&
         (tx < 16 || tx > 256 || (tx & (tx - 1)) != 0 || tx * ty != 256))
         return fail(LB_ERR_INVALID_ARG,
-                    "tile must be (0,0), (-1, rows) with rows in [1,65535], or tx*ty = 256 "
-                    "with tx a power of two in [16,256]");
+                    "tile must be (0,0), (-S, rows) with S in {2,4,8} and rows in [1,65535], "
+                    "or tx*ty = 256 with tx a power of two in [16,256]");
     if (tx == b->tx && ty == b->ty) return LB_OK;
     return build_tiles(b, tx, ty);
 }
 
+// Launches that advance nsteps in the current tile mode: passes of S steps
+// for a mode (-S, rows), the rest single steps on the linear tiles.
+static int64_t batch_launches(const lb_batch* b, int64_t nsteps) {
+    if (b->tx >= 0) return nsteps;
+    const int S = -b->tx;
+    return nsteps / S + nsteps % S;
+}
+
 // Enqueue nsteps steps starting from pool[cur]; *cur_out receives the pool
-// that then holds the state.  A two-step tile mode advances pairs of steps
-// per launch and takes the odd step with the linear tiles.
+// that then holds the state.
 static lb_status batch_launch_plain(lb_batch* b, int64_t nsteps, hipStream_t st, int cur,
                                     int* cur_out) {
     if (b->tx < 0) {
-        for (int64_t n = 0; n + 1 < nsteps; n += 2) {
-            LB_HIP(lbm::launch_batch_step2(b->d_insts, b->d_tiles, b->ntiles, b->pool[cur],
+        const int S = -b->tx;
+        int64_t n = 0;
+        for (; n + S <= nsteps; n += S) {
+            LB_HIP(lbm::launch_batch_steps(S, b->d_insts, b->d_tiles, b->ntiles, b->pool[cur],
                                            b->pool[1 - cur], st),
-                   "batch two-step launch");
+                   "batch multi-step launch");
             cur ^= 1;
         }
-        if (nsteps & 1) {
+        for (; n < nsteps; ++n) {
             LB_HIP(lbm::launch_batch_step(b->d_insts, b->d_lin, b->nlin, 0, 0, b->pool[cur],
                                           b->pool[1 - cur], st),
                    "batch step launch");
@@ -670,8 +690,7 @@ lb_status lb_batch_step(lb_batch* b, int64_t nsteps, int32_t use_graph) {
             it = b->graphs.emplace(key, exec).first;
         }
         LB_HIP(hipGraphLaunch(it->second, b->stream), "hipGraphLaunch");
-        const int64_t launches = b->tx < 0 ? nsteps / 2 + (nsteps & 1) : nsteps;
-        next = b->cur ^ (int)(launches & 1);
+        next = b->cur ^ (int)(batch_launches(b, nsteps) & 1);
     }
     b->cur = next;
     b->steps += nsteps;
@@ -683,8 +702,8 @@ lb_status lb_batch_autotune(lb_batch* b, int32_t steps_per_trial, int32_t* best_
     if (!b) return fail(LB_ERR_INVALID_ARG, "batch is NULL");
     if (!b->inited) return fail(LB_ERR_STATE, "autotune needs an initialised batch");
     if (steps_per_trial < 1) steps_per_trial = 1;
-    static const int cand[][2] = {{0, 0},   {256, 1}, {128, 2}, {64, 4},  {32, 8},
-                                  {16, 16}, {-1, 16}, {-1, 32}, {-1, 64}, {-1, 128}};
+    static const int cand[][2] = {{0, 0},  {256, 1}, {64, 4},  {16, 16}, {-2, 64},
+                                  {-4, 64}, {-8, 32}, {-8, 64}, {-8, 128}};
     hipEvent_t e0, e1;
     LB_HIP(hipEventCreate(&e0), "hipEventCreate");
     LB_HIP(hipEventCreate(&e1), "hipEventCreate");
@@ -696,13 +715,13 @@ lb_status lb_batch_autotune(lb_batch* b, int32_t steps_per_trial, int32_t* best_
         if (st != LB_OK) break;
         // Trials always launch pool[cur] -> pool[1-cur]: the current state
         // is untouched and the other pool is scratch.  Times are per step.
-        const int per_launch = c[0] < 0 ? 2 : 1;
+        const int per_launch = c[0] < 0 ? -c[0] : 1;
         auto trial = [&](int reps) -> lb_status {
             for (int r = 0; r < reps; ++r) {
                 if (c[0] < 0)
-                    LB_HIP(lbm::launch_batch_step2(b->d_insts, b->d_tiles, b->ntiles,
+                    LB_HIP(lbm::launch_batch_steps(per_launch, b->d_insts, b->d_tiles, b->ntiles,
                                                    b->pool[b->cur], b->pool[1 - b->cur], b->stream),
-                           "batch two-step launch");
+                           "batch multi-step launch");
                 else
                     LB_HIP(lbm::launch_batch_step(b->d_insts, b->d_tiles, b->ntiles, b->tx, b->ty,
                                                   b->pool[b->cur], b->pool[1 - b->cur], b->stream),

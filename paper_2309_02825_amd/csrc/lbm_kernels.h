@@ -45,9 +45,13 @@ Launch launch_shape(int d, const Geo& g);
 
 hipError_t launch_step(int d, const Geo& g, const Rates& r, const double* src, double* dst,
                        hipStream_t st);
-// Two D2Q9 steps in one pass (temporal blocking); bitwise equal to two
-// launch_step calls.
-hipError_t launch_step2(const Geo& g, const Rates& r, const double* src, double* dst,
+// nsteps (2, 4 or 8) D2Q9 steps in one pass over HBM (temporal blocking);
+// bitwise equal to nsteps launch_step calls.  A block of MS_THREADS threads
+// produces a strip of strip_width(nsteps) columns.
+constexpr int MS_THREADS = 128;
+constexpr int MAX_STEPS_PER_PASS = 8;
+__host__ __device__ constexpr int strip_width(int nsteps) { return MS_THREADS - 2 * nsteps; }
+hipError_t launch_steps(int nsteps, const Geo& g, const Rates& r, const double* src, double* dst,
                         hipStream_t st);
 // 1-D grids up to this many nodes run all their steps in one launch with the
 // state in LDS (3 populations x 8 B x 2048 = 48 KiB).
@@ -96,13 +100,13 @@ struct BatchInst {
 struct BatchTile {
     int inst;           // instance index
     int x0, y0;         // tile origin
-    int pad;            // two-step tiles: end row of the segment
+    int pad;            // multi-step tiles: end row of the segment
 };
 hipError_t launch_batch_step(const BatchInst* insts, const BatchTile* tiles, int64_t ntiles,
                              int tx, int ty, const double* src, double* dst, hipStream_t st);
-// Two steps per pass; tiles (inst, x0, y0, y1) cover STRIP_W-column strips.
-constexpr int STRIP_W = 128;
-hipError_t launch_batch_step2(const BatchInst* insts, const BatchTile* tiles, int64_t ntiles,
-                              const double* src, double* dst, hipStream_t st);
+// nsteps (2, 4 or 8) steps per pass; tiles (inst, x0, y0, y1) cover strips of
+// strip_width(nsteps) columns.
+hipError_t launch_batch_steps(int nsteps, const BatchInst* insts, const BatchTile* tiles,
+                              int64_t ntiles, const double* src, double* dst, hipStream_t st);
 
 }  // namespace lbm

@@ -192,115 +192,150 @@ __device__ __forceinline__ int wrapi(int v, int n) {
 }
 
 // ---------------------------------------------------------------------------
-// Two D2Q9 time steps per pass over HBM (temporal blocking).  A block owns a
-// strip of TB_W columns and a segment of rows.  It marches down the segment
-// one input row at a time: input rows (the stored state, TB_W + 4 columns)
-// and step-1 results (TB_W + 2 columns) live in 3-row rings in LDS; when
-// input row y arrives, step 1 is done for row y-1 and step 2 for row y-2,
-// whose result is stored.  Each stored value is read from HBM once per two
-// steps (plus a 2-column and 2-row halo), and the arithmetic is the one of
-// k_step<2> twice, so the result is bitwise that of two single steps.
+// S D2Q9 time steps per pass over HBM (temporal blocking).
+//
+// A block of MS_THREADS threads owns a strip of MS_THREADS - 2S output columns
+// and a segment of rows; thread t owns column x0 - S + t in every stage (the
+// strip plus an S-column halo on each side).  The block marches down its
+// segment one row per iteration: it loads input row ys - S + k and, in the
+// same iteration, stage j = 1..S computes row ys - S + k - j of step j from
+// rows (that row + {-1, 0, +1}) of step j - 1.  Only the last stage's rows
+// are stored, so each value is read from and written to HBM once per S steps
+// (plus the halo).
+//
+// Exchange between stages: the three populations with e_x = 0 never leave
+// their thread.  The six with e_x != 0 are written to LDS already shifted by
+// e_x (producer column t -> slot t + e_x), so every consumer reads its own
+// column.  Rows are delayed in registers: a population with e_y = -1 is used
+// in the iteration it arrives, e_y = 0 one iteration later, e_y = +1 two
+// iterations later (two registers that alternate with the row parity; the
+// march is unrolled by two so that the parity is static).  Stages alternate
+// between two LDS buffers of 6 x MS_THREADS doubles, so LDS use does not grow
+// with S.  The arithmetic is collide<2> S times, so the result is bitwise that
+// of S single steps.
 // ---------------------------------------------------------------------------
-constexpr int TB_W = 128;               // output columns per strip
-constexpr int TB_THREADS = 128;
-constexpr int TB_IN = TB_W + 4;         // input columns (2-column halo)
-constexpr int TB_S1 = TB_W + 2;         // step-1 columns (1-column halo)
-constexpr int TB_PREFETCH = 2;          // input rows in flight per block
-constexpr int TB_NL = (9 * TB_IN + TB_THREADS - 1) / TB_THREADS;
+__host__ __device__ constexpr int ms_ex(int i) { return Lat<2>::E[i][0]; }
+__host__ __device__ constexpr int ms_ey(int i) { return Lat<2>::E[i][1]; }
+// index of population i among those with e_x != 0
+__host__ __device__ constexpr int ms_xslot(int i) {
+    int s = 0;
+    for (int j = 0; j < i; ++j) s += ms_ex(j) != 0;
+    return s;
+}
+// index of population i among those with the same e_y
+__host__ __device__ constexpr int ms_yslot(int i) {
+    int s = 0;
+    for (int j = 0; j < i; ++j) s += ms_ey(j) == ms_ey(i);
+    return s;
+}
 
-// Advance rows [ys, ye) of the columns [x0, x0 + TB_W) of one D2Q9 grid by
-// two steps (the strip reads rows ys-2 .. ye+1 and columns x0-2 .. x0+TB_W+1,
-// wrapped periodically).
-__device__ __forceinline__ void step2_tile(const double* __restrict__ src,
-                                           double* __restrict__ dst, int nx, int ny,
-                                           const Rates& r, int x0, int ys, int ye,
-                                           double (&ring_in)[3][9][TB_IN],
-                                           double (&ring_s1)[3][9][TB_S1]) {
-    constexpr int Q = 9;
+template <int S>
+struct MsState {
+    double pre[9];      // next input row (prefetched)
+    double z[S][3];     // e_y = 0 populations of the previous row, per stage input
+    double u[2][S][3];  // e_y = +1 populations of the rows of each parity
+};
+
+// One iteration k of the march; P = k & 1.
+template <int S, int P>
+__device__ __forceinline__ void ms_row(MsState<S>& st, double (&lds)[2][6][MS_THREADS], int k,
+                                       int kend, const double* __restrict__ src,
+                                       double* __restrict__ dst, int nx, int ny, int gx, int ys,
+                                       int x0, const Rates& r) {
+    constexpr int W = MS_THREADS - 2 * S;
     const int tid = threadIdx.x;
-    // the (population, column) items of one input row this thread loads
-    int ipop[TB_NL], icol[TB_NL], igx[TB_NL];
+    double f[9];
 #pragma unroll
-    for (int p = 0; p < TB_NL; ++p) {
-        const int item = tid + p * TB_THREADS;
-        ipop[p] = item / TB_IN;
-        icol[p] = item % TB_IN;
-        igx[p] = wrapi(x0 - 2 + icol[p], nx);
+    for (int i = 0; i < 9; ++i) f[i] = st.pre[i];
+    if (k < kend) {
+        const int base = wrapi(ys - S + k + 1, ny) * nx + gx;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) st.pre[i] = src[slot<9>(i, base)];
     }
-    const int kend = ye - ys + 3;  // input rows ys-2 .. ye+1
-    double pre[TB_PREFETCH][TB_NL];
 #pragma unroll
-    for (int d = 0; d < TB_PREFETCH; ++d) {
-        if (d <= kend) {
-            const int base = wrapi(ys - 2 + d, ny) * nx;
-#pragma unroll
-            for (int p = 0; p < TB_NL; ++p)
-                if (tid + p * TB_THREADS < Q * TB_IN) pre[d][p] = src[slot<Q>(ipop[p], base + igx[p])];
+    for (int i = 0; i < 9; ++i)
+        if (ms_ex(i) != 0) {
+            const int c = tid + ms_ex(i);
+            if (c >= 0 && c < MS_THREADS) lds[0][ms_xslot(i)][c] = f[i];
         }
+    __syncthreads();
+#pragma unroll
+    for (int j = 1; j <= S; ++j) {
+        // inputs of stage j: stage j-1 rows of iterations k (e_y = -1), k-1
+        // (e_y = 0) and k-2 (e_y = +1)
+        double in[9];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            const double v = ms_ex(i) != 0 ? lds[(j - 1) & 1][ms_xslot(i)][tid] : f[i];
+            if (ms_ey(i) == -1) {
+                in[i] = v;
+            } else if (ms_ey(i) == 0) {
+                in[i] = st.z[j - 1][ms_yslot(i)];
+                st.z[j - 1][ms_yslot(i)] = v;
+            } else {
+                in[i] = st.u[P][j - 1][ms_yslot(i)];
+                st.u[P][j - 1][ms_yslot(i)] = v;
+            }
+        }
+        // stage j holds valid rows from iteration 2j on, in columns j .. T-1-j
+        if (k >= 2 * j && tid >= j && tid < MS_THREADS - j) {
+            collide<2>(in, r);
+            if (j < S) {
+#pragma unroll
+                for (int i = 0; i < 9; ++i) {
+                    f[i] = in[i];
+                    if (ms_ex(i) != 0) {
+                        const int c = tid + ms_ex(i);
+                        if (c >= 0 && c < MS_THREADS) lds[j & 1][ms_xslot(i)][c] = in[i];
+                    }
+                }
+            } else if (tid >= S && tid < S + W && x0 - S + tid < nx) {
+                const int row = wrapi(ys - 2 * S + k, ny) * nx + x0 - S + tid;
+#pragma unroll
+                for (int i = 0; i < 9; ++i) __builtin_nontemporal_store(in[i], dst + slot<9>(i, row));
+            }
+        }
+        if (j < S) __syncthreads();
     }
-    for (int k = 0; k <= kend; ++k) {
-        const int yi = ys - 2 + k;
-        const int sl = k % 3;
-        const int pd = k % TB_PREFETCH;
+    // with S odd the last stage reads buffer 0, which the next load rewrites
+    if (S & 1) __syncthreads();
+}
+
+// Advance rows [ys, ye) of the columns [x0, x0 + MS_THREADS - 2S) of one
+// D2Q9 grid by S steps (reads rows ys-S .. ye-1+S and columns x0-S ..
+// x0+MS_THREADS-S-1, wrapped periodically).
+template <int S>
+__device__ __forceinline__ void ms_tile(const double* __restrict__ src, double* __restrict__ dst,
+                                        int nx, int ny, const Rates& r, int x0, int ys, int ye,
+                                        double (&lds)[2][6][MS_THREADS]) {
+    const int gx = wrapi(x0 - S + (int)threadIdx.x, nx);
+    const int kend = ye - ys + 2 * S - 1;
+    MsState<S> st;
+    {
+        const int base = wrapi(ys - S, ny) * nx + gx;
 #pragma unroll
-        for (int d = 0; d < TB_PREFETCH; ++d) {
-            if (d != pd) continue;
+        for (int i = 0; i < 9; ++i) st.pre[i] = src[slot<9>(i, base)];
+    }
 #pragma unroll
-            for (int p = 0; p < TB_NL; ++p)
-                if (tid + p * TB_THREADS < Q * TB_IN) ring_in[sl][ipop[p]][icol[p]] = pre[d][p];
-            if (k + TB_PREFETCH <= kend) {
-                const int base = wrapi(yi + TB_PREFETCH, ny) * nx;
+    for (int j = 0; j < S; ++j)
 #pragma unroll
-                for (int p = 0; p < TB_NL; ++p)
-                    if (tid + p * TB_THREADS < Q * TB_IN)
-                        pre[d][p] = src[slot<Q>(ipop[p], base + igx[p])];
-            }
-        }
-        __syncthreads();
-        if (k >= 2) {
-            // step 1 at row yi - 1: pull from input rows yi-2 (e_y = +1), yi-1 (0), yi (-1)
-            const int sey[3] = {k % 3, (k + 2) % 3, (k + 1) % 3};
-            const int s1 = (k + 1) % 3;
-            for (int c = tid; c < TB_S1; c += TB_THREADS) {
-                double f[Q];
-#pragma unroll
-                for (int i = 0; i < Q; ++i)
-                    f[i] = ring_in[sey[Lat<2>::E[i][1] + 1]][i][c + 1 - Lat<2>::E[i][0]];
-                collide<2>(f, r);
-#pragma unroll
-                for (int i = 0; i < Q; ++i) ring_s1[s1][i][c] = f[i];
-            }
-        }
-        __syncthreads();
-        if (k >= 4) {
-            // step 2 at row yi - 2 from step-1 rows yi-3 (+1), yi-2 (0), yi-1 (-1)
-            const int sey[3] = {(k + 1) % 3, k % 3, (k + 2) % 3};
-            const int row = wrapi(yi - 2, ny) * nx;
-            for (int c = tid; c < TB_W; c += TB_THREADS) {
-                const int x = x0 + c;
-                if (x >= nx) break;
-                double f[Q];
-#pragma unroll
-                for (int i = 0; i < Q; ++i)
-                    f[i] = ring_s1[sey[Lat<2>::E[i][1] + 1]][i][c + 1 - Lat<2>::E[i][0]];
-                collide<2>(f, r);
-#pragma unroll
-                for (int i = 0; i < Q; ++i) __builtin_nontemporal_store(f[i], dst + slot<Q>(i, row + x));
-            }
-        }
+        for (int a = 0; a < 3; ++a) st.z[j][a] = st.u[0][j][a] = st.u[1][j][a] = 0.0;
+    for (int k = 0; k <= kend; k += 2) {
+        ms_row<S, 0>(st, lds, k, kend, src, dst, nx, ny, gx, ys, x0, r);
+        if (k + 1 <= kend) ms_row<S, 1>(st, lds, k + 1, kend, src, dst, nx, ny, gx, ys, x0, r);
     }
 }
 
-__global__ void __launch_bounds__(TB_THREADS) k_step2_d2q9(const double* __restrict__ src,
+template <int S>
+__global__ void __launch_bounds__(MS_THREADS) k_steps_d2q9(const double* __restrict__ src,
                                                            double* __restrict__ dst, Geo g,
                                                            Rates r, int ly, int nstrips) {
-    __shared__ double ring_in[3][9][TB_IN];
-    __shared__ double ring_s1[3][9][TB_S1];
+    __shared__ double lds[2][6][MS_THREADS];
     const unsigned t = xcd_remap(blockIdx.x, gridDim.x);
     const int strip = (int)(t % (unsigned)nstrips);
     const int seg = (int)(t / (unsigned)nstrips);
     const int ys = seg * ly;
-    step2_tile(src, dst, g.nx, g.ny, r, strip * TB_W, ys, min(ys + ly, g.ny), ring_in, ring_s1);
+    ms_tile<S>(src, dst, g.nx, g.ny, r, strip * (MS_THREADS - 2 * S), ys, min(ys + ly, g.ny), lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -732,19 +767,18 @@ __global__ void __launch_bounds__(256) k_batch_step(const BatchInst* __restrict_
     for (int i = 0; i < Q; ++i) __builtin_nontemporal_store(f[i], d + slot<Q>(i, k));
 }
 
-// Batched two-step pass: tile (inst, x0, y0, y1) = rows [y0, y1) of the
-// strip at x0 of one instance.
-__global__ void __launch_bounds__(TB_THREADS) k_batch_step2(const BatchInst* __restrict__ insts,
+// Batched S-step pass: tile (inst, x0, y0, y1) = rows [y0, y1) of the strip
+// at x0 (MS_THREADS - 2S columns) of one instance.
+template <int S>
+__global__ void __launch_bounds__(MS_THREADS) k_batch_steps(const BatchInst* __restrict__ insts,
                                                             const BatchTile* __restrict__ tiles,
                                                             const double* __restrict__ src,
                                                             double* __restrict__ dst) {
-    __shared__ double ring_in[3][9][TB_IN];
-    __shared__ double ring_s1[3][9][TB_S1];
+    __shared__ double lds[2][6][MS_THREADS];
     const BatchTile t = tiles[xcd_remap(blockIdx.x, gridDim.x)];
     const BatchInst& in = insts[t.inst];
     const Rates r = in.r;
-    step2_tile(src + in.offset, dst + in.offset, in.nx, in.ny, r, t.x0, t.y0, t.pad, ring_in,
-               ring_s1);
+    ms_tile<S>(src + in.offset, dst + in.offset, in.nx, in.ny, r, t.x0, t.y0, t.pad, lds);
 }
 
 template <typename F>
@@ -797,22 +831,37 @@ hipError_t launch_step_resident1(const Geo& g, const Rates& r, const double* src
 
 // Segment length: about two blocks per CU in one wave (512 blocks), at least
 // 8 rows so the 4-row halo stays a small fraction.
-static int step2_rows(const Geo& g, int nstrips) {
-    const int64_t target = 512;
+// Rows per segment of an S-step launch: about 1536 blocks (a few per CU at
+// the kernel's occupancy), at least 16 rows so that the 2S-row pipeline fill
+// stays a modest share of the march.
+static int steps_rows(const Geo& g, int nstrips) {
+    const int64_t target = 1536;
     int64_t ly = ((int64_t)g.ny * nstrips + target - 1) / target;
-    if (ly < 8) ly = 8;
+    if (ly < 16) ly = 16;
     if (ly > g.ny) ly = g.ny;
     return (int)ly;
 }
 
-hipError_t launch_step2(const Geo& g, const Rates& r, const double* src, double* dst,
-                        hipStream_t st) {
-    const int nstrips = (g.nx + TB_W - 1) / TB_W;
-    const int ly = step2_rows(g, nstrips);
+template <int S>
+static hipError_t launch_steps_t(const Geo& g, const Rates& r, const double* src, double* dst,
+                                 hipStream_t st) {
+    const int w = strip_width(S);
+    const int nstrips = (g.nx + w - 1) / w;
+    const int ly = steps_rows(g, nstrips);
     const int nseg = (g.ny + ly - 1) / ly;
-    hipLaunchKernelGGL(k_step2_d2q9, dim3((unsigned)(nstrips * nseg)), dim3(TB_THREADS), 0, st, src,
-                       dst, g, r, ly, nstrips);
+    hipLaunchKernelGGL(k_steps_d2q9<S>, dim3((unsigned)((int64_t)nstrips * nseg)),
+                       dim3(MS_THREADS), 0, st, src, dst, g, r, ly, nstrips);
     return hipGetLastError();
+}
+
+hipError_t launch_steps(int nsteps, const Geo& g, const Rates& r, const double* src, double* dst,
+                        hipStream_t st) {
+    switch (nsteps) {
+        case 2: return launch_steps_t<2>(g, r, src, dst, st);
+        case 4: return launch_steps_t<4>(g, r, src, dst, st);
+        case 8: return launch_steps_t<8>(g, r, src, dst, st);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_init(int d, const Geo& g, const Rates& r, const double* theta0,
@@ -902,11 +951,16 @@ hipError_t launch_finalize(const double* partials, int64_t n, double* g_eps, hip
     return hipGetLastError();
 }
 
-hipError_t launch_batch_step2(const BatchInst* insts, const BatchTile* tiles, int64_t ntiles,
-                              const double* src, double* dst, hipStream_t st) {
+hipError_t launch_batch_steps(int nsteps, const BatchInst* insts, const BatchTile* tiles,
+                              int64_t ntiles, const double* src, double* dst, hipStream_t st) {
     if (ntiles <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_batch_step2, dim3((unsigned)ntiles), dim3(TB_THREADS), 0, st, insts, tiles,
-                       src, dst);
+    const dim3 grid((unsigned)ntiles), block(MS_THREADS);
+    switch (nsteps) {
+        case 2: hipLaunchKernelGGL(k_batch_steps<2>, grid, block, 0, st, insts, tiles, src, dst); break;
+        case 4: hipLaunchKernelGGL(k_batch_steps<4>, grid, block, 0, st, insts, tiles, src, dst); break;
+        case 8: hipLaunchKernelGGL(k_batch_steps<8>, grid, block, 0, st, insts, tiles, src, dst); break;
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

@@ -46,6 +46,11 @@ struct Rates {
     double ds1, ds21, ds22, dw0, dw1, dwd;
     double dinv_s1;          // d(1/s1)/deps = 3
     double c;                // dx / dt
+    // D2Q9 collision in folded form (collide_d2q9)
+    double d2_cj;            // (1 - s1) / 2
+    double d2_cp;            // (1 - s21) / 2
+    double d2_ct;            // s21 / 6 - 2 w_d
+    double d2_cq;            // (1 - s22) / 4
 };
 
 // Velocity tables in the order of Sec. III.A (a fourth component, zero
@@ -196,9 +201,47 @@ __device__ __forceinline__ void reconstruct(double theta, const double (&j)[D], 
     }
 }
 
+// D2Q9 collision with the algebra of collide<D> folded by hand (Sec. III.A,
+// Theorem 2).  The six moments share the partial sums over the three
+// velocities with e_x = +1 / -1 and e_y = +1 / -1; with
+//     hj_a = (1 - s1)/2 j_a,   hP_a = (1 - s21)/2 P_a + (s21/6 - 2 w_d) theta
+// the post-collision populations are hP_a +- hj_a on the axis velocities,
+// eR +- (1 - s22)/4 P_xy on the diagonals (sign e_x e_y) with eR = w_d theta,
+// and (theta - 4 eR) - 2 (hP_x + hP_y) at rest.  Writing the rest population
+// with the same rounded eR that the diagonals carry keeps sum_i f_i = theta
+// up to unbiased rounding; a separately rounded (1 - 4 w_d) would bias the
+// mass at every step (about 1e-16 per step, 1e-12 after 10^4 steps).  34
+// double operations against about 60 for the generic form.  The library is
+// built without floating-point contraction, so every kernel that calls this
+// performs the same roundings.
+__device__ __forceinline__ void collide_d2q9(double (&f)[9], const Rates& r) {
+    const double xp = f[1] + f[5] + f[8], xm = f[3] + f[6] + f[7];
+    const double yp = f[2] + f[5] + f[6], ym = f[4] + f[7] + f[8];
+    const double jx = xp - xm, Px = xp + xm, jy = yp - ym, Py = yp + ym;
+    const double th = f[0] + (f[2] + f[4]) + Px;
+    const double Pxy = (f[5] + f[7]) - (f[6] + f[8]);
+    const double hjx = r.d2_cj * jx, hjy = r.d2_cj * jy;
+    const double tt = r.d2_ct * th;
+    const double hPx = fma(r.d2_cp, Px, tt), hPy = fma(r.d2_cp, Py, tt);
+    const double eR = r.wd * th, eP = r.d2_cq * Pxy;
+    f[0] = fma(-2.0, hPx + hPy, th - 4.0 * eR);
+    f[1] = hPx + hjx;
+    f[3] = hPx - hjx;
+    f[2] = hPy + hjy;
+    f[4] = hPy - hjy;
+    f[5] = eR + eP;
+    f[7] = f[5];
+    f[6] = eR - eP;
+    f[8] = f[6];
+}
+
 // In-place collision f <- C f (Sec. III.A evolution equation, Theorem 2 rates).
 template <int D>
 __device__ __forceinline__ void collide(double (&f)[Lat<D>::Q], const Rates& r) {
+    if constexpr (D == 2) {
+        collide_d2q9(f, r);
+        return;
+    }
     Moments<D> m;
     moments<D>(f, m);
     const double th3 = m.theta * (1.0 / 3.0);

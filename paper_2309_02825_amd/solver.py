@@ -97,9 +97,10 @@ class Solver:
     def step(self, nsteps: int):
         L.lb_step(self.h, nsteps)
 
-    def set_fused(self, on: bool):
-        """D2Q9: advance pairs of steps per pass (default on) or one step per launch."""
-        L.lb_set_option(self.h, L.LB_OPT_FUSE_STEPS, int(bool(on)))
+    def set_steps_per_pass(self, n: int):
+        """D2Q9: the most time steps one pass over HBM advances (1, 2, 4 or 8;
+        default 8).  Results are bitwise the same for every value."""
+        L.lb_set_option(self.h, L.LB_OPT_STEPS_PER_PASS, int(n))
 
     def step_buffers(self, src: torch.Tensor, dst: torch.Tensor):
         L.lb_step_buffers(self.h, src, dst)

@@ -227,25 +227,28 @@ def test_resident_1d_run_equals_per_step_launches():
         assert np.array_equal(outs[0], outs[1]), n
 
 
-@pytest.mark.parametrize("grid,steps", [((4096, 64), 6), ((1000, 333), 5), ((130, 67), 9),
-                                         ((128, 8), 4), ((7, 1), 6), ((1, 5), 4), ((300, 2), 8)])
-def test_fused_two_step_pass_equals_single_steps(grid, steps):
-    """D2Q9 lb_step advances pairs of steps in one pass (temporal blocking);
-    the state is bitwise that of one launch per step, for ragged strips and
-    segments, odd step counts and degenerate grids."""
-    _say("fused vs single", grid, steps)
+@pytest.mark.parametrize("grid,steps", [((4096, 64), 23), ((1000, 333), 15), ((130, 67), 9),
+                                         ((128, 8), 17), ((7, 1), 14), ((1, 5), 12), ((300, 2), 8),
+                                         ((112, 40), 16), ((113, 3), 31)])
+def test_multi_step_passes_equal_single_steps(grid, steps):
+    """D2Q9 lb_step advances up to 8 steps in one pass (temporal blocking);
+    the state is bitwise that of one launch per step for every pass limit,
+    for ragged strips and segments, step counts that mix 8-, 4-, 2- and
+    single-step launches, and degenerate grids."""
+    _say("multi-step vs single", grid, steps)
     SV = _solver_mod()
     dx, dt, nu, th0, _ = _problem(grid, "random")
     outs = []
-    for fused in (True, False):
+    for spp in (1, 2, 4, 8):
         s = SV.Solver(grid, dx, dt, nu, device=_dev())
-        s.set_fused(fused)
+        s.set_steps_per_pass(spp)
         s.init(torch.from_numpy(th0).to(_dev()), None)
         s.step(steps)
         outs.append(s.get_state().cpu().numpy())
         assert s.steps == steps
         s.close()
-    assert np.array_equal(outs[0], outs[1])
+    for o in outs[1:]:
+        assert np.array_equal(outs[0], o)
 
 
 def test_run_to_run_bitwise_determinism():
@@ -377,7 +380,17 @@ def test_adjoint_matches_oracle(n, steps, nseg):
     torch.cuda.synchronize()
     assert abs(loss.item() - L_o) <= 1e-12 * L_o
     assert max_rel(th0_t.grad.cpu().numpy(), g_o) <= 1e-12
-    assert abs(nu_t.grad.item() - gnu_o) <= 1e-11 * abs(gnu_o)
+    # dL/dnu is a sum over nodes and steps that can cancel heavily (16^2,
+    # 60 steps: the oracle's own value moves by ~1e-10 relative when theta0
+    # is perturbed at the rounding level), so its bound is the larger of
+    # 1e-11 and ten times that sensitivity, measured on the oracle alone
+    rng = np.random.Generator(np.random.PCG64(7))
+    sens = 0.0
+    for _ in range(3):
+        th_p = th0 * (1.0 + 2e-16 * rng.standard_normal(th0.shape))
+        gnu_p = O.velocity_loss_and_grad(th_p, u_t, dx, dt, nu, steps)[2]
+        sens = max(sens, abs(gnu_p - gnu_o) / abs(gnu_o))
+    assert abs(nu_t.grad.item() - gnu_o) <= max(1e-11, 10.0 * sens) * abs(gnu_o)
 
 
 def test_adjoint_full_size_against_central_differences():
@@ -445,7 +458,17 @@ def test_adjoint_matches_oracle_other_lattices(grid, steps):
     torch.cuda.synchronize()
     assert abs(loss.item() - L_o) <= 1e-12 * L_o
     assert max_rel(th0_t.grad.cpu().numpy(), g_o) <= 1e-12
-    assert abs(nu_t.grad.item() - gnu_o) <= 1e-11 * abs(gnu_o)
+    # dL/dnu is a sum over nodes and steps that can cancel heavily (16^2,
+    # 60 steps: the oracle's own value moves by ~1e-10 relative when theta0
+    # is perturbed at the rounding level), so its bound is the larger of
+    # 1e-11 and ten times that sensitivity, measured on the oracle alone
+    rng = np.random.Generator(np.random.PCG64(7))
+    sens = 0.0
+    for _ in range(3):
+        th_p = th0 * (1.0 + 2e-16 * rng.standard_normal(th0.shape))
+        gnu_p = O.velocity_loss_and_grad(th_p, u_t, dx, dt, nu, steps)[2]
+        sens = max(sens, abs(gnu_p - gnu_o) / abs(gnu_o))
+    assert abs(nu_t.grad.item() - gnu_o) <= max(1e-11, 10.0 * sens) * abs(gnu_o)
 
 
 def test_adjoint_dot_product_on_gpu():
@@ -497,10 +520,11 @@ def test_batch_matches_single_instance_runs():
     th0s = [torch.from_numpy(W.evaluate(p.modes, p.grid, p.dx)[0]) for p in insts]
     grs = [torch.from_numpy(W.evaluate(p.modes, p.grid, p.dx)[1]) for p in insts]
     bs.init(th0s, grs)
-    # one-step tiles, then two-step tiles (strips wider than some instances,
+    # one-step tiles, then multi-step tiles (strips wider than some instances,
     # segments taller than some, odd counts that end on a linear-tile step)
     plan = ((64, 4, 10, True), (256, 1, 10, False), (16, 16, 10, True), (0, 0, 10, True),
-            (-1, 16, 7, True), (-1, 5, 6, False), (-1, 64, 3, True), (-1, 1, 5, False))
+            (-8, 16, 19, True), (-4, 5, 6, False), (-2, 64, 3, True), (-8, 1, 5, False),
+            (-8, 200, 8, True))
     for tx, ty, n, graph in plan:
         bs.set_tile(tx, ty)
         bs.step(n, graph=graph)
@@ -515,11 +539,11 @@ def test_batch_matches_single_instance_runs():
     bs.close()
 
 
-def test_batch_two_step_degenerate_shapes():
-    """Two-step tiles on instances narrower than a strip, with one or two
+def test_batch_multi_step_degenerate_shapes():
+    """Multi-step tiles on instances narrower than a strip, with one or two
     rows, one column, or a ragged last strip and segment; rough fields and
     difference-gradient init; bitwise equal to single-instance runs."""
-    _say("batch two-step degenerate shapes")
+    _say("batch multi-step degenerate shapes")
     SV = _solver_mod()
     rng = np.random.Generator(np.random.PCG64(11))
     shapes = [(1, 5), (7, 1), (2, 2), (130, 3), (129, 1), (257, 129), (128, 64), (1, 1)]
@@ -533,8 +557,8 @@ def test_batch_two_step_degenerate_shapes():
     bs = SV.BatchSolver(probs, device=_dev())
     bs.init(th0s, None)
     total = 0
-    for ty, n in ((64, 9), (2, 4), (200, 5)):
-        bs.set_tile(-1, ty)
+    for tx, ty, n in ((-8, 64, 9), (-2, 2, 4), (-8, 200, 21), (-4, 3, 7), (-8, 1, 8)):
+        bs.set_tile(tx, ty)
         bs.step(n, graph=True)
         total += n
     ths, us = bs.macro()
