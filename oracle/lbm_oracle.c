@@ -18,7 +18,8 @@
  *   - velocities are kept in lattice units e_i in {-1,0,1}^d; c = dx/dt.
  *     Scaling the rows of M by powers of c leaves M^-1 S M unchanged because
  *     S is diagonal, so M is built from e_i.
- *   - periodic boundaries in every direction (Examples 2-4 of Sec. IV).
+ *   - periodic boundaries in every direction (Examples 2-4 of Sec. IV), and
+ *     for d = 1 the bounded interval of Example 1 (oracle_run_dirichlet1).
  *
  * Readings of the paper taken here (listed with their justification in the
  * design notes of the repository):
@@ -450,6 +451,55 @@ int oracle_run(int d, const int64_t* n, double dx, double dt, double nu,
             for (int i = 0; i < q; ++i) tmp[i * V + shifted(&G, k, L.e[i])] = fout[i];
         }
         memcpy(f, tmp, sizeof(double) * (size_t)q * (size_t)V);
+    }
+    free(tmp);
+    return 0;
+}
+
+/* Example 1 of Sec. IV on the bounded interval: n nodes x_j = j dx,
+ * j = 0..n-1, with the end nodes on the boundary, where theta is given.
+ * One step: collide at every node, push f*_i to x + e_i where that node
+ * exists (populations leaving the interval are dropped), then give each end
+ * node the one population the push could not deliver (the one pointing into
+ * the interval) the value that makes sum_i f_i equal the boundary theta at
+ * the new time:
+ *   f_{+1}(x_0)     = theta_left  - f_0(x_0)     - f_{-1}(x_0),
+ *   f_{-1}(x_{n-1}) = theta_right - f_0(x_{n-1}) - f_{+1}(x_{n-1}).
+ * walls holds 2 * nsteps values, (theta_left, theta_right) at t + dt,
+ * t + 2 dt, ...  f is 3 x n (pre-collision), advanced in place. */
+int oracle_run_dirichlet1(int64_t n, double dx, double dt, double nu, double* f, int64_t nsteps,
+                          const double* walls) {
+    or_lattice L;
+    if (n < 2 || !(dx > 0) || !(dt > 0) || !(nu > 0) || nsteps < 0 || (nsteps > 0 && !walls))
+        return -1;
+    if (build_lattice(1, nu * dt / (dx * dx), &L) != 0) return -1;
+    const int q = L.q;
+    double* tmp = (double*)malloc(sizeof(double) * (size_t)q * (size_t)n);
+    if (!tmp) return -4;
+    for (int64_t s = 0; s < nsteps; ++s) {
+        for (int64_t k = 0; k < n; ++k) {
+            double fin[OR_MAXQ], fout[OR_MAXQ];
+            for (int i = 0; i < q; ++i) fin[i] = f[i * n + k];
+            collide_node(&L, fin, fout);
+            for (int i = 0; i < q; ++i) {
+                const int64_t to = k + L.e[i][0];
+                if (to >= 0 && to < n) tmp[i * n + to] = fout[i];
+            }
+        }
+        for (int i = 0; i < q; ++i) {
+            if (L.e[i][0] == 1) {
+                double rest = 0.0;
+                for (int j = 0; j < q; ++j)
+                    if (j != i) rest += tmp[j * n + 0];
+                tmp[i * n + 0] = walls[2 * s] - rest;
+            } else if (L.e[i][0] == -1) {
+                double rest = 0.0;
+                for (int j = 0; j < q; ++j)
+                    if (j != i) rest += tmp[j * n + n - 1];
+                tmp[i * n + n - 1] = walls[2 * s + 1] - rest;
+            }
+        }
+        memcpy(f, tmp, sizeof(double) * (size_t)q * (size_t)n);
     }
     free(tmp);
     return 0;

@@ -50,6 +50,7 @@ def _load():
         "oracle_adjoint_run": ([I, _i64p, D, D, D, _dp, I64, _dp, _dp], I),
         "oracle_init_adjoint": ([I, _i64p, D, D, D, _dp, _dp, _dp, _dp, _dp, _dp], I),
         "oracle_theta_from_velocity": ([I, _i64p, D, D, _dp, _dp, _dp], I),
+        "oracle_run_dirichlet1": ([I64, D, D, D, _dp, I64, _dp], I),
     }
     for name, (args, res) in sigs.items():
         fn = getattr(lib, name)
@@ -156,6 +157,17 @@ def run(f: np.ndarray, dx: float, dt: float, nu: float, nsteps: int) -> np.ndarr
     f = np.array(f, dtype=np.float64, order="C", copy=True)
     d, n = _dims(f.shape[1:])
     _check(_load().oracle_run(d, n, dx, dt, nu, _ptr(f), int(nsteps)), "run")
+    return f
+
+
+def run_dirichlet1(f: np.ndarray, dx: float, dt: float, nu: float, walls: np.ndarray) -> np.ndarray:
+    """Example 1 of Sec. IV: 1-D interval with end nodes on the boundary and
+    theta given there; walls is (nsteps, 2) = (left, right) at t + dt, ..."""
+    f = np.array(f, dtype=np.float64, order="C", copy=True)
+    assert f.ndim == 2 and f.shape[0] == 3
+    walls = np.ascontiguousarray(walls, dtype=np.float64).reshape(-1, 2)
+    _check(_load().oracle_run_dirichlet1(f.shape[1], dx, dt, nu, _ptr(f), walls.shape[0],
+                                         _ptr(walls)), "run_dirichlet1")
     return f
 
 

@@ -18,7 +18,7 @@ from __future__ import annotations
 
 import math
 from dataclasses import dataclass, field
-from typing import List, Sequence, Tuple
+from typing import List, Optional, Sequence, Tuple
 
 import numpy as np
 
@@ -216,6 +216,63 @@ def paper_example4(level: int, eps: float, t_end: float) -> Workload:
     modes = constant(2.0, 4) + trig_product(["sin"] * 4, [1, 2, 3, 4])
     return Workload(f"ex4_eps{eps}_t{t_end}_l{level}", (n,) * 4, dx, dt, nu, modes,
                     int(round(t_end / dt)))
+
+
+def paper_example1(level: int, eps: float) -> Workload:
+    """Example 1 (Sec. IV): 1-D Burgers on [0, 1] with u(x, 0) = sin(pi x) and
+    u(0, t) = u(1, t) = 0, run to t = 2.  Level l: dx = (1/40)/2^l,
+    dt = (1/100)/4^l, nu = eps dx^2/dt; nodes x_j = j dx, j = 0..1/dx (both
+    ends on the boundary).  theta0 and the boundary values come from
+    example1_theta0 and example1_exact (not a finite Fourier sum)."""
+    dx = 1.0 / (40 * 2 ** level)
+    dt = 1.0 / (100 * 4 ** level)
+    n = int(round(1.0 / dx)) + 1
+    nu = eps * dx * dx / dt
+    return Workload(f"ex1_eps{eps}_l{level}", (n,), dx, dt, nu, [], int(round(2.0 / dt)),
+                    extra={"bounded": True})
+
+
+def example1_theta0(wl: Workload):
+    """theta0 = exp(cos(pi x)/(2 pi nu)) and its derivative at the nodes: the
+    Cole-Hopf image of u0 = sin(pi x), scaled to the exact solution's
+    normalisation (theta = a_0 + 2 sum a_n e^{-n^2 pi^2 nu t} cos(n pi x),
+    a_n = I_n(1/(2 pi nu)), whose t = 0 value is this exponential)."""
+    x = np.arange(wl.grid[0]) * wl.dx
+    z = 1.0 / (2.0 * math.pi * wl.nu)
+    th = np.exp(z * np.cos(math.pi * x))
+    g = -z * math.pi * np.sin(math.pi * x) * th
+    return th, g[None]
+
+
+def example1_exact(nu: float, x: np.ndarray, t: float, nterms: int = 200):
+    """Exact theta and u of Example 1 at points x and time t (the series of
+    Sec. IV with modified Bessel coefficients a_n = I_n(1/(2 pi nu)))."""
+    from scipy.special import ive  # I_n(z) e^{-z}
+    z = 1.0 / (2.0 * math.pi * nu)
+    x = np.asarray(x, dtype=np.float64)
+    k = np.arange(1, nterms)
+    a = ive(k, z) * np.exp(-(k ** 2) * math.pi ** 2 * nu * t)
+    cos = np.cos(np.outer(k, math.pi * x))
+    sin = np.sin(np.outer(k, math.pi * x))
+    th = ive(0, z) + 2.0 * (a @ cos)
+    thx = -2.0 * ((a * k * math.pi) @ sin)
+    return th * math.exp(z), -2.0 * nu * thx / th
+
+
+def example1_walls(wl: Workload, nsteps: Optional[int] = None, first: int = 1,
+                   nterms: int = 200) -> np.ndarray:
+    """Boundary theta (left, right) of Example 1 at the times (first + s) dt,
+    s = 0..nsteps-1: an (nsteps, 2) array (the series of example1_exact at
+    x = 0, where cos(n pi x) = 1, and x = 1, where it is (-1)^n)."""
+    from scipy.special import ive
+    nsteps = wl.nsteps if nsteps is None else nsteps
+    z = 1.0 / (2.0 * math.pi * wl.nu)
+    k = np.arange(1, nterms)
+    t = (first + np.arange(nsteps)) * wl.dt
+    a = ive(k, z)[None, :] * np.exp(-np.outer(t, k ** 2) * math.pi ** 2 * wl.nu)
+    left = ive(0, z) + 2.0 * a.sum(axis=1)
+    right = ive(0, z) + 2.0 * (a * (-1.0) ** k).sum(axis=1)
+    return np.stack([left, right], axis=1) * math.exp(z)
 
 
 def random_fourier_modes(rng: np.random.Generator, d: int = 2, nmodes: int = 8,
