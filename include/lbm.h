@@ -7,7 +7,9 @@
  * D1Q3 / D2Q9 / D3Q19 / D4Q33 natural-moment MRT-LB model of Sec. III.A, using the
  * relaxation rates and weights of Theorem 2 (Sec. III.D) that make the scheme
  * and the velocity u = -2 nu grad(theta)/theta fourth-order accurate.  All
- * arithmetic is IEEE double precision on the GPU; boundaries are periodic.
+ * arithmetic is IEEE double precision on the GPU.  Boundaries are periodic;
+ * a 1-D solver can instead span a closed interval whose end nodes carry a
+ * given theta (LB_FLAG_BOUNDED, Example 1 of Sec. IV).
  *
  * Conventions shared by every entry point
  *   - Every function returns lb_status: LB_OK (0) or a negative error code.
@@ -73,12 +75,23 @@ typedef struct lb_batch lb_batch;   /* opaque, library-owned host object */
 
 typedef struct {
     int32_t dim;     /* 1, 2, 3 or 4 */
-    int32_t flags;   /* reserved, must be 0 */
+    int32_t flags;   /* 0 (periodic) or LB_FLAG_BOUNDED */
     int64_t n[4];    /* nodes per axis, >= 1; n[a] = 1 for a >= dim */
     double dx;       /* node spacing, > 0 */
     double dt;       /* time step, > 0 */
     double nu;       /* viscosity of the Burgers equations (Sec. II), > 0 */
 } lb_config;
+
+/* lb_config.flags: the n[0] nodes x_j = j dx, j = 0..n[0]-1, of a 1-D grid
+ * span a closed interval with both end nodes on the boundary, where theta is
+ * prescribed (Example 1 of Sec. IV: the Burgers velocity vanishes there and
+ * theta follows from the exact solution).  After each push the one population
+ * that would enter an end node from outside takes the value that makes
+ * sum_i f_i equal that node's boundary theta.  Requires dim = 1 and
+ * n[0] >= 2.  Such a solver steps with lb_step_bounded; lb_step,
+ * lb_step_buffers, lb_macro_buffer, lb_theta_from_velocity and the adjoint
+ * calls return LB_ERR_STATE, and the batched form rejects the flag. */
+#define LB_FLAG_BOUNDED 1
 
 /* Relaxation rates and weights of Theorem 2 (Sec. III.D) for a config:
  * s1 = 2/(6 eps + 1), s21 = 24 eps/(6 eps + 1)^2 (s2 when d = 1),
@@ -115,7 +128,9 @@ lb_status lb_create(const lb_config* cfg, void* hip_stream, double* f_a, double*
  * (-theta(x+2) + 8 theta(x+1) - 8 theta(x-1) + theta(x-2)) / (12 dx).
  * Writes f_a and resets the step counter.  If check_theta != 0 the call also
  * verifies theta0 > 0 and finite (Cole-Hopf needs theta > 0, Sec. II) and
- * returns LB_ERR_NONFINITE otherwise; the check synchronises the stream. */
+ * returns LB_ERR_NONFINITE otherwise; the check synchronises the stream.
+ * LB_FLAG_BOUNDED: grad_theta0 is required (LB_ERR_INVALID_ARG if NULL), and
+ * theta0 at the two end nodes becomes the boundary theta of time 0. */
 lb_status lb_init(lb_solver* s, const double* theta0, const double* grad_theta0,
                   int32_t check_theta);
 
@@ -136,6 +151,15 @@ lb_status lb_theta_from_velocity(lb_solver* s, const double* u0, double* theta0,
 /* Advance nsteps >= 0 time steps (evolution equation of Sec. III.A: collide in
  * moment space, then stream), alternating the two buffers. */
 lb_status lb_step(lb_solver* s, int64_t nsteps);
+
+/* LB_FLAG_BOUNDED solvers: advance nsteps >= 0 time steps on the interval.
+ * walls is a device array of 2 * nsteps doubles, the boundary theta
+ * (left end, right end) at t + dt, t + 2 dt, ..., t + nsteps dt, where t is
+ * the current time; the last pair is kept as the boundary theta of the new
+ * current time (used by lb_macro and lb_get_state).  Grids of up to 2048
+ * nodes run all steps in one launch with the state in LDS.  LB_ERR_STATE on a
+ * periodic solver or before lb_init / lb_set_state. */
+lb_status lb_step_bounded(lb_solver* s, int64_t nsteps, const double* walls);
 
 /* Options of a solver (lb_set_option).
  * LB_OPT_STEPS_PER_PASS (default 8): on D2Q9, the most time steps lb_step
@@ -164,18 +188,24 @@ int64_t lb_steps_taken(const lb_solver* s);
  *   u_a   = (2 - s1) sum_i c_{ia} f^ne_i / theta,  f^ne = f - w theta,
  * which equals -2 nu d_a theta / theta with the fourth-order gradient
  * d_a theta = -(s1/(dt c_s^2)) sum_i c_{ia} f^ne_i.  theta (V) or u (d x V)
- * may be NULL. */
+ * may be NULL.  LB_FLAG_BOUNDED: the end nodes' distribution is completed
+ * with the current boundary theta, so theta there equals it. */
 lb_status lb_macro(lb_solver* s, double* theta, double* u);
 
 /* Same as lb_macro for an explicit state buffer in the storage layout. */
 lb_status lb_macro_buffer(lb_solver* s, const double* state, double* theta, double* u);
 
 /* Copy the current pre-collision distribution to f_out in the dense
- * canonical layout (q planes of V doubles, f_out[i*V + k] = f_i(node k)). */
+ * canonical layout (q planes of V doubles, f_out[i*V + k] = f_i(node k)).
+ * LB_FLAG_BOUNDED: the population entering each end node is the one the
+ * boundary theta determines. */
 lb_status lb_get_state(lb_solver* s, double* f_out);
 
 /* Load a dense canonical distribution (q x V) as the current state and set
- * the step counter to step. */
+ * the step counter to step.  LB_FLAG_BOUNDED: the boundary theta of the
+ * current time becomes sum_i f_i at each end node, and the population
+ * entering an end node is kept only through that sum (lb_get_state returns
+ * it to rounding). */
 lb_status lb_set_state(lb_solver* s, const double* f_in, int64_t step);
 
 /* Copy a dense q x V array (dense[i*V + k] for population i of node k) into

@@ -107,7 +107,9 @@ double eps_limit(int d) {
 lb_status validate(const lb_config* c) {
     if (!c) return fail(LB_ERR_INVALID_ARG, "config is NULL");
     if (c->dim < 1 || c->dim > 4) return fail(LB_ERR_INVALID_ARG, "dim must be 1, 2, 3 or 4");
-    if (c->flags != 0) return fail(LB_ERR_INVALID_ARG, "flags must be 0");
+    if (c->flags & ~LB_FLAG_BOUNDED) return fail(LB_ERR_INVALID_ARG, "unknown flags");
+    if ((c->flags & LB_FLAG_BOUNDED) && (c->dim != 1 || c->n[0] < 2))
+        return fail(LB_ERR_INVALID_ARG, "LB_FLAG_BOUNDED needs dim = 1 and n[0] >= 2");
     int64_t V = 1;
     for (int a = 0; a < 4; ++a) {
         if (c->n[a] < 1) return fail(LB_ERR_INVALID_ARG, "every n[a] must be >= 1");
@@ -164,7 +166,14 @@ struct lb_solver {
     int64_t npartials;
     int* flag;
     int steps_per_pass;  // LB_OPT_STEPS_PER_PASS: 1, 2, 4 or 8
+    bool bounded;        // LB_FLAG_BOUNDED
+    double* wall_now;    // bounded: theta at the two end nodes at the current time
 };
+
+static lb_status not_bounded(const lb_solver* s, const char* what) {
+    if (s->bounded) return fail(LB_ERR_STATE, what);
+    return LB_OK;
+}
 
 extern "C" {
 
@@ -228,10 +237,14 @@ lb_status lb_create(const lb_config* cfg, void* hip_stream, double* f_a, double*
     s->npartials = lbm::launch_shape(s->d, s->g).nblocks;
     s->partials = nullptr;
     s->flag = nullptr;
+    s->bounded = (cfg->flags & LB_FLAG_BOUNDED) != 0;
+    s->wall_now = nullptr;
     hipError_t e = hipMalloc((void**)&s->partials, sizeof(double) * (size_t)s->npartials);
     if (e == hipSuccess) e = hipMalloc((void**)&s->flag, sizeof(int));
+    if (e == hipSuccess && s->bounded) e = hipMalloc((void**)&s->wall_now, 2 * sizeof(double));
     if (e != hipSuccess) {
         if (s->partials) (void)hipFree(s->partials);
+        if (s->flag) (void)hipFree(s->flag);
         delete s;
         return hip_fail(e, "hipMalloc of solver tables");
     }
@@ -243,6 +256,7 @@ lb_status lb_destroy(lb_solver* s) {
     if (!s) return LB_OK;
     if (s->partials) (void)hipFree(s->partials);
     if (s->flag) (void)hipFree(s->flag);
+    if (s->wall_now) (void)hipFree(s->wall_now);
     delete s;
     return LB_OK;
 }
@@ -261,12 +275,22 @@ static lb_status check_theta(lb_solver* s, const double* theta, int64_t n) {
 lb_status lb_init(lb_solver* s, const double* theta0, const double* grad_theta0,
                   int32_t check) {
     if (!s || !theta0) return fail(LB_ERR_INVALID_ARG, "solver and theta0 must not be NULL");
+    if (s->bounded && !grad_theta0)
+        return fail(LB_ERR_INVALID_ARG, "a bounded interval needs grad_theta0");
     if (check) {
         lb_status st = check_theta(s, theta0, s->g.V);
         if (st != LB_OK) return st;
     }
     LB_HIP(lbm::launch_init(s->d, s->g, s->r, theta0, grad_theta0, s->buf[0], s->stream),
            "init launch");
+    if (s->bounded) {
+        LB_HIP(hipMemcpyAsync(s->wall_now, theta0, sizeof(double), hipMemcpyDeviceToDevice,
+                              s->stream),
+               "hipMemcpyAsync");
+        LB_HIP(hipMemcpyAsync(s->wall_now + 1, theta0 + (s->g.nx - 1), sizeof(double),
+                              hipMemcpyDeviceToDevice, s->stream),
+               "hipMemcpyAsync");
+    }
     s->cur = 0;
     s->steps = 0;
     s->inited = true;
@@ -277,12 +301,13 @@ lb_status lb_step(lb_solver* s, int64_t nsteps) {
     if (!s) return fail(LB_ERR_INVALID_ARG, "solver is NULL");
     if (nsteps < 0) return fail(LB_ERR_INVALID_ARG, "nsteps must be >= 0");
     if (!s->inited) return fail(LB_ERR_STATE, "lb_step before lb_init/lb_set_state");
+    if (s->bounded) return fail(LB_ERR_STATE, "a bounded interval steps with lb_step_bounded");
     if (s->d == 1 && s->g.nx <= lbm::RESIDENT_MAX_1D && nsteps >= 2) {
         // whole run in one launch; the result lands where the per-step
         // ping-pong would have left it
         const int dst = s->cur ^ (int)(nsteps & 1);
         LB_HIP(lbm::launch_step_resident1(s->g, s->r, s->buf[s->cur], s->buf[dst], nsteps,
-                                          s->stream),
+                                          nullptr, nullptr, s->stream),
                "resident step launch");
         s->cur = dst;
         s->steps += nsteps;
@@ -309,6 +334,35 @@ lb_status lb_step(lb_solver* s, int64_t nsteps) {
     return LB_OK;
 }
 
+lb_status lb_step_bounded(lb_solver* s, int64_t nsteps, const double* walls) {
+    if (!s) return fail(LB_ERR_INVALID_ARG, "solver is NULL");
+    if (!s->bounded) return fail(LB_ERR_STATE, "the solver was not created with LB_FLAG_BOUNDED");
+    if (nsteps < 0) return fail(LB_ERR_INVALID_ARG, "nsteps must be >= 0");
+    if (!s->inited) return fail(LB_ERR_STATE, "lb_step_bounded before lb_init/lb_set_state");
+    if (nsteps == 0) return LB_OK;
+    if (!walls) return fail(LB_ERR_INVALID_ARG, "walls is NULL");
+    if (s->g.nx <= lbm::RESIDENT_MAX_1D) {
+        const int dst = s->cur ^ (int)(nsteps & 1);
+        LB_HIP(lbm::launch_step_resident1(s->g, s->r, s->buf[s->cur], s->buf[dst], nsteps, walls,
+                                          s->wall_now, s->stream),
+               "resident step launch");
+        s->cur = dst;
+    } else {
+        for (int64_t n = 0; n < nsteps; ++n) {
+            const double* wall = n == 0 ? s->wall_now : walls + 2 * (n - 1);
+            LB_HIP(lbm::launch_step_wall1(s->g, s->r, s->buf[s->cur], s->buf[1 - s->cur], wall,
+                                          s->stream),
+                   "step launch");
+            s->cur ^= 1;
+        }
+        LB_HIP(hipMemcpyAsync(s->wall_now, walls + 2 * (nsteps - 1), 2 * sizeof(double),
+                              hipMemcpyDeviceToDevice, s->stream),
+               "hipMemcpyAsync");
+    }
+    s->steps += nsteps;
+    return LB_OK;
+}
+
 lb_status lb_set_option(lb_solver* s, int32_t option, int32_t value) {
     if (!s) return fail(LB_ERR_INVALID_ARG, "solver is NULL");
     switch (option) {
@@ -326,6 +380,8 @@ lb_status lb_set_option(lb_solver* s, int32_t option, int32_t value) {
 lb_status lb_step_buffers(lb_solver* s, const double* src, double* dst) {
     if (!s || !src || !dst) return fail(LB_ERR_INVALID_ARG, "NULL argument");
     if (src == dst) return fail(LB_ERR_INVALID_ARG, "src and dst must differ");
+    lb_status st = not_bounded(s, "lb_step_buffers is periodic only");
+    if (st != LB_OK) return st;
     LB_HIP(lbm::launch_step(s->d, s->g, s->r, src, dst, s->stream), "step launch");
     return LB_OK;
 }
@@ -335,6 +391,8 @@ int64_t lb_steps_taken(const lb_solver* s) { return s ? s->steps : -1; }
 
 lb_status lb_macro_buffer(lb_solver* s, const double* state, double* theta, double* u) {
     if (!s || !state) return fail(LB_ERR_INVALID_ARG, "NULL argument");
+    lb_status st = not_bounded(s, "lb_macro_buffer is periodic only (use lb_macro)");
+    if (st != LB_OK) return st;
     if (!theta && !u) return LB_OK;
     LB_HIP(lbm::launch_macro(s->d, s->g, s->r, state, theta, u, s->stream), "macro launch");
     return LB_OK;
@@ -343,13 +401,24 @@ lb_status lb_macro_buffer(lb_solver* s, const double* state, double* theta, doub
 lb_status lb_macro(lb_solver* s, double* theta, double* u) {
     if (!s) return fail(LB_ERR_INVALID_ARG, "solver is NULL");
     if (!s->inited) return fail(LB_ERR_STATE, "lb_macro before lb_init/lb_set_state");
+    if (s->bounded) {
+        if (!theta && !u) return LB_OK;
+        LB_HIP(lbm::launch_macro_wall1(s->g, s->r, s->buf[s->cur], theta, u, s->wall_now,
+                                       s->stream),
+               "macro launch");
+        return LB_OK;
+    }
     return lb_macro_buffer(s, s->buf[s->cur], theta, u);
 }
 
 lb_status lb_get_state(lb_solver* s, double* f_out) {
     if (!s || !f_out) return fail(LB_ERR_INVALID_ARG, "NULL argument");
     if (!s->inited) return fail(LB_ERR_STATE, "no state yet");
-    LB_HIP(lbm::launch_get_state(s->d, s->g, s->buf[s->cur], f_out, s->stream), "get_state");
+    if (s->bounded)
+        LB_HIP(lbm::launch_get_state_wall1(s->g, s->buf[s->cur], f_out, s->wall_now, s->stream),
+               "get_state");
+    else
+        LB_HIP(lbm::launch_get_state(s->d, s->g, s->buf[s->cur], f_out, s->stream), "get_state");
     return LB_OK;
 }
 
@@ -357,6 +426,8 @@ lb_status lb_set_state(lb_solver* s, const double* f_in, int64_t step) {
     if (!s || !f_in) return fail(LB_ERR_INVALID_ARG, "NULL argument");
     if (step < 0) return fail(LB_ERR_INVALID_ARG, "step must be >= 0");
     LB_HIP(lbm::launch_set_state(s->d, s->g, f_in, s->buf[0], s->stream), "set_state");
+    if (s->bounded)
+        LB_HIP(lbm::launch_wall_from_dense1(s->g, f_in, s->wall_now, s->stream), "set_state walls");
     s->cur = 0;
     s->steps = step;
     s->inited = true;
@@ -377,6 +448,8 @@ lb_status lb_layout_to_dense(lb_solver* s, const double* buf, double* dense) {
 
 lb_status lb_theta_from_velocity(lb_solver* s, const double* u0, double* theta0, double* grad) {
     if (!s || !u0 || !theta0) return fail(LB_ERR_INVALID_ARG, "NULL argument");
+    lb_status st = not_bounded(s, "lb_theta_from_velocity is periodic only");
+    if (st != LB_OK) return st;
     const int64_t nw = lbm::potential_workspace(s->d, s->g);
     double* work = nullptr;
     LB_HIP(hipMalloc((void**)&work, sizeof(double) * (size_t)nw), "hipMalloc potential workspace");
@@ -392,6 +465,8 @@ lb_status lb_theta_from_velocity(lb_solver* s, const double* u0, double* theta0,
 lb_status lb_macro_adjoint(lb_solver* s, const double* state, const double* g_theta,
                            const double* g_u, double* lambda, double* g_eps) {
     if (!s || !state || !lambda || !g_eps) return fail(LB_ERR_INVALID_ARG, "NULL argument");
+    lb_status st = not_bounded(s, "the adjoint is periodic only");
+    if (st != LB_OK) return st;
     LB_HIP(lbm::launch_macro_adjoint(s->d, s->g, s->r, state, g_theta, g_u, lambda, s->partials,
                                      s->stream),
            "macro_adjoint launch");
@@ -404,6 +479,8 @@ lb_status lb_adjoint_step(lb_solver* s, const double* state_n, const double* lam
     if (!s || !state_n || !lambda_in || !lambda_out || !g_eps)
         return fail(LB_ERR_INVALID_ARG, "NULL argument");
     if (lambda_in == lambda_out) return fail(LB_ERR_INVALID_ARG, "lambda_in == lambda_out");
+    lb_status st = not_bounded(s, "the adjoint is periodic only");
+    if (st != LB_OK) return st;
     LB_HIP(lbm::launch_adjoint_step(s->d, s->g, s->r, state_n, lambda_in, lambda_out, s->partials,
                                     s->stream),
            "adjoint_step launch");
@@ -416,6 +493,8 @@ lb_status lb_init_adjoint(lb_solver* s, const double* theta0, const double* grad
                           double* g_eps) {
     if (!s || !theta0 || !lambda0 || !g_theta0 || !g_eps)
         return fail(LB_ERR_INVALID_ARG, "NULL argument");
+    lb_status st = not_bounded(s, "the adjoint is periodic only");
+    if (st != LB_OK) return st;
     LB_HIP(lbm::launch_init_adjoint(s->d, s->g, s->r, theta0, grad_theta0, lambda0, g_theta0,
                                     g_grad, s->partials, s->stream),
            "init_adjoint launch");
@@ -529,6 +608,7 @@ lb_status lb_batch_create(const lb_config* cfgs, int32_t count, void* hip_stream
         lb_status st = validate(&cfgs[i]);
         if (st != LB_OK) return st;
         if (cfgs[i].dim != 2) return fail(LB_ERR_INVALID_ARG, "batched form is 2-D only");
+        if (cfgs[i].flags != 0) return fail(LB_ERR_INVALID_ARG, "batched form is periodic only");
     }
     if (!pool_a || !pool_b || pool_a == pool_b)
         return fail(LB_ERR_INVALID_ARG, "two distinct pools are required");

@@ -56,8 +56,21 @@ hipError_t launch_steps(int nsteps, const Geo& g, const Rates& r, const double* 
 // 1-D grids up to this many nodes run all their steps in one launch with the
 // state in LDS (3 populations x 8 B x 2048 = 48 KiB).
 constexpr int RESIDENT_MAX_1D = 2048;
+// walls != NULL: bounded interval (see launch_step_wall1); wall_now holds the
+// boundary theta of the current time and receives the last pair of walls.
 hipError_t launch_step_resident1(const Geo& g, const Rates& r, const double* src, double* dst,
-                                int64_t nsteps, hipStream_t st);
+                                int64_t nsteps, const double* walls, double* wall_now,
+                                hipStream_t st);
+// 1-D interval whose end nodes carry a given theta (2 doubles at wall: left,
+// right, of the time the step starts from); n >= 2.
+hipError_t launch_step_wall1(const Geo& g, const Rates& r, const double* src, double* dst,
+                             const double* wall, hipStream_t st);
+hipError_t launch_macro_wall1(const Geo& g, const Rates& r, const double* state, double* theta,
+                              double* u, const double* wall, hipStream_t st);
+hipError_t launch_get_state_wall1(const Geo& g, const double* state, double* dense,
+                                  const double* wall, hipStream_t st);
+hipError_t launch_wall_from_dense1(const Geo& g, const double* dense, double* wall,
+                                   hipStream_t st);
 hipError_t launch_init(int d, const Geo& g, const Rates& r, const double* theta0,
                        const double* grad, double* dst, hipStream_t st);
 hipError_t launch_macro(int d, const Geo& g, const Rates& r, const double* state, double* theta,

@@ -145,9 +145,14 @@ __global__ void __launch_bounds__(256) k_step(const double* __restrict__ src,
 // bound by one kernel launch per step.  Same collision as k_step<1>.
 constexpr int RES_THREADS = 256;
 
+// With walls != NULL the interval is bounded (wall_pull1): step s forms the
+// distribution of the time whose boundary theta is wall_now (s = 0) or
+// walls[2(s-1) .. 2(s-1)+1]; at the end wall_now takes the last pair.
 __global__ void __launch_bounds__(RES_THREADS) k_step_resident1(const double* __restrict__ src,
                                                                 double* __restrict__ dst, int n,
-                                                                int64_t nsteps, Rates r) {
+                                                                int64_t nsteps, Rates r,
+                                                                const double* __restrict__ walls,
+                                                                double* __restrict__ wall_now) {
     __shared__ double lds[3 * RESIDENT_MAX_1D];
     for (int x = threadIdx.x; x < n; x += RES_THREADS)
 #pragma unroll
@@ -155,6 +160,7 @@ __global__ void __launch_bounds__(RES_THREADS) k_step_resident1(const double* __
     __syncthreads();
     constexpr int PER = (RESIDENT_MAX_1D + RES_THREADS - 1) / RES_THREADS;
     for (int64_t s = 0; s < nsteps; ++s) {
+        const double* wall = walls ? (s == 0 ? wall_now : walls + 2 * (s - 1)) : nullptr;
         double f[PER][3];
 #pragma unroll
         for (int p = 0; p < PER; ++p) {
@@ -163,6 +169,10 @@ __global__ void __launch_bounds__(RES_THREADS) k_step_resident1(const double* __
                 const int xm = x == 0 ? n - 1 : x - 1;
                 const int xp = x == n - 1 ? 0 : x + 1;
                 double g[3] = {lds[x], lds[RESIDENT_MAX_1D + xm], lds[2 * RESIDENT_MAX_1D + xp]};
+                if (wall) {
+                    if (x == 0) g[1] = wall[0] - (g[0] + g[2]);
+                    if (x == n - 1) g[2] = wall[1] - (g[0] + g[1]);
+                }
                 collide<1>(g, r);
                 f[p][0] = g[0];
                 f[p][1] = g[1];
@@ -184,6 +194,78 @@ __global__ void __launch_bounds__(RES_THREADS) k_step_resident1(const double* __
     for (int x = threadIdx.x; x < n; x += RES_THREADS)
 #pragma unroll
         for (int i = 0; i < 3; ++i) dst[slot<3>(i, x)] = lds[i * RESIDENT_MAX_1D + x];
+    if (walls && nsteps > 0 && threadIdx.x < 2) wall_now[threadIdx.x] = walls[2 * (nsteps - 1) + threadIdx.x];
+}
+
+// ---------------------------------------------------------------------------
+// 1-D interval with theta given at the end nodes (Example 1 of Sec. IV)
+//
+// Nodes x = 0..n-1 (n >= 2), the two ends on the boundary.  The distribution
+// at x is pulled as usual, except for the one population that would come
+// from outside the interval: it takes the value that makes sum_i f_i equal
+// the boundary theta of the current time, wall[0] at x = 0 and wall[1] at
+// x = n-1.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void wall_pull1(const double* __restrict__ src, int x, int n,
+                                           const double* __restrict__ wall, double (&f)[3]) {
+    f[0] = src[slot<3>(0, x)];
+    f[1] = x > 0 ? src[slot<3>(1, x - 1)] : 0.0;
+    f[2] = x < n - 1 ? src[slot<3>(2, x + 1)] : 0.0;
+    if (x == 0) f[1] = wall[0] - (f[0] + f[2]);
+    if (x == n - 1) f[2] = wall[1] - (f[0] + f[1]);
+}
+
+__global__ void __launch_bounds__(256) k_step_wall1(const double* __restrict__ src,
+                                                    double* __restrict__ dst, int n, Rates r,
+                                                    const double* __restrict__ wall) {
+    const int x = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (x >= n) return;
+    double f[3];
+    wall_pull1(src, x, n, wall, f);
+    collide<1>(f, r);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) __builtin_nontemporal_store(f[i], dst + slot<3>(i, x));
+}
+
+// theta and u as k_macro<1>, from the bounded-interval distribution.
+__global__ void __launch_bounds__(256) k_macro_wall1(const double* __restrict__ src,
+                                                     double* __restrict__ theta,
+                                                     double* __restrict__ u, int n, Rates r,
+                                                     const double* __restrict__ wall) {
+    const int x = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (x >= n) return;
+    double f[3];
+    wall_pull1(src, x, n, wall, f);
+    double th = 0.0;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) th += f[i];
+    if (theta) theta[x] = th;
+    if (u) {
+        const double inv = r.ucoef / th;
+        double j = 0.0;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) j = LBM_SADD(j, Lat<1>::E[i][0], f[i]);
+        u[x] = j * inv;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_get_state_wall1(const double* __restrict__ src,
+                                                         double* __restrict__ dense, int n,
+                                                         const double* __restrict__ wall) {
+    const int x = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (x >= n) return;
+    double f[3];
+    wall_pull1(src, x, n, wall, f);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) dense[(int64_t)i * n + x] = f[i];
+}
+
+// Boundary theta of a dense 3 x n distribution: sum_i f_i at the end nodes.
+__global__ void k_wall_from_dense1(const double* __restrict__ dense, int n, double* __restrict__ wall) {
+    const int e = (int)threadIdx.x;
+    if (e >= 2) return;
+    const int x = e == 0 ? 0 : n - 1;
+    wall[e] = (dense[x] + dense[(int64_t)n + x]) + dense[2 * (int64_t)n + x];
 }
 
 __device__ __forceinline__ int wrapi(int v, int n) {
@@ -822,15 +904,46 @@ hipError_t launch_step(int d, const Geo& g, const Rates& r, const double* src, d
 }
 
 hipError_t launch_step_resident1(const Geo& g, const Rates& r, const double* src, double* dst,
-                                int64_t nsteps, hipStream_t st) {
+                                int64_t nsteps, const double* walls, double* wall_now,
+                                hipStream_t st) {
     if (g.nx > RESIDENT_MAX_1D || g.ny != 1 || g.nz != 1 || g.nw != 1) return hipErrorInvalidValue;
+    if (walls && (!wall_now || g.nx < 2)) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_step_resident1, dim3(1), dim3(RES_THREADS), 0, st, src, dst, g.nx, nsteps,
-                       r);
+                       r, walls, wall_now);
     return hipGetLastError();
 }
 
-// Segment length: about two blocks per CU in one wave (512 blocks), at least
-// 8 rows so the 4-row halo stays a small fraction.
+static dim3 grid_1d(int n) { return dim3((unsigned)((n + 255) / 256)); }
+
+hipError_t launch_step_wall1(const Geo& g, const Rates& r, const double* src, double* dst,
+                             const double* wall, hipStream_t st) {
+    if (g.nx < 2 || g.ny != 1 || g.nz != 1 || g.nw != 1 || !wall) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_step_wall1, grid_1d(g.nx), dim3(256), 0, st, src, dst, g.nx, r, wall);
+    return hipGetLastError();
+}
+
+hipError_t launch_macro_wall1(const Geo& g, const Rates& r, const double* state, double* theta,
+                              double* u, const double* wall, hipStream_t st) {
+    if (g.nx < 2 || g.ny != 1 || g.nz != 1 || g.nw != 1 || !wall) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_macro_wall1, grid_1d(g.nx), dim3(256), 0, st, state, theta, u, g.nx, r,
+                       wall);
+    return hipGetLastError();
+}
+
+hipError_t launch_get_state_wall1(const Geo& g, const double* state, double* dense,
+                                  const double* wall, hipStream_t st) {
+    if (g.nx < 2 || g.ny != 1 || g.nz != 1 || g.nw != 1 || !wall) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_get_state_wall1, grid_1d(g.nx), dim3(256), 0, st, state, dense, g.nx, wall);
+    return hipGetLastError();
+}
+
+hipError_t launch_wall_from_dense1(const Geo& g, const double* dense, double* wall,
+                                   hipStream_t st) {
+    if (g.nx < 2 || !wall) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_wall_from_dense1, dim3(1), dim3(64), 0, st, dense, g.nx, wall);
+    return hipGetLastError();
+}
+
 // Rows per segment of an S-step launch: about 1536 blocks (a few per CU at
 // the kernel's occupancy), at least 16 rows so that the 2S-row pipeline fill
 // stays a modest share of the march.

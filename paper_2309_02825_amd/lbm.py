@@ -23,6 +23,7 @@ LB_ERR_OOM = -4
 LB_ERR_HIP = -5
 LB_ERR_STATE = -6
 LB_OPT_STEPS_PER_PASS = 1
+LB_FLAG_BOUNDED = 1
 _NAMES = {0: "LB_OK", -1: "LB_ERR_INVALID_ARG", -2: "LB_ERR_UNSTABLE", -3: "LB_ERR_NONFINITE",
           -4: "LB_ERR_OOM", -5: "LB_ERR_HIP", -6: "LB_ERR_STATE"}
 
@@ -38,14 +39,15 @@ class lb_config(ctypes.Structure):
                 ("dx", ctypes.c_double), ("dt", ctypes.c_double), ("nu", ctypes.c_double)]
 
 
-def make_config(grid: Sequence[int], dx: float, dt: float, nu: float) -> lb_config:
+def make_config(grid: Sequence[int], dx: float, dt: float, nu: float,
+                flags: int = 0) -> lb_config:
     """grid is x_0-first: (n_0,), (n_0, n_1), (n_0, n_1, n_2) or (n_0, ..., n_3)."""
     n = [1, 1, 1, 1]
     for a, v in enumerate(grid):
         n[a] = int(v)
     c = lb_config()
     c.dim = len(grid)
-    c.flags = 0
+    c.flags = int(flags)
     c.n = (ctypes.c_int64 * 4)(*n)
     c.dx, c.dt, c.nu = float(dx), float(dt), float(nu)
     return c
@@ -77,6 +79,7 @@ def _load():
         "lb_create": ([_cp, _vp, _vp, _vp, ctypes.POINTER(_vp)], st),
         "lb_init": ([_vp, _vp, _vp, I32], st),
         "lb_step": ([_vp, I64], st),
+        "lb_step_bounded": ([_vp, I64, _vp], st),
         "lb_set_option": ([_vp, I32, I32], st),
         "lb_step_buffers": ([_vp, _vp, _vp], st),
         "lb_current_state": ([_vp], _vp),
@@ -172,6 +175,10 @@ def lb_init(h: int, theta0, grad=None, check_theta: bool = False):
 
 def lb_step(h: int, nsteps: int):
     _check(_load().lb_step(h, int(nsteps)))
+
+
+def lb_step_bounded(h: int, nsteps: int, walls):
+    _check(_load().lb_step_bounded(h, int(nsteps), _ptr(walls)))
 
 
 def lb_set_option(h: int, option: int, value: int):

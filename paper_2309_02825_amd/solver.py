@@ -33,16 +33,19 @@ def _field(x: torch.Tensor, shape, device, name: str) -> torch.Tensor:
 
 
 class Solver:
-    """One periodic problem (Sec. III.A scheme) on one GPU."""
+    """One problem (Sec. III.A scheme) on one GPU: periodic, or with
+    bounded=True a 1-D interval whose end nodes carry a prescribed theta
+    (Example 1 of Sec. IV; advance it with step_bounded)."""
 
     def __init__(self, grid: Sequence[int], dx: float, dt: float, nu: float,
                  device: Optional[torch.device] = None,
-                 stream: Optional[torch.cuda.Stream] = None):
+                 stream: Optional[torch.cuda.Stream] = None, bounded: bool = False):
         self.grid = tuple(int(v) for v in grid)
         self.d = len(self.grid)
         self.dx, self.dt, self.nu = float(dx), float(dt), float(nu)
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
-        self.cfg = L.make_config(self.grid, dx, dt, nu)
+        self.bounded = bool(bounded)
+        self.cfg = L.make_config(self.grid, dx, dt, nu, L.LB_FLAG_BOUNDED if bounded else 0)
         self.q = L.lb_num_populations(self.d)
         self.V = math.prod(self.grid)
         self.shape = tuple(reversed(self.grid))
@@ -96,6 +99,13 @@ class Solver:
 
     def step(self, nsteps: int):
         L.lb_step(self.h, nsteps)
+
+    def step_bounded(self, walls: torch.Tensor):
+        """Bounded interval: advance len(walls) steps; walls is (nsteps, 2),
+        the boundary theta (left, right) at t + dt, ..., t + nsteps dt."""
+        walls = _field(walls, (walls.shape[0], 2), self.device, "walls")
+        self._walls = walls  # keep alive until the kernels ran
+        L.lb_step_bounded(self.h, walls.shape[0], walls)
 
     def set_steps_per_pass(self, n: int):
         """D2Q9: the most time steps one pass over HBM advances (1, 2, 4 or 8;

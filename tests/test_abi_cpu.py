@@ -122,3 +122,19 @@ def test_null_handles_are_rejected():
             fn(*args)
     assert L.lb_steps_taken(0) == -1
     L.lb_destroy(0)
+
+
+def test_bounded_flag_validation():
+    """LB_FLAG_BOUNDED is accepted only for 1-D grids of at least two nodes;
+    unknown flags are rejected; the batched form is periodic only."""
+    ok = L.make_config((41,), 1 / 40, 1 / 100, 0.03125, L.LB_FLAG_BOUNDED)
+    assert L.lb_state_bytes(ok) == L.lb_state_bytes(L.make_config((41,), 1 / 40, 1 / 100, 0.03125))
+    for grid in ((1,), (8, 8), (4, 4, 4)):
+        c = L.make_config(grid, 0.1, 0.001, 0.1, L.LB_FLAG_BOUNDED)
+        assert L.lb_state_bytes(c) == 0, grid
+    assert L.lb_state_bytes(L.make_config((41,), 1 / 40, 1 / 100, 0.03125, 2)) == 0
+    # eps = 2 is fine for D1Q3 (no stability limit), bounded or not
+    assert L.lb_state_bytes(L.make_config((41,), 1 / 40, 1 / 100, 0.125, L.LB_FLAG_BOUNDED)) > 0
+    for fn, args in [(L.lb_step_bounded, (0, 1, None))]:
+        with pytest.raises(L.LBError):
+            fn(*args)

@@ -17,6 +17,7 @@ torch = pytest.importorskip("torch")
 from oracle import oracle as O  # noqa: E402
 from oracle import spectral as S  # noqa: E402
 from paper_2309_02825_amd import workloads as W  # noqa: E402
+from tests.helpers import read_table  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 
@@ -354,6 +355,108 @@ def test_full_size_2d(n):
 def test_full_size_3d(n):
     _say("full-size 3d", n, "2000 steps")
     _full_size_case(W.heat_3d(n), 2000)
+
+
+# ---------------------------------------------------------------------------
+# bounded 1-D interval (theta given at the end nodes, Example 1)
+# ---------------------------------------------------------------------------
+
+def _bounded_gpu(wl, th0, g0, walls, chunks=None, want_f=False):
+    SV = _solver_mod()
+    s = SV.Solver(wl.grid, wl.dx, wl.dt, wl.nu, device=_dev(), bounded=True)
+    s.init(torch.from_numpy(th0).to(_dev()), torch.from_numpy(g0).to(_dev()))
+    w = torch.from_numpy(np.ascontiguousarray(walls)).to(_dev())
+    done = 0
+    for n in (chunks or [walls.shape[0]]):
+        s.step_bounded(w[done:done + n].contiguous())
+        done += n
+    th, u = s.macro()
+    f = s.get_state() if want_f else None
+    torch.cuda.synchronize()
+    out = (th.cpu().numpy(), u.cpu().numpy(), None if f is None else f.cpu().numpy())
+    assert s.steps == walls.shape[0]
+    s.close()
+    return out
+
+
+def _bounded_oracle(wl, th0, g0, walls):
+    f = O.run_dirichlet1(O.init(th0, g0, wl.dx, wl.dt, wl.nu), wl.dx, wl.dt, wl.nu, walls)
+    th, u = O.macro(f, wl.dx, wl.dt, wl.nu)
+    return th, u, f
+
+
+@pytest.mark.parametrize("eps,level", [(0.5, 0), (2.0, 0), (1.0, 1), (1.5, 2)])
+def test_bounded_example1_matches_oracle(eps, level):
+    """Example 1 on the GPU (one LDS-resident launch with the boundary theta
+    of every step) against the oracle pinned to Table 1; the RMSEs against
+    the exact solution then agree with the printed ones."""
+    _say("bounded example 1", eps, level)
+    wl = W.paper_example1(level, eps)
+    th0, g0 = W.example1_theta0(wl)
+    walls = W.example1_walls(wl)
+    th_g, u_g, _ = _bounded_gpu(wl, th0, g0, walls)
+    th_o, u_o, _ = _bounded_oracle(wl, th0, g0, walls)
+    assert max_rel(th_g, th_o) <= TOL_THETA
+    assert max_rel(u_g[0], u_o[0]) <= TOL_U
+    x = np.arange(wl.grid[0]) * wl.dx
+    te, ue = W.example1_exact(wl.nu, x, wl.nsteps * wl.dt)
+    printed = {r[0]: r[2] for r in read_table("table1.txt") if r[1] == "theta"}[eps][level]
+    got = float(np.sqrt(np.mean((th_g - te) ** 2)))
+    assert abs(got - printed) / printed < 6e-5
+
+
+def test_bounded_large_interval_and_split_runs():
+    """An interval of 3001 nodes (one launch per step) with a rough positive
+    theta0 and arbitrary boundary theta against the oracle; a run split into
+    three calls is bitwise the single call; the state round-trips."""
+    _say("bounded 3001 nodes")
+    rng = np.random.Generator(np.random.PCG64(21))
+    n = 3001
+    x = np.arange(n) / (n - 1)
+    th0 = 2.0 + 0.5 * np.sin(2 * np.pi * 3.3 * x) + 0.3 * np.cos(2 * np.pi * 7.1 * x + 0.4)
+    g0 = (0.5 * 2 * np.pi * 3.3 * np.cos(2 * np.pi * 3.3 * x)
+          - 0.3 * 2 * np.pi * 7.1 * np.sin(2 * np.pi * 7.1 * x + 0.4))[None]
+    wl = W.Workload("bounded3001", (n,), 1.0 / (n - 1), 0.3 / (n - 1) ** 2 / 0.02, 0.02, [])
+    nsteps = 37
+    t = np.arange(1, nsteps + 1)
+    walls = np.stack([th0[0] + 0.01 * np.sin(0.3 * t), th0[-1] * (1 + 0.002 * t)], axis=1)
+    walls = walls * (1.0 + 1e-3 * rng.standard_normal(walls.shape))
+    th_g, u_g, f_g = _bounded_gpu(wl, th0, g0, walls, want_f=True)
+    th_o, u_o, f_o = _bounded_oracle(wl, th0, g0, walls)
+    assert max_rel(th_g, th_o) <= TOL_THETA
+    assert max_rel(u_g[0], u_o[0]) <= TOL_U
+    assert max_rel(f_g, f_o) <= TOL_THETA
+    th_s, u_s, f_s = _bounded_gpu(wl, th0, g0, walls, chunks=[10, 1, 26], want_f=True)
+    assert np.array_equal(th_s, th_g) and np.array_equal(u_s, u_g) and np.array_equal(f_s, f_g)
+    # reload the state in a new solver, continue both by the same steps
+    SV = _solver_mod()
+    more = walls[-1] * np.ones((5, 2))
+    a = SV.Solver(wl.grid, wl.dx, wl.dt, wl.nu, device=_dev(), bounded=True)
+    a.set_state(torch.from_numpy(f_g).to(_dev()), nsteps)
+    a.step_bounded(torch.from_numpy(more).to(_dev()))
+    th_a, _ = a.macro()
+    f_cont = O.run_dirichlet1(f_o, wl.dx, wl.dt, wl.nu, more)
+    th_c, _ = O.macro(f_cont, wl.dx, wl.dt, wl.nu)
+    assert max_rel(th_a.cpu().numpy(), th_c) <= TOL_THETA
+    with pytest.raises(Exception):
+        a.step(1)
+    a.close()
+
+
+def test_bounded_small_interval_resident_vs_per_step():
+    """n = 2 and n = 5: the LDS-resident launch against the oracle; the
+    smallest interval has both end nodes and nothing else."""
+    for n in (2, 5):
+        _say("bounded tiny", n)
+        wl = W.Workload(f"b{n}", (n,), 0.25, 0.01, 0.5, [])
+        x = np.arange(n) * wl.dx
+        th0 = 1.5 + 0.2 * np.cos(x)
+        g0 = (-0.2 * np.sin(x))[None]
+        walls = np.stack([np.full(9, 1.6), np.full(9, 1.4)], axis=1)
+        th_g, u_g, _ = _bounded_gpu(wl, th0, g0, walls)
+        th_o, u_o, _ = _bounded_oracle(wl, th0, g0, walls)
+        assert max_rel(th_g, th_o) <= TOL_THETA
+        assert np.max(np.abs(u_g[0] - u_o[0])) <= TOL_U * max(np.max(np.abs(u_o[0])), 1e-3)
 
 
 # ---------------------------------------------------------------------------
