@@ -34,6 +34,7 @@ BYTES_PER_LU = {1: 48, 2: 144, 3: 304, 4: 528}
 FLOPS_PER_LU_D2Q9 = 38
 FP64_PEAK_TFLOPS = 78.6
 D2_STEPS_PER_PASS = 8
+D3_STEPS_PER_PASS = 2
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_step.json")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2309_02825_amd", "csrc", n)
                   for n in ("lbm_kernels.hip", "lbm_lattice.h", "lbm_kernels.h")]
@@ -322,8 +323,9 @@ def main():
     # D2Q9 runs eight LB steps per launch (temporal blocking); the algorithmic
     # bytes of a launch are 144 B per lattice update times its 8V updates,
     # while the pass itself reads and writes the state once (see "traffic")
-    per_launch = D2_STEPS_PER_PASS if d == 2 else 1
-    kernel = f"k_steps_d2q9<{D2_STEPS_PER_PASS}>" if d == 2 else f"k_step<{d}>"
+    per_launch = {2: D2_STEPS_PER_PASS, 3: D3_STEPS_PER_PASS}.get(d, 1)
+    kernel = {2: f"k_steps_d2q9<{D2_STEPS_PER_PASS}>",
+              3: f"k_steps_d3q19<{D3_STEPS_PER_PASS}>"}.get(d, f"k_step<{d}>")
     launch_us = kms * 1e3 * per_launch
     rec = {
         "metric": METRIC,
@@ -383,9 +385,19 @@ def main():
             ml = w2.nodes / (ms / 1e3) / 1e6
             gbs = BYTES_PER_LU[w2.d] * ml / 1e3
             forms[name] = {"lattice": {2: "D2Q9", 3: "D3Q19", 4: "D4Q33"}[w2.d],
+                           "kernel": {2: f"k_steps_d2q9<{D2_STEPS_PER_PASS}>",
+                                      3: f"k_steps_d3q19<{D3_STEPS_PER_PASS}>"}.get(
+                                          w2.d, f"k_step<{w2.d}>"),
                            "kernel_us_per_step": round(ms * 1e3, 2),
                            "mlups": round(ml, 1), "gbs_algorithmic": round(gbs, 1),
                            "frac": round(gbs / HBM_PEAK_GBS, 4), "lb_steps_timed": n}
+            if w2.d == 3:
+                ms1 = kernel_only(torch, SV, W, w2, n, dev, steps_per_pass=1)
+                ml1 = w2.nodes / (ms1 / 1e3) / 1e6
+                forms[name]["single_step"] = {
+                    "kernel": "k_step<3>", "kernel_us_per_step": round(ms1 * 1e3, 2),
+                    "mlups": round(ml1, 1),
+                    "frac": round(BYTES_PER_LU[3] * ml1 / 1e3 / HBM_PEAK_GBS, 4)}
             log(name, forms[name])
         forms["heat1d_sweep"] = form_heat1d(torch, SV, W, dev)
         log("heat1d_sweep", forms["heat1d_sweep"])

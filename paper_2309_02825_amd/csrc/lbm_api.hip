@@ -82,10 +82,10 @@ Rates make_rates(int d, double dx, double dt, double nu) {
     r.dwd = dwd;
     r.dw0 = -2.0 * d * dw1 - 2.0 * d * (d - 1) * dwd;
     r.dinv_s1 = 3.0;
-    r.d2_cj = 0.5 * (1.0 - r.s1);
-    r.d2_cp = 0.5 * (1.0 - r.s21);
-    r.d2_ct = r.s21 / 6.0 - 2.0 * r.wd;
-    r.d2_cq = 0.25 * (1.0 - r.s22);
+    r.f_cj = 0.5 * (1.0 - r.s1);
+    r.f_cp = 0.5 * (1.0 - r.s21);
+    r.f_ct = r.s21 / 6.0 - 2.0 * (d - 1) * r.wd;
+    r.f_cq = 0.25 * (1.0 - r.s22);
     return r;
 }
 
@@ -323,6 +323,15 @@ lb_status lb_step(lb_solver* s, int64_t nsteps) {
                 s->cur ^= 1;
                 s->steps += pass;
             }
+        }
+    } else if (s->d == 3 && s->steps_per_pass >= lbm::MAX_STEPS_PER_PASS_3D) {
+        const int pass = lbm::MAX_STEPS_PER_PASS_3D;
+        for (; n + pass <= nsteps; n += pass) {
+            LB_HIP(lbm::launch_steps3(pass, s->g, s->r, s->buf[s->cur], s->buf[1 - s->cur],
+                                      s->stream),
+                   "multi-step launch");
+            s->cur ^= 1;
+            s->steps += pass;
         }
     }
     for (; n < nsteps; ++n) {

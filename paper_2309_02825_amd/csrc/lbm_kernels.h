@@ -53,6 +53,14 @@ constexpr int MAX_STEPS_PER_PASS = 8;
 __host__ __device__ constexpr int strip_width(int nsteps) { return MS_THREADS - 2 * nsteps; }
 hipError_t launch_steps(int nsteps, const Geo& g, const Rates& r, const double* src, double* dst,
                         hipStream_t st);
+// nsteps (2) D3Q19 steps in one pass; a block of MS3_TX x MS3_TY threads
+// produces a tile of tile_width3 x tile_height3 columns and marches along z.
+constexpr int MS3_TX = 64, MS3_TY = 8;
+constexpr int MAX_STEPS_PER_PASS_3D = 2;
+__host__ __device__ constexpr int tile_width3(int nsteps) { return MS3_TX - 2 * nsteps; }
+__host__ __device__ constexpr int tile_height3(int nsteps) { return MS3_TY - 2 * nsteps; }
+hipError_t launch_steps3(int nsteps, const Geo& g, const Rates& r, const double* src, double* dst,
+                         hipStream_t st);
 // 1-D grids up to this many nodes run all their steps in one launch with the
 // state in LDS (3 populations x 8 B x 2048 = 48 KiB).
 constexpr int RESIDENT_MAX_1D = 2048;

@@ -421,6 +421,143 @@ __global__ void __launch_bounds__(MS_THREADS) k_steps_d2q9(const double* __restr
 }
 
 // ---------------------------------------------------------------------------
+// S D3Q19 time steps per pass over HBM.
+//
+// The 2-D scheme above one dimension up: a block of MS3_TX x MS3_TY threads
+// owns a tile of (MS3_TX - 2S) x (MS3_TY - 2S) output columns (x, y) plus an
+// S-wide halo, thread (tx, ty) owns one column in every stage, and the block
+// marches along z through a segment of planes.  The three populations with
+// e_x = e_y = 0 stay in their thread; the sixteen others go through LDS
+// already shifted by (e_x, e_y).  Planes are delayed in registers by e_z
+// (0, 1 or 2 iterations).  Register pressure limits S to 2 (about 250 VGPRs,
+// two waves per SIMD); each block uses 2 x 16 x 512 doubles of LDS.
+// ---------------------------------------------------------------------------
+__host__ __device__ constexpr int m3_ex(int i) { return Lat<3>::E[i][0]; }
+__host__ __device__ constexpr int m3_ey(int i) { return Lat<3>::E[i][1]; }
+__host__ __device__ constexpr int m3_ez(int i) { return Lat<3>::E[i][2]; }
+__host__ __device__ constexpr bool m3_mover(int i) { return m3_ex(i) != 0 || m3_ey(i) != 0; }
+// index of population i among the movers, and among those with its e_z
+__host__ __device__ constexpr int m3_xyslot(int i) {
+    int s = 0;
+    for (int j = 0; j < i; ++j) s += m3_mover(j);
+    return s;
+}
+__host__ __device__ constexpr int m3_zslot(int i) {
+    int s = 0;
+    for (int j = 0; j < i; ++j) s += m3_ez(j) == m3_ez(i);
+    return s;
+}
+constexpr int M3_MOVERS = m3_xyslot(19);
+constexpr int M3_Z0 = 9, M3_ZP = 5;  // populations with e_z = 0 and with e_z = +1
+static_assert(M3_MOVERS == 16, "D3Q19 has 16 populations with e_x or e_y != 0");
+constexpr int M3_THREADS = MS3_TX * MS3_TY;
+
+template <int S>
+struct Ms3State {
+    double pre[19];            // next input plane (prefetched)
+    double z[S][M3_Z0];        // e_z = 0 populations of the previous plane, per stage input
+    double u[2][S][M3_ZP];     // e_z = +1 populations of the planes of each parity
+};
+
+template <int S, int P>
+__device__ __forceinline__ void ms3_plane(Ms3State<S>& st, double* lds, int k, int kend,
+                                          const double* __restrict__ src, double* __restrict__ dst,
+                                          const Geo& g, int col, int zs, int x0, int y0,
+                                          const Rates& r) {
+    const int tid = threadIdx.x, tx = tid % MS3_TX, ty = tid / MS3_TX;
+    const int64_t plane = (int64_t)g.nx * g.ny;
+    double f[19];
+#pragma unroll
+    for (int i = 0; i < 19; ++i) f[i] = st.pre[i];
+    if (k < kend) {
+        const int64_t base = (int64_t)wrapi(zs - S + k + 1, g.nz) * plane + col;
+#pragma unroll
+        for (int i = 0; i < 19; ++i) st.pre[i] = src[slot<19>(i, base)];
+    }
+#pragma unroll
+    for (int i = 0; i < 19; ++i)
+        if (m3_mover(i)) {
+            const int cx = tx + m3_ex(i), cy = ty + m3_ey(i);
+            if (cx >= 0 && cx < MS3_TX && cy >= 0 && cy < MS3_TY)
+                lds[m3_xyslot(i) * M3_THREADS + cy * MS3_TX + cx] = f[i];
+        }
+    __syncthreads();
+#pragma unroll
+    for (int j = 1; j <= S; ++j) {
+        double in[19];
+        const double* rd = lds + ((j - 1) & 1) * M3_MOVERS * M3_THREADS;
+#pragma unroll
+        for (int i = 0; i < 19; ++i) {
+            const double v = m3_mover(i) ? rd[m3_xyslot(i) * M3_THREADS + tid] : f[i];
+            if (m3_ez(i) == -1) {
+                in[i] = v;
+            } else if (m3_ez(i) == 0) {
+                in[i] = st.z[j - 1][m3_zslot(i)];
+                st.z[j - 1][m3_zslot(i)] = v;
+            } else {
+                in[i] = st.u[P][j - 1][m3_zslot(i)];
+                st.u[P][j - 1][m3_zslot(i)] = v;
+            }
+        }
+        if (k >= 2 * j && tx >= j && tx < MS3_TX - j && ty >= j && ty < MS3_TY - j) {
+            collide<3>(in, r);
+            if (j < S) {
+                double* wr = lds + (j & 1) * M3_MOVERS * M3_THREADS;
+#pragma unroll
+                for (int i = 0; i < 19; ++i) {
+                    f[i] = in[i];
+                    if (m3_mover(i)) {
+                        const int cx = tx + m3_ex(i), cy = ty + m3_ey(i);
+                        if (cx >= 0 && cx < MS3_TX && cy >= 0 && cy < MS3_TY)
+                            wr[m3_xyslot(i) * M3_THREADS + cy * MS3_TX + cx] = in[i];
+                    }
+                }
+            } else if (tx >= S && tx < MS3_TX - S && ty >= S && ty < MS3_TY - S &&
+                       x0 - S + tx < g.nx && y0 - S + ty < g.ny) {
+                const int64_t kk = (int64_t)wrapi(zs - 2 * S + k, g.nz) * plane +
+                                   (int64_t)(y0 - S + ty) * g.nx + (x0 - S + tx);
+#pragma unroll
+                for (int i = 0; i < 19; ++i) __builtin_nontemporal_store(in[i], dst + slot<19>(i, kk));
+            }
+        }
+        if (j < S) __syncthreads();
+    }
+    if (S & 1) __syncthreads();
+}
+
+template <int S>
+__global__ void __launch_bounds__(M3_THREADS) k_steps_d3q19(const double* __restrict__ src,
+                                                            double* __restrict__ dst, Geo g,
+                                                            Rates r, int lz, int ntx, int nty) {
+    __shared__ double lds[2 * M3_MOVERS * M3_THREADS];
+    const unsigned t = xcd_remap(blockIdx.x, gridDim.x);
+    const unsigned ntile = (unsigned)ntx * (unsigned)nty;
+    const int tile = (int)(t % ntile), seg = (int)(t / ntile);
+    const int x0 = (tile % ntx) * tile_width3(S), y0 = (tile / ntx) * tile_height3(S);
+    const int zs = seg * lz, ze = min(zs + lz, g.nz);
+    const int tx = threadIdx.x % MS3_TX, ty = threadIdx.x / MS3_TX;
+    const int col = wrapi(y0 - S + ty, g.ny) * g.nx + wrapi(x0 - S + tx, g.nx);
+    const int kend = ze - zs + 2 * S - 1;
+    Ms3State<S> st;
+    {
+        const int64_t base = (int64_t)wrapi(zs - S, g.nz) * g.nx * g.ny + col;
+#pragma unroll
+        for (int i = 0; i < 19; ++i) st.pre[i] = src[slot<19>(i, base)];
+    }
+#pragma unroll
+    for (int j = 0; j < S; ++j) {
+#pragma unroll
+        for (int a = 0; a < M3_Z0; ++a) st.z[j][a] = 0.0;
+#pragma unroll
+        for (int a = 0; a < M3_ZP; ++a) st.u[0][j][a] = st.u[1][j][a] = 0.0;
+    }
+    for (int k = 0; k <= kend; k += 2) {
+        ms3_plane<S, 0>(st, lds, k, kend, src, dst, g, col, zs, x0, y0, r);
+        if (k + 1 <= kend) ms3_plane<S, 1>(st, lds, k + 1, kend, src, dst, g, col, zs, x0, y0, r);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // initialisation
 // ---------------------------------------------------------------------------
 // Fourth-order central difference of theta along axis a at node c.
@@ -965,6 +1102,34 @@ static hipError_t launch_steps_t(const Geo& g, const Rates& r, const double* src
     hipLaunchKernelGGL(k_steps_d2q9<S>, dim3((unsigned)((int64_t)nstrips * nseg)),
                        dim3(MS_THREADS), 0, st, src, dst, g, r, ly, nstrips);
     return hipGetLastError();
+}
+
+// Planes per segment of a D3Q19 pass: 64, fewer (at least 16) when the grid
+// would otherwise give under about 1280 blocks.
+template <int S>
+static hipError_t launch_steps3_t(const Geo& g, const Rates& r, const double* src, double* dst,
+                                  hipStream_t st) {
+    const int ntx = (g.nx + tile_width3(S) - 1) / tile_width3(S);
+    const int nty = (g.ny + tile_height3(S) - 1) / tile_height3(S);
+    int64_t lz = ((int64_t)g.nz * ntx * nty + 1279) / 1280;
+    if (lz > 64) lz = 64;
+    if (lz < 16) lz = 16;
+    if (lz > g.nz) lz = g.nz;
+    const int64_t nseg = (g.nz + lz - 1) / lz;
+    const int64_t nb = (int64_t)ntx * nty * nseg;
+    if (nb > (int64_t)UINT32_MAX) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_steps_d3q19<S>, dim3((unsigned)nb), dim3(M3_THREADS), 0, st, src, dst, g,
+                       r, (int)lz, ntx, nty);
+    return hipGetLastError();
+}
+
+hipError_t launch_steps3(int nsteps, const Geo& g, const Rates& r, const double* src, double* dst,
+                         hipStream_t st) {
+    if (g.nw != 1) return hipErrorInvalidValue;
+    switch (nsteps) {
+        case 2: return launch_steps3_t<2>(g, r, src, dst, st);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_steps(int nsteps, const Geo& g, const Rates& r, const double* src, double* dst,

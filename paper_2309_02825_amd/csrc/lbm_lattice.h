@@ -46,11 +46,11 @@ struct Rates {
     double ds1, ds21, ds22, dw0, dw1, dwd;
     double dinv_s1;          // d(1/s1)/deps = 3
     double c;                // dx / dt
-    // D2Q9 collision in folded form (collide_d2q9)
-    double d2_cj;            // (1 - s1) / 2
-    double d2_cp;            // (1 - s21) / 2
-    double d2_ct;            // s21 / 6 - 2 w_d
-    double d2_cq;            // (1 - s22) / 4
+    // D2Q9 / D3Q19 collisions in folded form (collide_d2q9, collide_d3q19)
+    double f_cj;             // (1 - s1) / 2
+    double f_cp;             // (1 - s21) / 2
+    double f_ct;             // s21 / 6 - 2 (d - 1) w_d
+    double f_cq;             // (1 - s22) / 4
 };
 
 // Velocity tables in the order of Sec. III.A (a fourth component, zero
@@ -220,10 +220,10 @@ __device__ __forceinline__ void collide_d2q9(double (&f)[9], const Rates& r) {
     const double jx = xp - xm, Px = xp + xm, jy = yp - ym, Py = yp + ym;
     const double th = f[0] + (f[2] + f[4]) + Px;
     const double Pxy = (f[5] + f[7]) - (f[6] + f[8]);
-    const double hjx = r.d2_cj * jx, hjy = r.d2_cj * jy;
-    const double tt = r.d2_ct * th;
-    const double hPx = fma(r.d2_cp, Px, tt), hPy = fma(r.d2_cp, Py, tt);
-    const double eR = r.wd * th, eP = r.d2_cq * Pxy;
+    const double hjx = r.f_cj * jx, hjy = r.f_cj * jy;
+    const double tt = r.f_ct * th;
+    const double hPx = fma(r.f_cp, Px, tt), hPy = fma(r.f_cp, Py, tt);
+    const double eR = r.wd * th, eP = r.f_cq * Pxy;
     f[0] = fma(-2.0, hPx + hPy, th - 4.0 * eR);
     f[1] = hPx + hjx;
     f[3] = hPx - hjx;
@@ -235,11 +235,63 @@ __device__ __forceinline__ void collide_d2q9(double (&f)[9], const Rates& r) {
     f[8] = f[6];
 }
 
+// D3Q19 collision folded the same way: with hj_a = (1 - s1)/2 j_a and
+// hP_a = (1 - s21)/2 P_a + (s21/6 - 4 w_d) theta the axis populations are
+// hP_a +- hj_a, the edge populations of the pair (a, b) are
+// eR +- (1 - s22)/4 P_ab (sign e_a e_b) with eR = w_d theta, and the rest
+// population is (theta - 12 eR) - 2 (hP_x + hP_y + hP_z), which again keeps
+// sum_i f_i = theta up to unbiased rounding.  75 double operations against
+// about 140 for the generic form.
+__device__ __forceinline__ void collide_d3q19(double (&f)[19], const Rates& r) {
+    // partial sums over the five velocities with e_a = +1 / -1
+    const double xp = (f[1] + f[7]) + (f[10] + f[11]) + f[14];
+    const double xm = (f[4] + f[8]) + (f[9] + f[12]) + f[13];
+    const double yp = (f[2] + f[7]) + (f[8] + f[15]) + f[18];
+    const double ym = (f[5] + f[9]) + (f[10] + f[16]) + f[17];
+    const double zp = (f[3] + f[11]) + (f[12] + f[15]) + f[16];
+    const double zm = (f[6] + f[13]) + (f[14] + f[17]) + f[18];
+    const double jx = xp - xm, Px = xp + xm, jy = yp - ym, Py = yp + ym;
+    const double jz = zp - zm, Pz = zp + zm;
+    const double th =
+        ((f[0] + Px) + (f[2] + f[5])) + ((f[3] + f[6]) + ((f[15] + f[16]) + (f[17] + f[18])));
+    const double Pxy = (f[7] + f[9]) - (f[8] + f[10]);
+    const double Pxz = (f[11] + f[13]) - (f[12] + f[14]);
+    const double Pyz = (f[15] + f[17]) - (f[16] + f[18]);
+    const double tt = r.f_ct * th;
+    const double hPx = fma(r.f_cp, Px, tt), hPy = fma(r.f_cp, Py, tt), hPz = fma(r.f_cp, Pz, tt);
+    const double hjx = r.f_cj * jx, hjy = r.f_cj * jy, hjz = r.f_cj * jz;
+    const double eR = r.wd * th;
+    const double exy = r.f_cq * Pxy, exz = r.f_cq * Pxz, eyz = r.f_cq * Pyz;
+    f[0] = fma(-2.0, (hPx + hPy) + hPz, th - 12.0 * eR);
+    f[1] = hPx + hjx;
+    f[4] = hPx - hjx;
+    f[2] = hPy + hjy;
+    f[5] = hPy - hjy;
+    f[3] = hPz + hjz;
+    f[6] = hPz - hjz;
+    f[7] = eR + exy;
+    f[9] = f[7];
+    f[8] = eR - exy;
+    f[10] = f[8];
+    f[11] = eR + exz;
+    f[13] = f[11];
+    f[12] = eR - exz;
+    f[14] = f[12];
+    f[15] = eR + eyz;
+    f[17] = f[15];
+    f[16] = eR - eyz;
+    f[18] = f[16];
+}
+
 // In-place collision f <- C f (Sec. III.A evolution equation, Theorem 2 rates).
 template <int D>
 __device__ __forceinline__ void collide(double (&f)[Lat<D>::Q], const Rates& r) {
     if constexpr (D == 2) {
         collide_d2q9(f, r);
+        return;
+    }
+    if constexpr (D == 3) {
+        collide_d3q19(f, r);
         return;
     }
     Moments<D> m;

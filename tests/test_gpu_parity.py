@@ -252,6 +252,26 @@ def test_multi_step_passes_equal_single_steps(grid, steps):
         assert np.array_equal(outs[0], o)
 
 
+@pytest.mark.parametrize("grid,steps", [((37, 29, 23), 5), ((5, 3, 2), 4), ((1, 1, 1), 3),
+                                         ((64, 9, 40), 8), ((130, 7, 11), 7), ((61, 5, 70), 6)])
+def test_multi_step_passes_equal_single_steps_3d(grid, steps):
+    """D3Q19 lb_step advances pairs of steps in one pass (x-y tiles marching
+    along z); the state is bitwise that of one launch per step for ragged
+    tiles, short and long z segments, odd counts and degenerate grids."""
+    _say("multi-step 3d vs single", grid, steps)
+    SV = _solver_mod()
+    dx, dt, nu, th0, _ = _problem(grid, "random")
+    outs = []
+    for spp in (1, 2):
+        s = SV.Solver(grid, dx, dt, nu, device=_dev())
+        s.set_steps_per_pass(spp)
+        s.init(torch.from_numpy(th0).to(_dev()), None)
+        s.step(steps)
+        outs.append(s.get_state().cpu().numpy())
+        s.close()
+    assert np.array_equal(outs[0], outs[1])
+
+
 def test_run_to_run_bitwise_determinism():
     _say("determinism")
     grid = (257, 129)
