@@ -547,7 +547,7 @@ static void drop_graphs(lb_batch* b) {
 }
 
 // Tile tables.  tx == 0: 256 consecutive node indices of one instance;
-// tx == -S: S-step tiles of strip_width(S) columns x ty rows (y1 in .pad),
+// tx == -S: S-step tiles of batch_strip_width(S) columns x ty rows (y1 in .pad),
 // ordered strip-fastest within an instance so that neighbouring strips share
 // an XCD; otherwise tx x ty rectangles.
 static std::vector<BatchTile> tile_list(const lb_batch* b, int tx, int ty) {
@@ -559,7 +559,7 @@ static std::vector<BatchTile> tile_list(const lb_batch* b, int tx, int ty) {
             for (int64_t k0 = 0; k0 < V; k0 += 256) tiles.push_back(BatchTile{(int)i, (int)k0, 0, 0});
         } else if (tx < 0) {
             for (int y0 = 0; y0 < in.ny; y0 += ty)
-                for (int x0 = 0; x0 < in.nx; x0 += lbm::strip_width(-tx))
+                for (int x0 = 0; x0 < in.nx; x0 += lbm::batch_strip_width(-tx))
                     tiles.push_back(BatchTile{(int)i, x0, y0, std::min(y0 + ty, in.ny)});
         } else {
             for (int y0 = 0; y0 < in.ny; y0 += ty)
@@ -791,8 +791,9 @@ lb_status lb_batch_autotune(lb_batch* b, int32_t steps_per_trial, int32_t* best_
     if (!b) return fail(LB_ERR_INVALID_ARG, "batch is NULL");
     if (!b->inited) return fail(LB_ERR_STATE, "autotune needs an initialised batch");
     if (steps_per_trial < 1) steps_per_trial = 1;
-    static const int cand[][2] = {{0, 0},  {256, 1}, {64, 4},  {16, 16}, {-2, 64},
-                                  {-4, 64}, {-8, 32}, {-8, 64}, {-8, 128}};
+    static const int cand[][2] = {{0, 0},   {256, 1}, {64, 4},   {16, 16},  {-2, 64},
+                                  {-4, 64},  {-8, 32}, {-8, 64},  {-8, 128}, {-8, 192},
+                                  {-8, 256}};
     hipEvent_t e0, e1;
     LB_HIP(hipEventCreate(&e0), "hipEventCreate");
     LB_HIP(hipEventCreate(&e1), "hipEventCreate");

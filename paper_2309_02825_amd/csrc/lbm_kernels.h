@@ -47,8 +47,8 @@ hipError_t launch_step(int d, const Geo& g, const Rates& r, const double* src, d
                        hipStream_t st);
 // nsteps (2, 4 or 8) D2Q9 steps in one pass over HBM (temporal blocking);
 // bitwise equal to nsteps launch_step calls.  A block of MS_THREADS threads
-// produces a strip of strip_width(nsteps) columns.
-constexpr int MS_THREADS = 128;
+// (one wave) produces a strip of strip_width(nsteps) columns.
+constexpr int MS_THREADS = 64;
 constexpr int MAX_STEPS_PER_PASS = 8;
 __host__ __device__ constexpr int strip_width(int nsteps) { return MS_THREADS - 2 * nsteps; }
 hipError_t launch_steps(int nsteps, const Geo& g, const Rates& r, const double* src, double* dst,
@@ -126,7 +126,9 @@ struct BatchTile {
 hipError_t launch_batch_step(const BatchInst* insts, const BatchTile* tiles, int64_t ntiles,
                              int tx, int ty, const double* src, double* dst, hipStream_t st);
 // nsteps (2, 4 or 8) steps per pass; tiles (inst, x0, y0, y1) cover strips of
-// strip_width(nsteps) columns.
+// batch_strip_width(nsteps) columns (blocks of LW_THREADS threads).
+constexpr int LW_THREADS = 128;
+__host__ __device__ constexpr int batch_strip_width(int nsteps) { return LW_THREADS - 2 * nsteps; }
 hipError_t launch_batch_steps(int nsteps, const BatchInst* insts, const BatchTile* tiles,
                               int64_t ntiles, const double* src, double* dst, hipStream_t st);
 

@@ -276,39 +276,45 @@ __device__ __forceinline__ int wrapi(int v, int n) {
 // ---------------------------------------------------------------------------
 // S D2Q9 time steps per pass over HBM (temporal blocking).
 //
-// A block of MS_THREADS threads owns a strip of MS_THREADS - 2S output columns
-// and a segment of rows; thread t owns column x0 - S + t in every stage (the
-// strip plus an S-column halo on each side).  The block marches down its
-// segment one row per iteration: it loads input row ys - S + k and, in the
-// same iteration, stage j = 1..S computes row ys - S + k - j of step j from
-// rows (that row + {-1, 0, +1}) of step j - 1.  Only the last stage's rows
-// are stored, so each value is read from and written to HBM once per S steps
-// (plus the halo).
+// One wave (64 lanes) owns a strip of 64 - 2S output columns plus an
+// S-column halo on each side; lane t owns column x0 - S + t in every stage.
+// The wave marches down a segment of rows: in iteration k it loads input
+// row ys - S + k and stage j = 1..S computes row ys - S + k - j of step j from
+// rows (that row + {-1, 0, +1}) of step j - 1.  Only stage S stores, so each
+// value crosses HBM once per S steps (plus the halo).
 //
-// Exchange between stages: the three populations with e_x = 0 never leave
-// their thread.  The six with e_x != 0 are written to LDS already shifted by
-// e_x (producer column t -> slot t + e_x), so every consumer reads its own
-// column.  Rows are delayed in registers: a population with e_y = -1 is used
-// in the iteration it arrives, e_y = 0 one iteration later, e_y = +1 two
-// iterations later (two registers that alternate with the row parity; the
-// march is unrolled by two so that the parity is static).  Stages alternate
-// between two LDS buffers of 6 x MS_THREADS doubles, so LDS use does not grow
-// with S.  The arithmetic is collide<2> S times, so the result is bitwise that
-// of S single steps.
+// Exchange between stages never leaves the wave: a population with e_x = +1
+// (-1) is pulled from the lane on the left (right) with a DPP wave shift
+// (wave_shr:1 / wave_shl:1, two 32-bit moves per double), e_x = 0 stays in
+// its lane.  Rows are delayed in registers: e_y = -1 is used in the
+// iteration it arrives, e_y = 0 one iteration later, e_y = +1 two iterations
+// later (two registers that alternate with the row parity; the march is
+// unrolled by two so that the parity is static).  No LDS and no barrier.
+//
+// Every lane computes every stage (halo lanes produce values that only halo
+// lanes consume); only stage S stores, from its valid lanes.  The first 2S
+// iterations fill the pipeline (stage j holds valid rows from iteration 2j
+// on) and are unrolled at compile time with the stages that are already
+// valid, so the steady-state loop has no per-stage branch.  The arithmetic is
+// collide<2> S times, so the result is bitwise that of S single steps.
 // ---------------------------------------------------------------------------
 __host__ __device__ constexpr int ms_ex(int i) { return Lat<2>::E[i][0]; }
 __host__ __device__ constexpr int ms_ey(int i) { return Lat<2>::E[i][1]; }
-// index of population i among those with e_x != 0
-__host__ __device__ constexpr int ms_xslot(int i) {
-    int s = 0;
-    for (int j = 0; j < i; ++j) s += ms_ex(j) != 0;
-    return s;
-}
 // index of population i among those with the same e_y
 __host__ __device__ constexpr int ms_yslot(int i) {
     int s = 0;
     for (int j = 0; j < i; ++j) s += ms_ey(j) == ms_ey(i);
     return s;
+}
+
+// value of a double in the lane on the left (DIR = +1) or right (DIR = -1)
+template <int DIR>
+__device__ __forceinline__ double lane_shift(double x) {
+    constexpr int ctrl = DIR == 1 ? 0x138 : 0x130;  // wave_shr:1 : wave_shl:1
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffff), ctrl, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), ctrl, 0xf, 0xf, true);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
 template <int S>
@@ -318,14 +324,14 @@ struct MsState {
     double u[2][S][3];  // e_y = +1 populations of the rows of each parity
 };
 
-// One iteration k of the march; P = k & 1.
-template <int S, int P>
-__device__ __forceinline__ void ms_row(MsState<S>& st, double (&lds)[2][6][MS_THREADS], int k,
-                                       int kend, const double* __restrict__ src,
-                                       double* __restrict__ dst, int nx, int ny, int gx, int ys,
-                                       int x0, const Rates& r) {
+// One iteration k of the march; P = k & 1; stages above ACTIVE are skipped
+// (pipeline fill), stage S stores only when ACTIVE == S.
+template <int S, int P, int ACTIVE>
+__device__ __forceinline__ void ms_row(MsState<S>& st, int k, int kend,
+                                       const double* __restrict__ src, double* __restrict__ dst,
+                                       int nx, int ny, int gx, int ys, int x0, const FoldedRates& r) {
     constexpr int W = MS_THREADS - 2 * S;
-    const int tid = threadIdx.x;
+    const int lane = threadIdx.x;
     double f[9];
 #pragma unroll
     for (int i = 0; i < 9; ++i) f[i] = st.pre[i];
@@ -335,20 +341,14 @@ __device__ __forceinline__ void ms_row(MsState<S>& st, double (&lds)[2][6][MS_TH
         for (int i = 0; i < 9; ++i) st.pre[i] = src[slot<9>(i, base)];
     }
 #pragma unroll
-    for (int i = 0; i < 9; ++i)
-        if (ms_ex(i) != 0) {
-            const int c = tid + ms_ex(i);
-            if (c >= 0 && c < MS_THREADS) lds[0][ms_xslot(i)][c] = f[i];
-        }
-    __syncthreads();
-#pragma unroll
     for (int j = 1; j <= S; ++j) {
         // inputs of stage j: stage j-1 rows of iterations k (e_y = -1), k-1
-        // (e_y = 0) and k-2 (e_y = +1)
+        // (e_y = 0) and k-2 (e_y = +1), pulled from lane t - e_x
         double in[9];
 #pragma unroll
         for (int i = 0; i < 9; ++i) {
-            const double v = ms_ex(i) != 0 ? lds[(j - 1) & 1][ms_xslot(i)][tid] : f[i];
+            const double v = ms_ex(i) == 0 ? f[i]
+                                           : (ms_ex(i) == 1 ? lane_shift<1>(f[i]) : lane_shift<-1>(f[i]));
             if (ms_ey(i) == -1) {
                 in[i] = v;
             } else if (ms_ey(i) == 0) {
@@ -359,39 +359,38 @@ __device__ __forceinline__ void ms_row(MsState<S>& st, double (&lds)[2][6][MS_TH
                 st.u[P][j - 1][ms_yslot(i)] = v;
             }
         }
-        // stage j holds valid rows from iteration 2j on, in columns j .. T-1-j
-        if (k >= 2 * j && tid >= j && tid < MS_THREADS - j) {
-            collide<2>(in, r);
-            if (j < S) {
+        if (j <= ACTIVE) {
+            collide_d2q9(in, r);
 #pragma unroll
-                for (int i = 0; i < 9; ++i) {
-                    f[i] = in[i];
-                    if (ms_ex(i) != 0) {
-                        const int c = tid + ms_ex(i);
-                        if (c >= 0 && c < MS_THREADS) lds[j & 1][ms_xslot(i)][c] = in[i];
-                    }
-                }
-            } else if (tid >= S && tid < S + W && x0 - S + tid < nx) {
-                const int row = wrapi(ys - 2 * S + k, ny) * nx + x0 - S + tid;
+            for (int i = 0; i < 9; ++i) f[i] = in[i];
+            if (j == S && ACTIVE == S && lane >= S && lane < S + W && x0 - S + lane < nx) {
+                const int row = wrapi(ys - 2 * S + k, ny) * nx + x0 - S + lane;
 #pragma unroll
                 for (int i = 0; i < 9; ++i) __builtin_nontemporal_store(in[i], dst + slot<9>(i, row));
             }
         }
-        if (j < S) __syncthreads();
     }
-    // with S odd the last stage reads buffer 0, which the next load rewrites
-    if (S & 1) __syncthreads();
 }
 
-// Advance rows [ys, ye) of the columns [x0, x0 + MS_THREADS - 2S) of one
+template <int S, int K>
+__device__ __forceinline__ void ms_fill(MsState<S>& st, int kend, const double* __restrict__ src,
+                                        double* __restrict__ dst, int nx, int ny, int gx, int ys,
+                                        int x0, const FoldedRates& r) {
+    if constexpr (K < 2 * S) {
+        ms_row<S, K & 1, K / 2>(st, K, kend, src, dst, nx, ny, gx, ys, x0, r);
+        ms_fill<S, K + 1>(st, kend, src, dst, nx, ny, gx, ys, x0, r);
+    }
+}
+
+// Advance rows [ys, ye) (ye > ys) of the columns [x0, x0 + 64 - 2S) of one
 // D2Q9 grid by S steps (reads rows ys-S .. ye-1+S and columns x0-S ..
-// x0+MS_THREADS-S-1, wrapped periodically).
+// x0+63-S, wrapped periodically).  All 64 lanes of the wave must be active.
 template <int S>
 __device__ __forceinline__ void ms_tile(const double* __restrict__ src, double* __restrict__ dst,
-                                        int nx, int ny, const Rates& r, int x0, int ys, int ye,
-                                        double (&lds)[2][6][MS_THREADS]) {
+                                        int nx, int ny, const FoldedRates& r, int x0, int ys,
+                                        int ye) {
     const int gx = wrapi(x0 - S + (int)threadIdx.x, nx);
-    const int kend = ye - ys + 2 * S - 1;
+    const int kend = ye - ys + 2 * S - 1;  // >= 2S
     MsState<S> st;
     {
         const int base = wrapi(ys - S, ny) * nx + gx;
@@ -402,22 +401,24 @@ __device__ __forceinline__ void ms_tile(const double* __restrict__ src, double* 
     for (int j = 0; j < S; ++j)
 #pragma unroll
         for (int a = 0; a < 3; ++a) st.z[j][a] = st.u[0][j][a] = st.u[1][j][a] = 0.0;
-    for (int k = 0; k <= kend; k += 2) {
-        ms_row<S, 0>(st, lds, k, kend, src, dst, nx, ny, gx, ys, x0, r);
-        if (k + 1 <= kend) ms_row<S, 1>(st, lds, k + 1, kend, src, dst, nx, ny, gx, ys, x0, r);
+    ms_fill<S, 0>(st, kend, src, dst, nx, ny, gx, ys, x0, r);
+    for (int k = 2 * S; k <= kend; k += 2) {
+        ms_row<S, 0, S>(st, k, kend, src, dst, nx, ny, gx, ys, x0, r);
+        if (k + 1 <= kend) ms_row<S, 1, S>(st, k + 1, kend, src, dst, nx, ny, gx, ys, x0, r);
     }
 }
 
+// Two waves per SIMD: the register budget (256 per wave) holds S = 8.
 template <int S>
-__global__ void __launch_bounds__(MS_THREADS) k_steps_d2q9(const double* __restrict__ src,
+__global__ void __launch_bounds__(MS_THREADS) __attribute__((amdgpu_waves_per_eu(2)))
+k_steps_d2q9(const double* __restrict__ src,
                                                            double* __restrict__ dst, Geo g,
                                                            Rates r, int ly, int nstrips) {
-    __shared__ double lds[2][6][MS_THREADS];
     const unsigned t = xcd_remap(blockIdx.x, gridDim.x);
     const int strip = (int)(t % (unsigned)nstrips);
     const int seg = (int)(t / (unsigned)nstrips);
     const int ys = seg * ly;
-    ms_tile<S>(src, dst, g.nx, g.ny, r, strip * (MS_THREADS - 2 * S), ys, min(ys + ly, g.ny), lds);
+    ms_tile<S>(src, dst, g.nx, g.ny, folded(r), strip * strip_width(S), ys, min(ys + ly, g.ny));
 }
 
 // ---------------------------------------------------------------------------
@@ -463,7 +464,7 @@ template <int S, int P>
 __device__ __forceinline__ void ms3_plane(Ms3State<S>& st, double* lds, int k, int kend,
                                           const double* __restrict__ src, double* __restrict__ dst,
                                           const Geo& g, int col, int zs, int x0, int y0,
-                                          const Rates& r) {
+                                          const FoldedRates& r) {
     const int tid = threadIdx.x, tx = tid % MS3_TX, ty = tid / MS3_TX;
     const int64_t plane = (int64_t)g.nx * g.ny;
     double f[19];
@@ -500,7 +501,7 @@ __device__ __forceinline__ void ms3_plane(Ms3State<S>& st, double* lds, int k, i
             }
         }
         if (k >= 2 * j && tx >= j && tx < MS3_TX - j && ty >= j && ty < MS3_TY - j) {
-            collide<3>(in, r);
+            collide_d3q19(in, r);
             if (j < S) {
                 double* wr = lds + (j & 1) * M3_MOVERS * M3_THREADS;
 #pragma unroll
@@ -538,6 +539,7 @@ __global__ void __launch_bounds__(M3_THREADS) k_steps_d3q19(const double* __rest
     const int tx = threadIdx.x % MS3_TX, ty = threadIdx.x / MS3_TX;
     const int col = wrapi(y0 - S + ty, g.ny) * g.nx + wrapi(x0 - S + tx, g.nx);
     const int kend = ze - zs + 2 * S - 1;
+    const FoldedRates fr = folded(r);
     Ms3State<S> st;
     {
         const int64_t base = (int64_t)wrapi(zs - S, g.nz) * g.nx * g.ny + col;
@@ -552,8 +554,8 @@ __global__ void __launch_bounds__(M3_THREADS) k_steps_d3q19(const double* __rest
         for (int a = 0; a < M3_ZP; ++a) st.u[0][j][a] = st.u[1][j][a] = 0.0;
     }
     for (int k = 0; k <= kend; k += 2) {
-        ms3_plane<S, 0>(st, lds, k, kend, src, dst, g, col, zs, x0, y0, r);
-        if (k + 1 <= kend) ms3_plane<S, 1>(st, lds, k + 1, kend, src, dst, g, col, zs, x0, y0, r);
+        ms3_plane<S, 0>(st, lds, k, kend, src, dst, g, col, zs, x0, y0, fr);
+        if (k + 1 <= kend) ms3_plane<S, 1>(st, lds, k + 1, kend, src, dst, g, col, zs, x0, y0, fr);
     }
 }
 
@@ -986,18 +988,144 @@ __global__ void __launch_bounds__(256) k_batch_step(const BatchInst* __restrict_
     for (int i = 0; i < Q; ++i) __builtin_nontemporal_store(f[i], d + slot<Q>(i, k));
 }
 
-// Batched S-step pass: tile (inst, x0, y0, y1) = rows [y0, y1) of the strip
-// at x0 (MS_THREADS - 2S columns) of one instance.
+// ---------------------------------------------------------------------------
+// S D2Q9 time steps per pass, two-wave variant for the batched form.
+//
+// A block of LW_THREADS = 128 threads owns a strip of 128 - 2S columns (112
+// at S = 8 against 48 for one wave), which wastes fewer columns on the
+// halo and on the ragged last strip of instances 64..1024 nodes wide.  Thread
+// t owns column x0 - S + t in every stage; the populations with e_x != 0
+// cross between the two waves through LDS, written already shifted by e_x
+// (producer column t -> slot t + e_x) so that every consumer reads its own
+// column, with a barrier per stage; stages alternate between two LDS buffers
+// of 6 x 128 doubles.  Rows are delayed in registers as in the one-wave
+// routine.  Same arithmetic, so also bitwise S single steps.
+// ---------------------------------------------------------------------------
+__host__ __device__ constexpr int lw_ex(int i) { return Lat<2>::E[i][0]; }
+__host__ __device__ constexpr int lw_ey(int i) { return Lat<2>::E[i][1]; }
+// index of population i among those with e_x != 0
+__host__ __device__ constexpr int lw_xslot(int i) {
+    int s = 0;
+    for (int j = 0; j < i; ++j) s += lw_ex(j) != 0;
+    return s;
+}
+// index of population i among those with the same e_y
+__host__ __device__ constexpr int lw_yslot(int i) {
+    int s = 0;
+    for (int j = 0; j < i; ++j) s += lw_ey(j) == lw_ey(i);
+    return s;
+}
+
 template <int S>
-__global__ void __launch_bounds__(MS_THREADS) k_batch_steps(const BatchInst* __restrict__ insts,
+struct LwState {
+    double pre[9];      // next input row (prefetched)
+    double z[S][3];     // e_y = 0 populations of the previous row, per stage input
+    double u[2][S][3];  // e_y = +1 populations of the rows of each parity
+};
+
+// One iteration k of the march; P = k & 1.
+template <int S, int P>
+__device__ __forceinline__ void lw_row(LwState<S>& st, double (&lds)[2][6][LW_THREADS], int k,
+                                       int kend, const double* __restrict__ src,
+                                       double* __restrict__ dst, int nx, int ny, int gx, int ys,
+                                       int x0, const FoldedRates& r) {
+    constexpr int W = LW_THREADS - 2 * S;
+    const int tid = threadIdx.x;
+    double f[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) f[i] = st.pre[i];
+    if (k < kend) {
+        const int base = wrapi(ys - S + k + 1, ny) * nx + gx;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) st.pre[i] = src[slot<9>(i, base)];
+    }
+#pragma unroll
+    for (int i = 0; i < 9; ++i)
+        if (lw_ex(i) != 0) {
+            const int c = tid + lw_ex(i);
+            if (c >= 0 && c < LW_THREADS) lds[0][lw_xslot(i)][c] = f[i];
+        }
+    __syncthreads();
+#pragma unroll
+    for (int j = 1; j <= S; ++j) {
+        // inputs of stage j: stage j-1 rows of iterations k (e_y = -1), k-1
+        // (e_y = 0) and k-2 (e_y = +1)
+        double in[9];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            const double v = lw_ex(i) != 0 ? lds[(j - 1) & 1][lw_xslot(i)][tid] : f[i];
+            if (lw_ey(i) == -1) {
+                in[i] = v;
+            } else if (lw_ey(i) == 0) {
+                in[i] = st.z[j - 1][lw_yslot(i)];
+                st.z[j - 1][lw_yslot(i)] = v;
+            } else {
+                in[i] = st.u[P][j - 1][lw_yslot(i)];
+                st.u[P][j - 1][lw_yslot(i)] = v;
+            }
+        }
+        // stage j holds valid rows from iteration 2j on, in columns j .. T-1-j
+        if (k >= 2 * j && tid >= j && tid < LW_THREADS - j) {
+            collide_d2q9(in, r);
+            if (j < S) {
+#pragma unroll
+                for (int i = 0; i < 9; ++i) {
+                    f[i] = in[i];
+                    if (lw_ex(i) != 0) {
+                        const int c = tid + lw_ex(i);
+                        if (c >= 0 && c < LW_THREADS) lds[j & 1][lw_xslot(i)][c] = in[i];
+                    }
+                }
+            } else if (tid >= S && tid < S + W && x0 - S + tid < nx) {
+                const int row = wrapi(ys - 2 * S + k, ny) * nx + x0 - S + tid;
+#pragma unroll
+                for (int i = 0; i < 9; ++i) __builtin_nontemporal_store(in[i], dst + slot<9>(i, row));
+            }
+        }
+        if (j < S) __syncthreads();
+    }
+    // with S odd the last stage reads buffer 0, which the next load rewrites
+    if (S & 1) __syncthreads();
+}
+
+// Advance rows [ys, ye) of the columns [x0, x0 + LW_THREADS - 2S) of one
+// D2Q9 grid by S steps (reads rows ys-S .. ye-1+S and columns x0-S ..
+// x0+LW_THREADS-S-1, wrapped periodically).
+template <int S>
+__device__ __forceinline__ void lw_tile(const double* __restrict__ src, double* __restrict__ dst,
+                                        int nx, int ny, const FoldedRates& r, int x0, int ys, int ye,
+                                        double (&lds)[2][6][LW_THREADS]) {
+    const int gx = wrapi(x0 - S + (int)threadIdx.x, nx);
+    const int kend = ye - ys + 2 * S - 1;
+    LwState<S> st;
+    {
+        const int base = wrapi(ys - S, ny) * nx + gx;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) st.pre[i] = src[slot<9>(i, base)];
+    }
+#pragma unroll
+    for (int j = 0; j < S; ++j)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) st.z[j][a] = st.u[0][j][a] = st.u[1][j][a] = 0.0;
+    for (int k = 0; k <= kend; k += 2) {
+        lw_row<S, 0>(st, lds, k, kend, src, dst, nx, ny, gx, ys, x0, r);
+        if (k + 1 <= kend) lw_row<S, 1>(st, lds, k + 1, kend, src, dst, nx, ny, gx, ys, x0, r);
+    }
+}
+
+
+// Batched S-step pass: tile (inst, x0, y0, y1) = rows [y0, y1) of the strip
+// at x0 (batch_strip_width(S) columns) of one instance.
+template <int S>
+__global__ void __launch_bounds__(LW_THREADS) k_batch_steps(const BatchInst* __restrict__ insts,
                                                             const BatchTile* __restrict__ tiles,
                                                             const double* __restrict__ src,
                                                             double* __restrict__ dst) {
-    __shared__ double lds[2][6][MS_THREADS];
+    __shared__ double lds[2][6][LW_THREADS];
     const BatchTile t = tiles[xcd_remap(blockIdx.x, gridDim.x)];
     const BatchInst& in = insts[t.inst];
-    const Rates r = in.r;
-    ms_tile<S>(src + in.offset, dst + in.offset, in.nx, in.ny, r, t.x0, t.y0, t.pad, lds);
+    lw_tile<S>(src + in.offset, dst + in.offset, in.nx, in.ny, folded(in.r), t.x0, t.y0, t.pad,
+               lds);
 }
 
 template <typename F>
@@ -1081,13 +1209,31 @@ hipError_t launch_wall_from_dense1(const Geo& g, const double* dense, double* wa
     return hipGetLastError();
 }
 
-// Rows per segment of an S-step launch: about 1536 blocks (a few per CU at
-// the kernel's occupancy), at least 16 rows so that the 2S-row pipeline fill
-// stays a modest share of the march.
+// Rows per segment of an S-step launch.  A one-wave block of k_steps_d2q9
+// holds about 240 VGPRs, so a CU runs 8 of them at once: the segments are
+// cut so that all blocks fit in one round of 8 x (number of CUs) (fewer,
+// longer segments amortise the 2S-row pipeline fill; a partial second round
+// costs far more), at least 24 rows, and in more rounds when a segment would
+// exceed 512 rows.
 static int steps_rows(const Geo& g, int nstrips) {
-    const int64_t target = 1536;
-    int64_t ly = ((int64_t)g.ny * nstrips + target - 1) / target;
-    if (ly < 16) ly = 16;
+    static int slots = 0;
+    if (slots == 0) {
+        int dev = 0, cus = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            cus <= 0)
+            cus = 256;
+        slots = 8 * cus;
+    }
+    int64_t per_round = slots / nstrips;
+    if (per_round < 1) per_round = 1;
+    int64_t nseg = per_round;
+    int64_t ly = (g.ny + nseg - 1) / nseg;
+    while (ly > 512) {
+        nseg += per_round;
+        ly = (g.ny + nseg - 1) / nseg;
+    }
+    if (ly < 24) ly = 24;
     if (ly > g.ny) ly = g.ny;
     return (int)ly;
 }
@@ -1232,7 +1378,7 @@ hipError_t launch_finalize(const double* partials, int64_t n, double* g_eps, hip
 hipError_t launch_batch_steps(int nsteps, const BatchInst* insts, const BatchTile* tiles,
                               int64_t ntiles, const double* src, double* dst, hipStream_t st) {
     if (ntiles <= 0) return hipSuccess;
-    const dim3 grid((unsigned)ntiles), block(MS_THREADS);
+    const dim3 grid((unsigned)ntiles), block(LW_THREADS);
     switch (nsteps) {
         case 2: hipLaunchKernelGGL(k_batch_steps<2>, grid, block, 0, st, insts, tiles, src, dst); break;
         case 4: hipLaunchKernelGGL(k_batch_steps<4>, grid, block, 0, st, insts, tiles, src, dst); break;

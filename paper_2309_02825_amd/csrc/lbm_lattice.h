@@ -214,16 +214,23 @@ __device__ __forceinline__ void reconstruct(double theta, const double (&j)[D], 
 // double operations against about 60 for the generic form.  The library is
 // built without floating-point contraction, so every kernel that calls this
 // performs the same roundings.
-__device__ __forceinline__ void collide_d2q9(double (&f)[9], const Rates& r) {
+struct FoldedRates {
+    double cj, cp, ct, cq, wd;  // f_cj, f_cp, f_ct, f_cq and w_d of Rates
+};
+__host__ __device__ __forceinline__ FoldedRates folded(const Rates& r) {
+    return FoldedRates{r.f_cj, r.f_cp, r.f_ct, r.f_cq, r.wd};
+}
+
+__device__ __forceinline__ void collide_d2q9(double (&f)[9], const FoldedRates& r) {
     const double xp = f[1] + f[5] + f[8], xm = f[3] + f[6] + f[7];
     const double yp = f[2] + f[5] + f[6], ym = f[4] + f[7] + f[8];
     const double jx = xp - xm, Px = xp + xm, jy = yp - ym, Py = yp + ym;
     const double th = f[0] + (f[2] + f[4]) + Px;
     const double Pxy = (f[5] + f[7]) - (f[6] + f[8]);
-    const double hjx = r.f_cj * jx, hjy = r.f_cj * jy;
-    const double tt = r.f_ct * th;
-    const double hPx = fma(r.f_cp, Px, tt), hPy = fma(r.f_cp, Py, tt);
-    const double eR = r.wd * th, eP = r.f_cq * Pxy;
+    const double hjx = r.cj * jx, hjy = r.cj * jy;
+    const double tt = r.ct * th;
+    const double hPx = fma(r.cp, Px, tt), hPy = fma(r.cp, Py, tt);
+    const double eR = r.wd * th, eP = r.cq * Pxy;
     f[0] = fma(-2.0, hPx + hPy, th - 4.0 * eR);
     f[1] = hPx + hjx;
     f[3] = hPx - hjx;
@@ -242,7 +249,7 @@ __device__ __forceinline__ void collide_d2q9(double (&f)[9], const Rates& r) {
 // population is (theta - 12 eR) - 2 (hP_x + hP_y + hP_z), which again keeps
 // sum_i f_i = theta up to unbiased rounding.  75 double operations against
 // about 140 for the generic form.
-__device__ __forceinline__ void collide_d3q19(double (&f)[19], const Rates& r) {
+__device__ __forceinline__ void collide_d3q19(double (&f)[19], const FoldedRates& r) {
     // partial sums over the five velocities with e_a = +1 / -1
     const double xp = (f[1] + f[7]) + (f[10] + f[11]) + f[14];
     const double xm = (f[4] + f[8]) + (f[9] + f[12]) + f[13];
@@ -257,11 +264,11 @@ __device__ __forceinline__ void collide_d3q19(double (&f)[19], const Rates& r) {
     const double Pxy = (f[7] + f[9]) - (f[8] + f[10]);
     const double Pxz = (f[11] + f[13]) - (f[12] + f[14]);
     const double Pyz = (f[15] + f[17]) - (f[16] + f[18]);
-    const double tt = r.f_ct * th;
-    const double hPx = fma(r.f_cp, Px, tt), hPy = fma(r.f_cp, Py, tt), hPz = fma(r.f_cp, Pz, tt);
-    const double hjx = r.f_cj * jx, hjy = r.f_cj * jy, hjz = r.f_cj * jz;
+    const double tt = r.ct * th;
+    const double hPx = fma(r.cp, Px, tt), hPy = fma(r.cp, Py, tt), hPz = fma(r.cp, Pz, tt);
+    const double hjx = r.cj * jx, hjy = r.cj * jy, hjz = r.cj * jz;
     const double eR = r.wd * th;
-    const double exy = r.f_cq * Pxy, exz = r.f_cq * Pxz, eyz = r.f_cq * Pyz;
+    const double exy = r.cq * Pxy, exz = r.cq * Pxz, eyz = r.cq * Pyz;
     f[0] = fma(-2.0, (hPx + hPy) + hPz, th - 12.0 * eR);
     f[1] = hPx + hjx;
     f[4] = hPx - hjx;
@@ -287,11 +294,11 @@ __device__ __forceinline__ void collide_d3q19(double (&f)[19], const Rates& r) {
 template <int D>
 __device__ __forceinline__ void collide(double (&f)[Lat<D>::Q], const Rates& r) {
     if constexpr (D == 2) {
-        collide_d2q9(f, r);
+        collide_d2q9(f, folded(r));
         return;
     }
     if constexpr (D == 3) {
-        collide_d3q19(f, r);
+        collide_d3q19(f, folded(r));
         return;
     }
     Moments<D> m;
