@@ -211,15 +211,13 @@ class VelocityFunction(torch.autograd.Function):
         s.init(theta0, None)
         starts = checkpoint_segments(nsteps, nseg)
         ckpts = []
-        cur = s.bufs[0]
-        other = s.bufs[1]
         for k, st in enumerate(starts):
-            ckpts.append(cur.clone())
+            # the solver's current buffer holds the state at step st; the
+            # segment runs with multi-step passes (bitwise single steps)
+            ckpts.append(s.current().clone())
             end = starts[k + 1] if k + 1 < len(starts) else nsteps
-            for _ in range(st, end):
-                s.step_buffers(cur, other)
-                cur, other = other, cur
-        final = cur
+            s.step(end - st)
+        final = s.current().clone()
         _, u = s.macro(final)
         ctx.solver = s
         ctx.starts = starts
