@@ -274,10 +274,11 @@ lb_status lb_batch_init(lb_batch* b, const double* theta0, const double* grad);
 
 /* Tile shape of the batched step (Sec. III.A scheme, the same arithmetic in
  * every mode, so all modes give bitwise identical states):
- *   (-1, rows)  two steps per pass over each instance: tiles of 128 columns x
- *               rows rows (1 <= rows <= 65535) that keep the intermediate
- *               step in LDS; an odd step count ends with one linear-tile
- *               step.  (-1, 64) is the default of a new batch;
+ *   (-S, rows)  S = 2, 4 or 8 steps per pass over each instance: tiles of
+ *               128 - 2S columns x rows rows (1 <= rows <= 65535) that keep
+ *               the intermediate steps on chip; a run of n steps takes n / S
+ *               such passes and n mod S linear-tile single steps.  (-8, 64)
+ *               is the default of a new batch;
  *   (0, 0)      one step per pass, linear tiles of 256 consecutive node
  *               indices of one instance (crossing row ends);
  *   (tx, ty)    one step per pass, tx x ty rectangles with tx*ty = 256 and tx
@@ -286,7 +287,7 @@ lb_status lb_batch_init(lb_batch* b, const double* theta0, const double* grad);
  * LB_ERR_INVALID_ARG. */
 lb_status lb_batch_set_tile(lb_batch* b, int32_t tx, int32_t ty);
 
-/* Time candidate tile shapes, one-step and two-step, per step on the real
+/* Time candidate tile shapes, one-step and multi-step, per step on the real
  * pools (the current state is left as it was; the other pool is used as
  * scratch) and keep the fastest; best_tx/best_ty receive the choice (may be
  * NULL). */
