@@ -9,7 +9,12 @@ the tolerances below.  Cells are compared as relative differences.
 Tolerances: theta cells agree to a few units in the fifth printed digit; the
 u cells at eps = 0.3/0.4 likewise; the Table 2 u cells at eps = 0.1/0.2 carry
 a level-independent offset of up to 0.8% that the paper does not explain, so
-they get 1e-2.  The finest levels run only with LBM_SLOW=1.
+they get 1e-2.  Cells close to the double-precision floor (the finest levels,
+RMSEs of 1e-10 .. 1e-14) differ from the printed ones by rounding: two FP64
+implementations of the scheme drift apart by about eps_mach sqrt(N) max|theta|
+after N steps (a random walk of per-step roundings), so every cell also
+accepts an absolute difference of 2 eps_mach sqrt(N) max|theta0|.  The finest
+levels run only with LBM_SLOW=1.
 """
 import math
 import os
@@ -24,11 +29,16 @@ from tests.helpers import read_table, read_table4, rmse_closed
 SLOW = os.environ.get("LBM_SLOW", "") == "1"
 
 
+def _floor(nsteps, th0):
+    """Absolute rounding floor of an RMSE after nsteps (see the module note)."""
+    return 2.0 * np.finfo(np.float64).eps * math.sqrt(max(nsteps, 1)) * float(np.max(np.abs(th0)))
+
+
 def _run(wl):
     th0, g0 = W.evaluate(wl.modes, wl.grid, wl.dx)
     th, u, _ = O.solve(th0, g0, wl.dx, wl.dt, wl.nu, wl.nsteps)
     te, ue = W.exact(wl, wl.nsteps * wl.dt)
-    out = {"theta": rmse_closed(th, te)}
+    out = {"theta": rmse_closed(th, te), "_floor": _floor(wl.nsteps, th0)}
     for a, name in enumerate(["u_x", "u_y", "u_z"][: wl.d]):
         out[name] = rmse_closed(u[a], ue[a])
     return out
@@ -68,9 +78,10 @@ def test_printed_rmse(table):
             printed = vals[level]
             if printed is None:
                 continue
-            got = _cached(table, eps, level)[var]
-            rel = abs(got - printed) / printed
-            assert rel < _tol(table, eps, var), (table, eps, var, level, got, printed)
+            cell = _cached(table, eps, level)
+            got = cell[var]
+            assert abs(got - printed) < max(_tol(table, eps, var) * printed, cell["_floor"]), \
+                (table, eps, var, level, got, printed)
             checked += 1
     assert checked >= (36 if table == 2 else 30)
 
@@ -100,7 +111,7 @@ def _run4(eps, t_end, level):
     th0, g0 = W.evaluate(wl.modes, wl.grid, wl.dx)
     th, u, _ = O.solve(th0, g0, wl.dx, wl.dt, wl.nu, wl.nsteps)
     te, ue = W.exact(wl, wl.nsteps * wl.dt)
-    out = {"theta": 0.5 * rmse_closed(th, te)}
+    out = {"theta": 0.5 * rmse_closed(th, te), "_floor": _floor(wl.nsteps, th0)}
     for a in range(4):
         out[f"u_x{a + 1}"] = rmse_closed(u[a], ue[a])
     return out
@@ -124,7 +135,8 @@ def test_printed_rmse_table4():
                 cache[key] = _run4(eps, t_end, level)
             got = cache[key][var]
             tol = 1e-3 if printed < 1e-12 else 3e-4
-            assert abs(got - printed) / printed < tol, (eps, t_end, var, level, got, printed)
+            assert abs(got - printed) < max(tol * printed, cache[key]["_floor"]), \
+                (eps, t_end, var, level, got, printed)
             checked += 1
     assert checked >= 20
 
