@@ -177,6 +177,50 @@ def form_heat1d(torch, SV, W, dev):
     return out
 
 
+def form_example1(torch, SV, W, dev):
+    """Example 1 (1-D interval, theta prescribed at the end nodes), eps = 0.5,
+    levels 0-3 to t = 2: time per solve (init, all steps in one LDS-resident
+    launch, macro) and the RMSEs against the exact solution beside Table 1's
+    printed values (level 0: 7.8613e-4 / 1.9827e-5)."""
+    import numpy as np
+    printed = {0: (7.8613e-4, 1.9827e-5), 1: (4.8926e-5, 1.1821e-6),
+               2: (3.0595e-6, 7.2429e-8), 3: (1.9139e-7, 4.4865e-9)}
+    out = {}
+    stream = torch.cuda.current_stream()
+    for level in range(4):
+        wl = W.paper_example1(level, 0.5)
+        th0, g0 = W.example1_theta0(wl)
+        th0 = torch.from_numpy(th0).to(dev)
+        g0 = torch.from_numpy(g0).to(dev)
+        walls = torch.from_numpy(W.example1_walls(wl)).to(dev)
+        s = SV.Solver(wl.grid, wl.dx, wl.dt, wl.nu, device=dev, bounded=True)
+
+        def solve():
+            s.init(th0, g0)
+            s.step_bounded(walls)
+            return s.macro()
+
+        solve()
+        timer = Timer(torch, stream)
+        reps = 10
+        timer.start()
+        for _ in range(reps):
+            th, u = solve()
+        timer.stop()
+        torch.cuda.synchronize()
+        x = np.arange(wl.grid[0]) * wl.dx
+        te, ue = W.example1_exact(wl.nu, x, wl.nsteps * wl.dt)
+        r_th = float(np.sqrt(np.mean((th.cpu().numpy() - te) ** 2)))
+        r_u = float(np.sqrt(np.mean((u[0].cpu().numpy() - ue) ** 2)))
+        us = timer.total_ms() / reps * 1e3
+        out[f"level{level}"] = {"nodes": wl.grid[0], "lb_steps": wl.nsteps,
+                                "us_per_solve": round(us, 2),
+                                "rmse_theta": float(f"{r_th:.5g}"), "rmse_u": float(f"{r_u:.5g}"),
+                                "table1_theta": printed[level][0], "table1_u": printed[level][1]}
+        s.close()
+    return out
+
+
 def form_batched(torch, SV, W, dev):
     insts = W.batch_instances()
     bs = SV.BatchSolver(insts, device=dev)
@@ -401,6 +445,8 @@ def main():
             log(name, forms[name])
         forms["heat1d_sweep"] = form_heat1d(torch, SV, W, dev)
         log("heat1d_sweep", forms["heat1d_sweep"])
+        forms["example1_bounded"] = form_example1(torch, SV, W, dev)
+        log("example1_bounded", forms["example1_bounded"])
         b = form_batched(torch, SV, W, dev)
         plain = V / (kms / 1e3) / 1e6 if d == 2 else None
         if plain:

@@ -14,6 +14,7 @@
 //
 // Every thread owns one node; a block is 256 consecutive nodes of one row;
 // y and (3-D) z run over grid.y and grid.z.
+#include <atomic>
 #include <type_traits>
 
 #include "lbm_kernels.h"
@@ -141,24 +142,26 @@ __global__ void __launch_bounds__(256) k_step(const double* __restrict__ src,
 }
 
 // Small 1-D grids (n <= RESIDENT_MAX_1D): the whole state lives in LDS and
-// one workgroup advances all nsteps in a single launch, so the run is not
-// bound by one kernel launch per step.  Same collision as k_step<1>.
-constexpr int RES_THREADS = 256;
-
+// one workgroup of T threads (PER nodes each, T * PER >= n) advances all
+// nsteps in a single launch, so the run is not bound by one kernel launch per
+// step; the smallest fitting shape keeps the per-step work and barrier cost
+// proportional to n.  Same collision as k_step<1>.
+//
 // With walls != NULL the interval is bounded (wall_pull1): step s forms the
 // distribution of the time whose boundary theta is wall_now (s = 0) or
 // walls[2(s-1) .. 2(s-1)+1]; at the end wall_now takes the last pair.
-__global__ void __launch_bounds__(RES_THREADS) k_step_resident1(const double* __restrict__ src,
-                                                                double* __restrict__ dst, int n,
-                                                                int64_t nsteps, Rates r,
-                                                                const double* __restrict__ walls,
-                                                                double* __restrict__ wall_now) {
+template <int T, int PER>
+__global__ void __launch_bounds__(T) k_step_resident1(const double* __restrict__ src,
+                                                      double* __restrict__ dst, int n,
+                                                      int64_t nsteps, Rates r,
+                                                      const double* __restrict__ walls,
+                                                      double* __restrict__ wall_now) {
+    constexpr int RES_THREADS = T;
     __shared__ double lds[3 * RESIDENT_MAX_1D];
     for (int x = threadIdx.x; x < n; x += RES_THREADS)
 #pragma unroll
         for (int i = 0; i < 3; ++i) lds[i * RESIDENT_MAX_1D + x] = src[slot<3>(i, x)];
     __syncthreads();
-    constexpr int PER = (RESIDENT_MAX_1D + RES_THREADS - 1) / RES_THREADS;
     for (int64_t s = 0; s < nsteps; ++s) {
         const double* wall = walls ? (s == 0 ? wall_now : walls + 2 * (s - 1)) : nullptr;
         double f[PER][3];
@@ -1173,8 +1176,18 @@ hipError_t launch_step_resident1(const Geo& g, const Rates& r, const double* src
                                 hipStream_t st) {
     if (g.nx > RESIDENT_MAX_1D || g.ny != 1 || g.nz != 1 || g.nw != 1) return hipErrorInvalidValue;
     if (walls && (!wall_now || g.nx < 2)) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_step_resident1, dim3(1), dim3(RES_THREADS), 0, st, src, dst, g.nx, nsteps,
-                       r, walls, wall_now);
+    const int n = g.nx;
+#define LBM_RES1(T, PER)                                                                          \
+    hipLaunchKernelGGL((k_step_resident1<T, PER>), dim3(1), dim3(T), 0, st, src, dst, n, nsteps, r, \
+                       walls, wall_now)
+    if (n <= 64) LBM_RES1(64, 1);
+    else if (n <= 128) LBM_RES1(64, 2);
+    else if (n <= 256) LBM_RES1(128, 2);
+    else if (n <= 512) LBM_RES1(256, 2);
+    else if (n <= 1024) LBM_RES1(256, 4);
+    else LBM_RES1(256, 8);
+#undef LBM_RES1
+    static_assert(256 * 8 >= RESIDENT_MAX_1D, "resident shapes cover RESIDENT_MAX_1D");
     return hipGetLastError();
 }
 
@@ -1215,16 +1228,28 @@ hipError_t launch_wall_from_dense1(const Geo& g, const double* dense, double* wa
 // longer segments amortise the 2S-row pipeline fill; a partial second round
 // costs far more), at least 24 rows, and in more rounds when a segment would
 // exceed 512 rows.
-static int steps_rows(const Geo& g, int nstrips) {
-    static int slots = 0;
+// Blocks of k_steps_d2q9 one round holds on the current device (8 per CU),
+// looked up once per device.
+static int round_slots() {
+    constexpr int kMaxDevices = 64;
+    static std::atomic<int> cached[kMaxDevices] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0) dev = 0;
+    const int d = dev < kMaxDevices ? dev : kMaxDevices - 1;
+    int slots = cached[d].load(std::memory_order_relaxed);
     if (slots == 0) {
-        int dev = 0, cus = 0;
-        if (hipGetDevice(&dev) != hipSuccess ||
-            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
             cus <= 0)
             cus = 256;
         slots = 8 * cus;
+        cached[d].store(slots, std::memory_order_relaxed);
     }
+    return slots;
+}
+
+static int steps_rows(const Geo& g, int nstrips) {
+    const int slots = round_slots();
     int64_t per_round = slots / nstrips;
     if (per_round < 1) per_round = 1;
     int64_t nseg = per_round;
