@@ -320,6 +320,82 @@ __device__ __forceinline__ double lane_shift(double x) {
     return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
+// value of a double in the lane on the left (DIR = +1) or right (DIR = -1),
+// rotating around the wave (lane 0 takes lane 63 and vice versa)
+template <int DIR>
+__device__ __forceinline__ double lane_rotate(double x) {
+    constexpr int ctrl = DIR == 1 ? 0x13C : 0x134;  // wave_ror:1 : wave_rol:1
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffff), ctrl, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), ctrl, 0xf, 0xf, true);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// ---------------------------------------------------------------------------
+// Small 1-D grids in one wave: lane l holds nodes l*PER .. l*PER+PER-1 in
+// registers for the whole run; each step pulls f_{+1} from the node on the
+// left and f_{-1} from the node on the right, inside the lane by register
+// moves and across lanes by one DPP move each (a rotation for a periodic grid
+// of exactly 64*PER nodes, a plain shift on a bounded interval, where the end
+// nodes then take the wall rule of wall_pull1).  No LDS and no barrier; the
+// arithmetic is that of k_step<1> / k_step_resident1.
+// ---------------------------------------------------------------------------
+template <int PER, bool PERIODIC>
+__global__ void __launch_bounds__(64) k_step_wave1(const double* __restrict__ src,
+                                                   double* __restrict__ dst, int n, int64_t nsteps,
+                                                   Rates r, const double* __restrict__ walls,
+                                                   double* __restrict__ wall_now) {
+    const int lane = threadIdx.x;
+    double s0[PER], sp[PER], sm[PER];
+#pragma unroll
+    for (int p = 0; p < PER; ++p) {
+        const int x = lane * PER + p;
+        s0[p] = x < n ? src[slot<3>(0, x)] : 0.0;
+        sp[p] = x < n ? src[slot<3>(1, x)] : 0.0;
+        sm[p] = x < n ? src[slot<3>(2, x)] : 0.0;
+    }
+    for (int64_t s = 0; s < nsteps; ++s) {
+        const double left = PERIODIC ? lane_rotate<1>(sp[PER - 1]) : lane_shift<1>(sp[PER - 1]);
+        const double right = PERIODIC ? lane_rotate<-1>(sm[0]) : lane_shift<-1>(sm[0]);
+        double w0 = 0.0, w1 = 0.0;
+        if (!PERIODIC) {
+            const double* wall = s == 0 ? wall_now : walls + 2 * (s - 1);
+            w0 = wall[0];
+            w1 = wall[1];
+        }
+        double t0[PER], tp[PER], tm[PER];
+#pragma unroll
+        for (int p = 0; p < PER; ++p) {
+            const int x = lane * PER + p;
+            double g[3] = {s0[p], p > 0 ? sp[p - 1] : left, p < PER - 1 ? sm[p + 1] : right};
+            if (!PERIODIC) {
+                if (x == 0) g[1] = w0 - (g[0] + g[2]);
+                if (x == n - 1) g[2] = w1 - (g[0] + g[1]);
+            }
+            collide<1>(g, r);
+            t0[p] = g[0];
+            tp[p] = g[1];
+            tm[p] = g[2];
+        }
+#pragma unroll
+        for (int p = 0; p < PER; ++p) {
+            s0[p] = t0[p];
+            sp[p] = tp[p];
+            sm[p] = tm[p];
+        }
+    }
+#pragma unroll
+    for (int p = 0; p < PER; ++p) {
+        const int x = lane * PER + p;
+        if (x < n) {
+            dst[slot<3>(0, x)] = s0[p];
+            dst[slot<3>(1, x)] = sp[p];
+            dst[slot<3>(2, x)] = sm[p];
+        }
+    }
+    if (!PERIODIC && nsteps > 0 && lane < 2) wall_now[lane] = walls[2 * (nsteps - 1) + lane];
+}
+
 template <int S>
 struct MsState {
     double pre[9];      // next input row (prefetched)
@@ -1177,6 +1253,20 @@ hipError_t launch_step_resident1(const Geo& g, const Rates& r, const double* src
     if (g.nx > RESIDENT_MAX_1D || g.ny != 1 || g.nz != 1 || g.nw != 1) return hipErrorInvalidValue;
     if (walls && (!wall_now || g.nx < 2)) return hipErrorInvalidValue;
     const int n = g.nx;
+#define LBM_WAVE1(PER, PERIODIC)                                                                  \
+    hipLaunchKernelGGL((k_step_wave1<PER, PERIODIC>), dim3(1), dim3(64), 0, st, src, dst, n, nsteps, \
+                       r, walls, wall_now)
+    if (!walls) {
+        // periodic grids of exactly 64, 128 or 256 nodes: one wave, lane rotations
+        if (n == 64) { LBM_WAVE1(1, true); return hipGetLastError(); }
+        if (n == 128) { LBM_WAVE1(2, true); return hipGetLastError(); }
+        if (n == 256) { LBM_WAVE1(4, true); return hipGetLastError(); }
+    } else {
+        if (n <= 64) { LBM_WAVE1(1, false); return hipGetLastError(); }
+        if (n <= 128) { LBM_WAVE1(2, false); return hipGetLastError(); }
+        if (n <= 256) { LBM_WAVE1(4, false); return hipGetLastError(); }
+    }
+#undef LBM_WAVE1
 #define LBM_RES1(T, PER)                                                                          \
     hipLaunchKernelGGL((k_step_resident1<T, PER>), dim3(1), dim3(T), 0, st, src, dst, n, nsteps, r, \
                        walls, wall_now)

@@ -207,11 +207,14 @@ def test_set_state_roundtrip_and_step_buffers():
 
 
 def test_resident_1d_run_equals_per_step_launches():
-    """Small 1-D grids run all steps in one LDS-resident launch; the result is
-    bitwise the one of one launch per step."""
+    """Small 1-D grids run all steps in one launch (one wave with the state in
+    registers for periodic grids of 64, 128 and 256 nodes, LDS-resident
+    workgroups of other sizes up to 2048); the result is bitwise the one of
+    one launch per step."""
     _say("1d resident vs per-step")
     SV = _solver_mod()
-    for n, steps in ((300, 51), (2048, 20), (2049, 6), (1, 4)):
+    for n, steps in ((300, 51), (2048, 20), (2049, 6), (1, 4), (64, 33), (128, 17), (256, 9),
+                     (100, 12), (512, 5)):
         dx, dt, nu, th0, _ = _problem((n,), "random")
         outs = []
         for per_step in (True, False):
