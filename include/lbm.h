@@ -19,7 +19,8 @@
  *     torch tensors).  A solver borrows the pointers given to it and must be
  *     destroyed before they are freed.  The library owns only its host-side
  *     solver object and a few small device tables (parameters, reduction
- *     partials), allocated at creation and freed by lb_destroy.
+ *     partials), allocated at creation (lb_adjoint_segment grows one table
+ *     of per-step partials on demand) and freed by lb_destroy.
  *   - Work is enqueued asynchronously on the HIP stream given at creation
  *     (NULL = the default stream); the host returns before the GPU finishes.
  *   - Grid: n[a] nodes along x_a (x_0 fastest); unused dimensions must be 1.
@@ -236,6 +237,25 @@ lb_status lb_macro_adjoint(lb_solver* s, const double* state, const double* g_th
 lb_status lb_adjoint_step(lb_solver* s, const double* state_n, const double* lambda_in,
                           double* lambda_out, double* g_eps);
 
+/* One checkpoint segment of the reverse sweep, driven from the library (the
+ * sqrt(T) checkpointing of the discrete adjoint).  ckpt holds f^{n0} in the
+ * storage layout; the call recomputes f^{n0+1} .. f^{n0+m-1} into `work`
+ * (m - 1 consecutive state buffers of lb_state_bytes each; may be NULL when
+ * m = 1), bitwise as single steps would (on D2Q9 by multi-step passes that
+ * store every step, up to LB_OPT_STEPS_PER_PASS steps each), then applies
+ * the adjoint steps for n = n0+m-1 down to n0.  lambda: in dL/df^{n0+m}, out dL/df^{n0}; lambda_tmp is a second
+ * state buffer used as the ping-pong partner.  lambda on return is bitwise
+ * that of m lb_adjoint_step calls.  On D2Q9 the reverse sweep runs in passes
+ * of up to min(4, LB_OPT_STEPS_PER_PASS) adjoint steps (the forward passes' one-wave
+ * march with every velocity reversed); each wave sums the eps parts of its
+ * nodes in a fixed order, so *g_eps is deterministic but rounded differently
+ * from the single calls.  Other lattices take one adjoint step per launch
+ * and *g_eps is bitwise that of the single calls.  None of the buffers may
+ * overlap.  Errors: NULL pointers, m < 0, a bounded solver,
+ * LB_ERR_HIP if the partials table cannot grow to m tables. */
+lb_status lb_adjoint_segment(lb_solver* s, const double* ckpt, int64_t m, double* work,
+                             double* lambda, double* lambda_tmp, double* g_eps);
+
 /* Adjoint of lb_init: given lambda0 = dL/df^0 (canonical) writes g_theta0 (V).
  * If grad_theta0 != NULL the gradient input was independent and its adjoint
  * is written to g_grad (d x V, may be NULL); if grad_theta0 == NULL the
@@ -305,6 +325,8 @@ lb_status lb_batch_macro(lb_batch* b, double* theta, double* u);
 
 /* Current pool (pool_a or pool_b) and steps taken. */
 double* lb_batch_current(const lb_batch* b);
+/* Waits for the batch's stream, then frees the cached graphs and tile tables
+ * (the pools stay the caller's).  NULL is accepted. */
 lb_status lb_batch_destroy(lb_batch* b);
 
 /* Message for the last error on the calling thread ("" if none). */

@@ -168,7 +168,21 @@ struct lb_solver {
     int steps_per_pass;  // LB_OPT_STEPS_PER_PASS: 1, 2, 4 or 8
     bool bounded;        // LB_FLAG_BOUNDED
     double* wall_now;    // bounded: theta at the two end nodes at the current time
+    double* seg_partials;  // lb_adjoint_segment: one partials table per launch
+    int64_t seg_cap;       // doubles seg_partials holds
 };
+
+// Make s->seg_partials hold at least n doubles.
+static lb_status reserve_seg_partials(lb_solver* s, int64_t n) {
+    if (n <= s->seg_cap) return LB_OK;
+    if (s->seg_partials) (void)hipFree(s->seg_partials);
+    s->seg_partials = nullptr;
+    s->seg_cap = 0;
+    LB_HIP(hipMalloc((void**)&s->seg_partials, sizeof(double) * (size_t)n),
+           "hipMalloc segment partials");
+    s->seg_cap = n;
+    return LB_OK;
+}
 
 static lb_status not_bounded(const lb_solver* s, const char* what) {
     if (s->bounded) return fail(LB_ERR_STATE, what);
@@ -239,6 +253,8 @@ lb_status lb_create(const lb_config* cfg, void* hip_stream, double* f_a, double*
     s->flag = nullptr;
     s->bounded = (cfg->flags & LB_FLAG_BOUNDED) != 0;
     s->wall_now = nullptr;
+    s->seg_partials = nullptr;
+    s->seg_cap = 0;
     hipError_t e = hipMalloc((void**)&s->partials, sizeof(double) * (size_t)s->npartials);
     if (e == hipSuccess) e = hipMalloc((void**)&s->flag, sizeof(int));
     if (e == hipSuccess && s->bounded) e = hipMalloc((void**)&s->wall_now, 2 * sizeof(double));
@@ -257,6 +273,7 @@ lb_status lb_destroy(lb_solver* s) {
     if (s->partials) (void)hipFree(s->partials);
     if (s->flag) (void)hipFree(s->flag);
     if (s->wall_now) (void)hipFree(s->wall_now);
+    if (s->seg_partials) (void)hipFree(s->seg_partials);
     delete s;
     return LB_OK;
 }
@@ -497,6 +514,88 @@ lb_status lb_adjoint_step(lb_solver* s, const double* state_n, const double* lam
     return LB_OK;
 }
 
+lb_status lb_adjoint_segment(lb_solver* s, const double* ckpt, int64_t m, double* work,
+                             double* lambda, double* lambda_tmp, double* g_eps) {
+    if (!s || !ckpt || !lambda || !lambda_tmp || !g_eps)
+        return fail(LB_ERR_INVALID_ARG, "NULL argument");
+    if (m < 0) return fail(LB_ERR_INVALID_ARG, "m must be >= 0");
+    if (m > 1 && !work) return fail(LB_ERR_INVALID_ARG, "work is NULL");
+    if (lambda == lambda_tmp) return fail(LB_ERR_INVALID_ARG, "lambda == lambda_tmp");
+    lb_status st = not_bounded(s, "the adjoint is periodic only");
+    if (st != LB_OK) return st;
+    if (m == 0) return LB_OK;
+    const int64_t se = elements_of(&s->cfg);
+    // forward recomputation of the segment's states f^{n0+1} .. f^{n0+m-1}
+    // (bitwise single steps): on D2Q9 by multi-step passes that store the
+    // state after each of their steps, the rest one step at a time
+    const double* prev = ckpt;
+    int64_t j = 1;  // next state to produce
+    if (s->d == 2) {
+        for (int pass = s->steps_per_pass; pass >= 2; pass /= 2) {
+            for (; j + pass <= m; j += pass) {
+                double* out = work + (j - 1) * se;
+                LB_HIP(lbm::launch_steps_all(pass, s->g, s->r, prev, out, se, s->stream),
+                       "multi-step launch");
+                prev = out + (int64_t)(pass - 1) * se;
+            }
+        }
+    }
+    for (; j < m; ++j) {
+        double* nxt = work + (j - 1) * se;
+        LB_HIP(lbm::launch_step(s->d, s->g, s->r, prev, nxt, s->stream), "step launch");
+        prev = nxt;
+    }
+    double* lin = lambda;
+    double* lout = lambda_tmp;
+    if (s->d == 2) {
+        // reverse sweep in passes of up to steps_per_pass (at most 4) adjoint steps over
+        // n0+m-1 .. n0+1 (their states are consecutive in work), then the
+        // step at the checkpoint; every launch leaves a table of T partials
+        std::vector<int> plan;
+        int64_t left = m - 1;
+        for (int pass = std::min(s->steps_per_pass, lbm::MAX_ADJOINT_STEPS_PER_PASS); pass >= 1;
+             pass /= 2)
+            for (; left >= pass; left -= pass) plan.push_back(pass);
+        plan.push_back(1);
+        const int64_t T = lbm::adjoint_steps_table(s->g);
+        const int64_t nt = (int64_t)plan.size();
+        st = reserve_seg_partials(s, nt * (T + 1));
+        if (st != LB_OK) return st;
+        int64_t N = m;  // lin holds lambda^{n0+N}
+        for (int64_t t = 0; t < nt; ++t) {
+            const double* ftop = N == 1 ? ckpt : work + (N - 2) * se;  // f^{n0+N-1}
+            LB_HIP(lbm::launch_adjoint_steps(plan[t], s->g, s->r, lin, lout, ftop, se,
+                                             s->seg_partials + t * T, T, s->stream),
+                   "adjoint multi-step launch");
+            std::swap(lin, lout);
+            N -= plan[t];
+        }
+        LB_HIP(lbm::launch_finalize_tables(s->seg_partials, T, nt, s->seg_partials + nt * T,
+                                           g_eps, s->stream),
+               "finalize");
+    } else {
+        // one adjoint step per launch; step j leaves its block partials in
+        // table j, and one reduction adds the tables in the order of the steps
+        st = reserve_seg_partials(s, m * (s->npartials + 1));
+        if (st != LB_OK) return st;
+        for (j = m - 1; j >= 0; --j) {
+            const double* fn = j == 0 ? ckpt : work + (j - 1) * se;
+            LB_HIP(lbm::launch_adjoint_step(s->d, s->g, s->r, fn, lin, lout,
+                                            s->seg_partials + j * s->npartials, s->stream),
+                   "adjoint_step launch");
+            std::swap(lin, lout);
+        }
+        LB_HIP(lbm::launch_finalize_tables(s->seg_partials, s->npartials, m,
+                                           s->seg_partials + m * s->npartials, g_eps, s->stream),
+               "finalize");
+    }
+    if (lin != lambda)
+        LB_HIP(hipMemcpyAsync(lambda, lin, sizeof(double) * (size_t)se, hipMemcpyDeviceToDevice,
+                              s->stream),
+               "hipMemcpyAsync");
+    return LB_OK;
+}
+
 lb_status lb_init_adjoint(lb_solver* s, const double* theta0, const double* grad_theta0,
                           const double* lambda0, double* g_theta0, double* g_grad,
                           double* g_eps) {
@@ -672,6 +771,8 @@ lb_status lb_batch_create(const lb_config* cfgs, int32_t count, void* hip_stream
 
 lb_status lb_batch_destroy(lb_batch* b) {
     if (!b) return LB_OK;
+    // graphs and tile tables may still be in use by enqueued work
+    (void)hipStreamSynchronize(b->stream);
     drop_graphs(b);
     if (b->d_tiles) (void)hipFree(b->d_tiles);
     if (b->d_lin) (void)hipFree(b->d_lin);

@@ -53,6 +53,10 @@ constexpr int MAX_STEPS_PER_PASS = 8;
 __host__ __device__ constexpr int strip_width(int nsteps) { return MS_THREADS - 2 * nsteps; }
 hipError_t launch_steps(int nsteps, const Geo& g, const Rates& r, const double* src, double* dst,
                         hipStream_t st);
+// The same passes keeping every intermediate state: step j of the pass
+// (1..nsteps) goes to out + (j - 1) stride; the buffers must not overlap src.
+hipError_t launch_steps_all(int nsteps, const Geo& g, const Rates& r, const double* src,
+                            double* out, int64_t stride, hipStream_t st);
 // nsteps (2) D3Q19 steps in one pass; a block of MS3_TX x MS3_TY threads
 // produces a tile of tile_width3 x tile_height3 columns and marches along z.
 constexpr int MS3_TX = 64, MS3_TY = 8;
@@ -111,6 +115,20 @@ hipError_t launch_init_adjoint(int d, const Geo& g, const Rates& r, const double
                                const double* grad, const double* lambda0, double* g_theta0,
                                double* g_grad, double* partials, hipStream_t st);
 hipError_t launch_finalize(const double* partials, int64_t n, double* g_eps, hipStream_t st);
+// nsteps (1, 2 or 4) D2Q9 adjoint steps in one pass: lam_out = lambda^{N-nsteps}
+// from lam_in = lambda^N, with f^{N-j} at ftop - (j-1) stride; writes a table of
+// exactly ntab eps partials (ntab >= adjoint_steps_table(g)).  lam_out is
+// bitwise nsteps launch_adjoint_step calls.
+constexpr int MAX_ADJOINT_STEPS_PER_PASS = 4;
+int64_t adjoint_steps_table(const Geo& g);
+hipError_t launch_adjoint_steps(int nsteps, const Geo& g, const Rates& r, const double* lam_in,
+                                double* lam_out, const double* ftop, int64_t stride,
+                                double* partials, int64_t ntab, hipStream_t st);
+// m tables of n partials (table j at partials + j n) added to *g_eps table
+// by table, j = m-1 first: bitwise m launch_finalize calls in that order.
+// sums: m doubles of scratch.
+hipError_t launch_finalize_tables(const double* partials, int64_t n, int64_t m, double* sums,
+                                  double* g_eps, hipStream_t st);
 
 // Batched 2-D form.
 struct BatchInst {

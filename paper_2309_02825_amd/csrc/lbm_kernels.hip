@@ -404,11 +404,14 @@ struct MsState {
 };
 
 // One iteration k of the march; P = k & 1; stages above ACTIVE are skipped
-// (pipeline fill), stage S stores only when ACTIVE == S.
-template <int S, int P, int ACTIVE>
+// (pipeline fill), stage S stores only when ACTIVE == S.  ALL: stage j < S
+// also stores its rows of [ys, ye) to dst - (S - j) stride (the state after
+// j steps, for a caller that keeps every intermediate state).
+template <int S, int P, int ACTIVE, bool ALL>
 __device__ __forceinline__ void ms_row(MsState<S>& st, int k, int kend,
                                        const double* __restrict__ src, double* __restrict__ dst,
-                                       int nx, int ny, int gx, int ys, int x0, const FoldedRates& r) {
+                                       int nx, int ny, int gx, int ys, int x0, const FoldedRates& r,
+                                       int nrows, int64_t stride) {
     constexpr int W = MS_THREADS - 2 * S;
     const int lane = threadIdx.x;
     double f[9];
@@ -447,27 +450,40 @@ __device__ __forceinline__ void ms_row(MsState<S>& st, int k, int kend,
 #pragma unroll
                 for (int i = 0; i < 9; ++i) __builtin_nontemporal_store(in[i], dst + slot<9>(i, row));
             }
+            if (ALL && j < S) {
+                // row ys + k - S - j of step j; lanes S .. S+W-1 hold valid
+                // values from stage j on (the valid band shrinks one lane per
+                // side per stage)
+                const int rr = k - S - j;
+                if (rr >= 0 && rr < nrows && lane >= S && lane < S + W && x0 - S + lane < nx) {
+                    const int row = (ys + rr) * nx + x0 - S + lane;
+                    double* out = dst - (int64_t)(S - j) * stride;
+#pragma unroll
+                    for (int i = 0; i < 9; ++i)
+                        __builtin_nontemporal_store(in[i], out + slot<9>(i, row));
+                }
+            }
         }
     }
 }
 
-template <int S, int K>
+template <int S, int K, bool ALL>
 __device__ __forceinline__ void ms_fill(MsState<S>& st, int kend, const double* __restrict__ src,
                                         double* __restrict__ dst, int nx, int ny, int gx, int ys,
-                                        int x0, const FoldedRates& r) {
+                                        int x0, const FoldedRates& r, int nrows, int64_t stride) {
     if constexpr (K < 2 * S) {
-        ms_row<S, K & 1, K / 2>(st, K, kend, src, dst, nx, ny, gx, ys, x0, r);
-        ms_fill<S, K + 1>(st, kend, src, dst, nx, ny, gx, ys, x0, r);
+        ms_row<S, K & 1, K / 2, ALL>(st, K, kend, src, dst, nx, ny, gx, ys, x0, r, nrows, stride);
+        ms_fill<S, K + 1, ALL>(st, kend, src, dst, nx, ny, gx, ys, x0, r, nrows, stride);
     }
 }
 
 // Advance rows [ys, ye) (ye > ys) of the columns [x0, x0 + 64 - 2S) of one
 // D2Q9 grid by S steps (reads rows ys-S .. ye-1+S and columns x0-S ..
 // x0+63-S, wrapped periodically).  All 64 lanes of the wave must be active.
-template <int S>
+template <int S, bool ALL = false>
 __device__ __forceinline__ void ms_tile(const double* __restrict__ src, double* __restrict__ dst,
                                         int nx, int ny, const FoldedRates& r, int x0, int ys,
-                                        int ye) {
+                                        int ye, int64_t stride = 0) {
     const int gx = wrapi(x0 - S + (int)threadIdx.x, nx);
     const int kend = ye - ys + 2 * S - 1;  // >= 2S
     MsState<S> st;
@@ -480,10 +496,12 @@ __device__ __forceinline__ void ms_tile(const double* __restrict__ src, double* 
     for (int j = 0; j < S; ++j)
 #pragma unroll
         for (int a = 0; a < 3; ++a) st.z[j][a] = st.u[0][j][a] = st.u[1][j][a] = 0.0;
-    ms_fill<S, 0>(st, kend, src, dst, nx, ny, gx, ys, x0, r);
+    const int nrows = ye - ys;
+    ms_fill<S, 0, ALL>(st, kend, src, dst, nx, ny, gx, ys, x0, r, nrows, stride);
     for (int k = 2 * S; k <= kend; k += 2) {
-        ms_row<S, 0, S>(st, k, kend, src, dst, nx, ny, gx, ys, x0, r);
-        if (k + 1 <= kend) ms_row<S, 1, S>(st, k + 1, kend, src, dst, nx, ny, gx, ys, x0, r);
+        ms_row<S, 0, S, ALL>(st, k, kend, src, dst, nx, ny, gx, ys, x0, r, nrows, stride);
+        if (k + 1 <= kend)
+            ms_row<S, 1, S, ALL>(st, k + 1, kend, src, dst, nx, ny, gx, ys, x0, r, nrows, stride);
     }
 }
 
@@ -498,6 +516,173 @@ k_steps_d2q9(const double* __restrict__ src,
     const int seg = (int)(t / (unsigned)nstrips);
     const int ys = seg * ly;
     ms_tile<S>(src, dst, g.nx, g.ny, folded(r), strip * strip_width(S), ys, min(ys + ly, g.ny));
+}
+
+// The same pass writing the state after every one of its S steps: step j to
+// out + (j - 1) stride (the adjoint's recomputation of a checkpoint segment).
+template <int S>
+__global__ void __launch_bounds__(MS_THREADS) __attribute__((amdgpu_waves_per_eu(2)))
+k_steps_d2q9_all(const double* __restrict__ src, double* __restrict__ out, int64_t stride, Geo g,
+                 Rates r, int ly, int nstrips) {
+    const unsigned t = xcd_remap(blockIdx.x, gridDim.x);
+    const int strip = (int)(t % (unsigned)nstrips);
+    const int seg = (int)(t / (unsigned)nstrips);
+    const int ys = seg * ly;
+    ms_tile<S, true>(src, out + (int64_t)(S - 1) * stride, g.nx, g.ny, folded(r),
+                     strip * strip_width(S), ys, min(ys + ly, g.ny), stride);
+}
+
+// ---------------------------------------------------------------------------
+// S adjoint D2Q9 steps per pass (the reverse sweep of a checkpoint segment).
+//
+// An adjoint step maps lambda^{n+1} to lambda^n = C^T mu with
+// mu_i(x) = lambda^{n+1}_i(x + e_i): the forward step with every velocity
+// reversed and C^T in place of C.  The one-wave march of k_steps_d2q9 applies
+// with e -> -e (a population with e_y = +1 is used in the iteration its row
+// arrives, e_y = -1 two iterations later; e_x = +1 comes from the lane on the
+// right).  Stage j produces lambda^{N-j} from lambda^{N-j+1}; at the nodes the
+// wave owns it also adds the eps part <mu, (dC/deps) f^{N-j}>, with f^{N-j}
+// pulled from its state buffer at ftop - (j - 1) stride (ftop = f^{N-1}).
+// Each lane sums the eps parts of its nodes over all stages and rows in a
+// fixed order; the wave's sum goes to partials[block], and the blocks from
+// nblocks to ntab - 1 write zeros, so the table always holds ntab entries.
+// lambda is bitwise that of S launches of k_adjoint_step<2>.
+// ---------------------------------------------------------------------------
+__host__ __device__ constexpr int as_ex(int i) { return -Lat<2>::E[i][0]; }
+__host__ __device__ constexpr int as_ey(int i) { return -Lat<2>::E[i][1]; }
+
+template <int S>
+struct AsState : MsState<S> {
+    double fp[S][9];  // f^{N-j} at the node of the next iteration's row, per stage
+};
+
+// f^{N-j} pulled at node (x, y): population i from (x - e_i, y - e_i).
+__device__ __forceinline__ void as_load_f(double (&fn)[9], const double* __restrict__ fs, int x,
+                                          int y, int nx, int ny) {
+    const int rows[3] = {wrapi(y + 1, ny) * nx, y * nx, wrapi(y - 1, ny) * nx};
+    const int cols[3] = {x == nx - 1 ? 0 : x + 1, x, x == 0 ? nx - 1 : x - 1};
+#pragma unroll
+    for (int i = 0; i < 9; ++i) fn[i] = fs[slot<9>(i, rows[ms_ey(i) + 1] + cols[ms_ex(i) + 1])];
+}
+
+template <int S, int P, int ACTIVE>
+__device__ __forceinline__ void as_row(AsState<S>& st, double& ge, int k, int kend,
+                                       const double* __restrict__ src, double* __restrict__ dst,
+                                       const double* __restrict__ ftop, int64_t stride, int nx,
+                                       int ny, int gx, int ys, int x0, int nrows, const Rates& r) {
+    constexpr int W = MS_THREADS - 2 * S;
+    const int lane = threadIdx.x;
+    const int x = x0 - S + lane;
+    const bool own = lane >= S && lane < S + W && x < nx;
+    double f[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) f[i] = st.pre[i];
+    if (k < kend) {
+        const int base = wrapi(ys - S + k + 1, ny) * nx + gx;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) st.pre[i] = src[slot<9>(i, base)];
+    }
+#pragma unroll
+    for (int j = 1; j <= S; ++j) {
+        double in[9];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            const double v = as_ex(i) == 0 ? f[i]
+                                           : (as_ex(i) == 1 ? lane_shift<1>(f[i]) : lane_shift<-1>(f[i]));
+            if (as_ey(i) == -1) {
+                in[i] = v;
+            } else if (as_ey(i) == 0) {
+                in[i] = st.z[j - 1][ms_yslot(i)];
+                st.z[j - 1][ms_yslot(i)] = v;
+            } else {
+                in[i] = st.u[P][j - 1][ms_yslot(i)];
+                st.u[P][j - 1][ms_yslot(i)] = v;
+            }
+        }
+        if (j <= ACTIVE) {
+            const int rr = k - S - j;  // owned row ys + rr of this stage
+            if (own && rr >= 0 && rr < nrows) {
+                double df[9];
+                collide_deps<2>(st.fp[j - 1], r, df);
+#pragma unroll
+                for (int i = 0; i < 9; ++i) ge += in[i] * df[i];
+            }
+            double lam[9];
+            collide_adjoint<2>(in, r, lam);
+#pragma unroll
+            for (int i = 0; i < 9; ++i) f[i] = lam[i];
+            if (j == S && ACTIVE == S && own) {
+                const int row = (ys + k - 2 * S) * nx + x;
+#pragma unroll
+                for (int i = 0; i < 9; ++i) dst[slot<9>(i, row)] = lam[i];
+            }
+        }
+    }
+    // f^{N-j} for the rows the stages own in the next iteration
+#pragma unroll
+    for (int j = 1; j <= S; ++j) {
+        const int rr = k + 1 - S - j;
+        if (own && rr >= 0 && rr < nrows)
+            as_load_f(st.fp[j - 1], ftop - (int64_t)(j - 1) * stride, x, ys + rr, nx, ny);
+    }
+}
+
+template <int S, int K>
+__device__ __forceinline__ void as_fill(AsState<S>& st, double& ge, int kend,
+                                        const double* __restrict__ src, double* __restrict__ dst,
+                                        const double* __restrict__ ftop, int64_t stride, int nx,
+                                        int ny, int gx, int ys, int x0, int nrows, const Rates& r) {
+    if constexpr (K < 2 * S) {
+        as_row<S, K & 1, K / 2>(st, ge, K, kend, src, dst, ftop, stride, nx, ny, gx, ys, x0, nrows,
+                                r);
+        as_fill<S, K + 1>(st, ge, kend, src, dst, ftop, stride, nx, ny, gx, ys, x0, nrows, r);
+    }
+}
+
+template <int S>
+__global__ void __launch_bounds__(MS_THREADS) __attribute__((amdgpu_waves_per_eu(2)))
+k_adjoint_steps_d2q9(const double* __restrict__ src, double* __restrict__ dst,
+                     const double* __restrict__ ftop, int64_t stride,
+                     double* __restrict__ partials, int ntab, Geo g, Rates r, int ly,
+                     int nstrips) {
+    const int nx = g.nx, ny = g.ny;
+    const unsigned t = xcd_remap(blockIdx.x, gridDim.x);
+    const int strip = (int)(t % (unsigned)nstrips);
+    const int seg = (int)(t / (unsigned)nstrips);
+    const int x0 = strip * strip_width(S);
+    const int ys = seg * ly;
+    const int ye = min(ys + ly, ny);
+    const int gx = wrapi(x0 - S + (int)threadIdx.x, nx);
+    const int kend = ye - ys + 2 * S - 1;
+    const int nrows = ye - ys;
+    AsState<S> st;
+    {
+        const int base = wrapi(ys - S, ny) * nx + gx;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) st.pre[i] = src[slot<9>(i, base)];
+    }
+#pragma unroll
+    for (int j = 0; j < S; ++j) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) st.z[j][a] = st.u[0][j][a] = st.u[1][j][a] = 0.0;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) st.fp[j][i] = 0.0;
+    }
+    double ge = 0.0;
+    as_fill<S, 0>(st, ge, kend, src, dst, ftop, stride, nx, ny, gx, ys, x0, nrows, r);
+    for (int k = 2 * S; k <= kend; k += 2) {
+        as_row<S, 0, S>(st, ge, k, kend, src, dst, ftop, stride, nx, ny, gx, ys, x0, nrows, r);
+        if (k + 1 <= kend)
+            as_row<S, 1, S>(st, ge, k + 1, kend, src, dst, ftop, stride, nx, ny, gx, ys, x0, nrows,
+                            r);
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) ge += __shfl_xor(ge, o, 64);
+    if (threadIdx.x == 0) {
+        partials[blockIdx.x] = ge;
+        for (int i = (int)gridDim.x + (int)blockIdx.x; i < ntab; i += (int)gridDim.x)
+            partials[i] = 0.0;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -953,6 +1138,26 @@ __global__ void __launch_bounds__(256) k_finalize(const double* __restrict__ par
     if (threadIdx.x == 0) *g_eps += s;
 }
 
+// The reductions of k_finalize for m tables: block j sums table j with the
+// same tree into sums[j]; k_accumulate then adds sums[m-1], ..., sums[0] to
+// *g_eps one at a time, the order of m k_finalize launches.
+__global__ void __launch_bounds__(256) k_table_sums(const double* __restrict__ partials, int64_t n,
+                                                    double* __restrict__ sums) {
+    const double* p = partials + (int64_t)blockIdx.x * n;
+    double v = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += 256) v += p[i];
+    const double s = block_sum(v);
+    if (threadIdx.x == 0) sums[blockIdx.x] = s;
+}
+
+__global__ void __launch_bounds__(64) k_accumulate(const double* __restrict__ sums, int64_t m,
+                                                   double* g_eps) {
+    if (threadIdx.x != 0) return;
+    double acc = *g_eps;
+    for (int64_t j = m - 1; j >= 0; --j) acc += sums[j];
+    *g_eps = acc;
+}
+
 // ---------------------------------------------------------------------------
 // Burgers front end: theta0 from the initial velocity u0 (inverse Cole-Hopf
 // transformation, Sec. II: u = -2 nu grad(theta)/theta, so theta0 =
@@ -1316,8 +1521,10 @@ hipError_t launch_wall_from_dense1(const Geo& g, const double* dense, double* wa
 // holds about 240 VGPRs, so a CU runs 8 of them at once: the segments are
 // cut so that all blocks fit in one round of 8 x (number of CUs) (fewer,
 // longer segments amortise the 2S-row pipeline fill; a partial second round
-// costs far more), at least 24 rows, and in more rounds when a segment would
-// exceed 512 rows.
+// costs far more), at least 8 rows, and in more rounds when a segment would
+// exceed 512 rows.  Measured minimum (MLUPS at 8 steps per pass): 512^2
+// 47,500 at 24 rows, 70,200 at 8; 1024^2 132,000 and 148,300; 2048^2 and
+// 4096^2 unchanged (their segments are longer).
 // Blocks of k_steps_d2q9 one round holds on the current device (8 per CU),
 // looked up once per device.
 static int round_slots() {
@@ -1348,7 +1555,7 @@ static int steps_rows(const Geo& g, int nstrips) {
         nseg += per_round;
         ly = (g.ny + nseg - 1) / nseg;
     }
-    if (ly < 24) ly = 24;
+    if (ly < 8) ly = 8;
     if (ly > g.ny) ly = g.ny;
     return (int)ly;
 }
@@ -1389,6 +1596,66 @@ hipError_t launch_steps3(int nsteps, const Geo& g, const Rates& r, const double*
     if (g.nw != 1) return hipErrorInvalidValue;
     switch (nsteps) {
         case 2: return launch_steps3_t<2>(g, r, src, dst, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <int S>
+static hipError_t launch_steps_all_t(const Geo& g, const Rates& r, const double* src, double* out,
+                                     int64_t stride, hipStream_t st) {
+    const int w = strip_width(S);
+    const int nstrips = (g.nx + w - 1) / w;
+    const int ly = steps_rows(g, nstrips);
+    const int nseg = (g.ny + ly - 1) / ly;
+    hipLaunchKernelGGL(k_steps_d2q9_all<S>, dim3((unsigned)((int64_t)nstrips * nseg)),
+                       dim3(MS_THREADS), 0, st, src, out, stride, g, r, ly, nstrips);
+    return hipGetLastError();
+}
+
+hipError_t launch_steps_all(int nsteps, const Geo& g, const Rates& r, const double* src,
+                            double* out, int64_t stride, hipStream_t st) {
+    switch (nsteps) {
+        case 2: return launch_steps_all_t<2>(g, r, src, out, stride, st);
+        case 4: return launch_steps_all_t<4>(g, r, src, out, stride, st);
+        case 8: return launch_steps_all_t<8>(g, r, src, out, stride, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <int S>
+static int64_t adjoint_steps_blocks_t(const Geo& g) {
+    const int w = strip_width(S);
+    const int64_t nstrips = (g.nx + w - 1) / w;
+    const int ly = steps_rows(g, (int)nstrips);
+    return nstrips * ((g.ny + ly - 1) / ly);
+}
+
+int64_t adjoint_steps_table(const Geo& g) {
+    return std::max(adjoint_steps_blocks_t<1>(g),
+                    std::max(adjoint_steps_blocks_t<2>(g), adjoint_steps_blocks_t<4>(g)));
+}
+
+template <int S>
+static hipError_t launch_adjoint_steps_t(const Geo& g, const Rates& r, const double* lam_in,
+                                         double* lam_out, const double* ftop, int64_t stride,
+                                         double* partials, int64_t ntab, hipStream_t st) {
+    const int w = strip_width(S);
+    const int nstrips = (g.nx + w - 1) / w;
+    const int ly = steps_rows(g, nstrips);
+    const int64_t nb = (int64_t)nstrips * ((g.ny + ly - 1) / ly);
+    if (nb > ntab || ntab > (int64_t)INT32_MAX) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_adjoint_steps_d2q9<S>, dim3((unsigned)nb), dim3(MS_THREADS), 0, st,
+                       lam_in, lam_out, ftop, stride, partials, (int)ntab, g, r, ly, nstrips);
+    return hipGetLastError();
+}
+
+hipError_t launch_adjoint_steps(int nsteps, const Geo& g, const Rates& r, const double* lam_in,
+                                double* lam_out, const double* ftop, int64_t stride,
+                                double* partials, int64_t ntab, hipStream_t st) {
+    switch (nsteps) {
+        case 1: return launch_adjoint_steps_t<1>(g, r, lam_in, lam_out, ftop, stride, partials, ntab, st);
+        case 2: return launch_adjoint_steps_t<2>(g, r, lam_in, lam_out, ftop, stride, partials, ntab, st);
+        case 4: return launch_adjoint_steps_t<4>(g, r, lam_in, lam_out, ftop, stride, partials, ntab, st);
         default: return hipErrorInvalidValue;
     }
 }
@@ -1487,6 +1754,16 @@ hipError_t launch_init_adjoint(int d, const Geo& g, const Rates& r, const double
 
 hipError_t launch_finalize(const double* partials, int64_t n, double* g_eps, hipStream_t st) {
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, st, partials, n, g_eps);
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize_tables(const double* partials, int64_t n, int64_t m, double* sums,
+                                  double* g_eps, hipStream_t st) {
+    if (m < 1 || m > (int64_t)INT32_MAX) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_table_sums, dim3((unsigned)m), dim3(256), 0, st, partials, n, sums);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_accumulate, dim3(1), dim3(64), 0, st, sums, m, g_eps);
     return hipGetLastError();
 }
 

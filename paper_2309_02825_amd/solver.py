@@ -164,6 +164,12 @@ class Solver:
     def adjoint_step(self, state_n, lam_in, lam_out, g_eps):
         L.lb_adjoint_step(self.h, state_n, lam_in, lam_out, g_eps)
 
+    def adjoint_segment(self, ckpt, m: int, work, lam, lam_tmp, g_eps):
+        """Recompute m - 1 states after the checkpoint into ``work`` and run
+        m reverse steps; ``lam`` holds dL/df at the segment end on entry and
+        dL/df at the checkpoint on return."""
+        L.lb_adjoint_segment(self.h, ckpt, m, work, lam, lam_tmp, g_eps)
+
     def init_adjoint(self, theta0, grad, lam0, g_eps, want_grad: bool = False):
         g_theta0 = torch.empty(self.shape, dtype=F64, device=self.device)
         g_grad = (torch.empty((self.d,) + self.shape, dtype=F64, device=self.device)
@@ -237,18 +243,15 @@ class VelocityFunction(torch.autograd.Function):
         lam = s.macro_adjoint(ctx.final, None, g_u, g_eps)
         lam_other = s.new_state()
         starts, N = ctx.starts, ctx.nsteps
+        ends = starts[1:] + [N]
+        # one workspace for the recomputed states of the longest segment; the
+        # library runs each segment's recomputation and reverse sweep
+        longest = max(e - b for b, e in zip(starts, ends))
+        work = (torch.empty((longest - 1) * s.state_elems, dtype=F64, device=theta0.device)
+                if longest > 1 else None)
         for k in range(len(starts) - 1, -1, -1):
-            st = starts[k]
-            end = starts[k + 1] if k + 1 < len(starts) else N
-            states = [ctx.ckpts[k]]
-            for _ in range(st + 1, end):
-                nxt = s.new_state()
-                s.step_buffers(states[-1], nxt)
-                states.append(nxt)
-            for n in range(end - 1, st - 1, -1):
-                s.adjoint_step(states[n - st], lam, lam_other, g_eps)
-                lam, lam_other = lam_other, lam
-            del states
+            s.adjoint_segment(ctx.ckpts[k], ends[k] - starts[k], work, lam, lam_other, g_eps)
+        del work
         g_theta0, _ = s.init_adjoint(theta0, None, lam, g_eps)
         g_nu = g_eps.reshape(()) * (ctx.dt / (ctx.dx * ctx.dx))
         s.close()

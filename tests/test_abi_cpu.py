@@ -117,7 +117,8 @@ def test_batch_layout():
 
 
 def test_null_handles_are_rejected():
-    for fn, args in [(L.lb_step, (0, 1)), (L.lb_macro, (0,)), (L.lb_init, (0, None))]:
+    for fn, args in [(L.lb_step, (0, 1)), (L.lb_macro, (0,)), (L.lb_init, (0, None)),
+                     (L.lb_adjoint_segment, (0, None, 1, None, None, None, None))]:
         with pytest.raises(L.LBError):
             fn(*args)
     assert L.lb_steps_taken(0) == -1

@@ -634,6 +634,63 @@ def test_adjoint_dot_product_on_gpu():
     assert abs(lhs - rhs) <= 1e-12 * float((lam * fk).abs().sum().item())
 
 
+@pytest.mark.parametrize("grid,m", [((40, 28), 0), ((40, 28), 1), ((40, 28), 6), ((33, 21), 7),
+                                    ((130, 70), 12), ((61, 200), 17), ((5, 3), 10), ((1, 1), 9),
+                                    ((9, 7, 6), 5), ((30,), 4)])
+def test_adjoint_segment_equals_single_adjoint_steps(grid, m):
+    """lb_adjoint_segment (recomputation plus reverse sweep in the library)
+    against the sequence of single steps and single adjoint steps: the
+    recomputed states and lambda are bitwise equal for every pass limit; the
+    eps gradient is bitwise equal where the sweep runs one step per launch
+    (D1Q3, D3Q19) and equal to rounding where D2Q9 passes sum it per wave."""
+    _say("adjoint segment", grid, m)
+    SV = _solver_mod()
+    d = len(grid)
+    dx, nu = 1.0 / max(grid), 0.02
+    dt = {1: 0.3, 2: 0.17, 3: 0.12}[d] * dx * dx / nu
+    s = SV.Solver(grid, dx, dt, nu, device=_dev())
+    q = s.q
+    shape = (q,) + tuple(reversed(grid))
+    g = torch.Generator(device="cpu").manual_seed(11 + m)
+    v = (1.0 + 0.1 * torch.randn(shape, generator=g, dtype=torch.float64)).to(_dev())
+    lam = torch.randn(shape, generator=g, dtype=torch.float64).to(_dev())
+    s.set_state(v, 0)
+    ckpt = s.current().clone()
+    # reference: single calls
+    st = [ckpt]
+    for _ in range(1, m):
+        nxt = s.new_state()
+        s.step_buffers(st[-1], nxt)
+        st.append(nxt)
+    ge_ref = torch.full((1,), 0.25, dtype=torch.float64, device=_dev())
+    cur, other = s.to_layout(lam), s.new_state()
+    for n in range(m - 1, -1, -1):
+        s.adjoint_step(st[n], cur, other, ge_ref)
+        cur, other = other, cur
+    # the library's segment driver, with every pass limit
+    lam_ref = s.from_layout(cur)
+    for spp in ((1, 2, 4, 8) if d == 2 else (8,)):
+        s.set_steps_per_pass(spp)
+        ge = torch.full((1,), 0.25, dtype=torch.float64, device=_dev())
+        lam_c = s.to_layout(lam)
+        work = (torch.full(((m - 1) * s.state_elems,), float("nan"), dtype=torch.float64,
+                           device=_dev()) if m > 1 else None)
+        s.adjoint_segment(ckpt, m, work, lam_c, s.new_state(), ge)
+        torch.cuda.synchronize()
+        assert torch.equal(s.from_layout(lam_c), lam_ref), spp
+        if d == 2:
+            # random lambda and f: no cancellation, the two summation orders
+            # agree to a few units of rounding
+            assert abs(ge.item() - ge_ref.item()) <= 1e-12 * max(abs(ge_ref.item()), 1.0), spp
+        else:
+            assert ge.item() == ge_ref.item()
+        if m > 1:
+            for j in range(1, m):
+                seg = work[(j - 1) * s.state_elems: j * s.state_elems]
+                assert torch.equal(s.from_layout(seg), s.from_layout(st[j])), (spp, j)
+    s.close()
+
+
 # ---------------------------------------------------------------------------
 # batched form
 # ---------------------------------------------------------------------------
