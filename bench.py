@@ -325,6 +325,9 @@ def main():
                     help="override the LB time steps per solve (profiling runs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true")
+    ap.add_argument("--forms", default="all",
+                    help="comma-separated subset of the forms to run: steps_per_pass, grids, "
+                         "heat1d, example1, batched, adjoint (default all)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="first run a plain 1 GiB device copy (reference for HBM counters)")
     args = ap.parse_args()
@@ -406,7 +409,12 @@ def main():
         rec["cpu_baseline"] = cpu_baseline(wl)
     if not args.no_forms:
         forms = {}
-        if d == 2:
+        chosen = set(args.forms.split(",")) if args.forms != "all" else None
+
+        def want(name):
+            return chosen is None or name in chosen
+
+        if d == 2 and want("steps_per_pass"):
             # the same workload with at most 1, 2 and 4 steps per launch
             sweep = {}
             for spp in (1, 2, 4):
@@ -421,7 +429,7 @@ def main():
             forms[wl.name + "_steps_per_pass"] = sweep
             log("steps per pass", sweep)
         for name in ("heat2d_1024", "heat3d_256", "heat3d_512", "heat4d_64"):
-            if name == args.workload:
+            if name == args.workload or not want("grids"):
                 continue
             w2 = workload(name)
             n = {2: 2000, 3: 400, 4: 100}[w2.d]
@@ -443,19 +451,23 @@ def main():
                     "mlups": round(ml1, 1),
                     "frac": round(BYTES_PER_LU[3] * ml1 / 1e3 / HBM_PEAK_GBS, 4)}
             log(name, forms[name])
-        forms["heat1d_sweep"] = form_heat1d(torch, SV, W, dev)
-        log("heat1d_sweep", forms["heat1d_sweep"])
-        forms["example1_bounded"] = form_example1(torch, SV, W, dev)
-        log("example1_bounded", forms["example1_bounded"])
-        b = form_batched(torch, SV, W, dev)
-        plain = V / (kms / 1e3) / 1e6 if d == 2 else None
-        if plain:
-            b["mlups_ratio_vs_plain"] = round(b["mlups"] / plain, 4)
-        forms["batched"] = b
-        log("batched", b)
-        a = form_adjoint(torch, SV, W, dev)
-        forms["adjoint"] = a
-        log("adjoint", a)
+        if want("heat1d"):
+            forms["heat1d_sweep"] = form_heat1d(torch, SV, W, dev)
+            log("heat1d_sweep", forms["heat1d_sweep"])
+        if want("example1"):
+            forms["example1_bounded"] = form_example1(torch, SV, W, dev)
+            log("example1_bounded", forms["example1_bounded"])
+        if want("batched"):
+            b = form_batched(torch, SV, W, dev)
+            plain = V / (kms / 1e3) / 1e6 if d == 2 else None
+            if plain:
+                b["mlups_ratio_vs_plain"] = round(b["mlups"] / plain, 4)
+            forms["batched"] = b
+            log("batched", b)
+        if want("adjoint"):
+            a = form_adjoint(torch, SV, W, dev)
+            forms["adjoint"] = a
+            log("adjoint", a)
         rec["forms"] = forms
     print(json.dumps(rec), flush=True)
 

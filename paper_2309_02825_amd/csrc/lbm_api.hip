@@ -508,7 +508,7 @@ lb_status lb_adjoint_step(lb_solver* s, const double* state_n, const double* lam
     lb_status st = not_bounded(s, "the adjoint is periodic only");
     if (st != LB_OK) return st;
     LB_HIP(lbm::launch_adjoint_step(s->d, s->g, s->r, state_n, lambda_in, lambda_out, s->partials,
-                                    s->stream),
+                                    s->npartials, s->stream),
            "adjoint_step launch");
     LB_HIP(lbm::launch_finalize(s->partials, s->npartials, g_eps, s->stream), "finalize");
     return LB_OK;
@@ -557,16 +557,21 @@ lb_status lb_adjoint_segment(lb_solver* s, const double* ckpt, int64_t m, double
              pass /= 2)
             for (; left >= pass; left -= pass) plan.push_back(pass);
         plan.push_back(1);
-        const int64_t T = lbm::adjoint_steps_table(s->g);
+        const int64_t T = std::max(lbm::adjoint_steps_table(s->g), s->npartials);
         const int64_t nt = (int64_t)plan.size();
         st = reserve_seg_partials(s, nt * (T + 1));
         if (st != LB_OK) return st;
         int64_t N = m;  // lin holds lambda^{n0+N}
         for (int64_t t = 0; t < nt; ++t) {
             const double* ftop = N == 1 ? ckpt : work + (N - 2) * se;  // f^{n0+N-1}
-            LB_HIP(lbm::launch_adjoint_steps(plan[t], s->g, s->r, lin, lout, ftop, se,
-                                             s->seg_partials + t * T, T, s->stream),
-                   "adjoint multi-step launch");
+            if (plan[t] == 1)
+                LB_HIP(lbm::launch_adjoint_step(2, s->g, s->r, ftop, lin, lout,
+                                                s->seg_partials + t * T, T, s->stream),
+                       "adjoint_step launch");
+            else
+                LB_HIP(lbm::launch_adjoint_steps(plan[t], s->g, s->r, lin, lout, ftop, se,
+                                                 s->seg_partials + t * T, T, s->stream),
+                       "adjoint multi-step launch");
             std::swap(lin, lout);
             N -= plan[t];
         }
@@ -581,7 +586,8 @@ lb_status lb_adjoint_segment(lb_solver* s, const double* ckpt, int64_t m, double
         for (j = m - 1; j >= 0; --j) {
             const double* fn = j == 0 ? ckpt : work + (j - 1) * se;
             LB_HIP(lbm::launch_adjoint_step(s->d, s->g, s->r, fn, lin, lout,
-                                            s->seg_partials + j * s->npartials, s->stream),
+                                            s->seg_partials + j * s->npartials, s->npartials,
+                                            s->stream),
                    "adjoint_step launch");
             std::swap(lin, lout);
         }

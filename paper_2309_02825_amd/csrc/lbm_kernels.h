@@ -108,14 +108,15 @@ hipError_t launch_check_theta(const double* theta, int64_t n, int* flag, hipStre
 hipError_t launch_macro_adjoint(int d, const Geo& g, const Rates& r, const double* state,
                                 const double* g_theta, const double* g_u, double* lambda,
                                 double* partials, hipStream_t st);
+// partials: a table of ntab >= launch_shape(d, g).nblocks entries, all written.
 hipError_t launch_adjoint_step(int d, const Geo& g, const Rates& r, const double* state,
                                const double* lam_in, double* lam_out, double* partials,
-                               hipStream_t st);
+                               int64_t ntab, hipStream_t st);
 hipError_t launch_init_adjoint(int d, const Geo& g, const Rates& r, const double* theta0,
                                const double* grad, const double* lambda0, double* g_theta0,
                                double* g_grad, double* partials, hipStream_t st);
 hipError_t launch_finalize(const double* partials, int64_t n, double* g_eps, hipStream_t st);
-// nsteps (1, 2 or 4) D2Q9 adjoint steps in one pass: lam_out = lambda^{N-nsteps}
+// nsteps (2 or 4) D2Q9 adjoint steps in one pass: lam_out = lambda^{N-nsteps}
 // from lam_in = lambda^N, with f^{N-j} at ftop - (j-1) stride; writes a table of
 // exactly ntab eps partials (ntab >= adjoint_steps_table(g)).  lam_out is
 // bitwise nsteps launch_adjoint_step calls.

@@ -1013,12 +1013,13 @@ __global__ void __launch_bounds__(256) k_macro_adjoint(const double* __restrict_
 }
 
 // lam_out(x) = C^T mu(x), mu_i(x) = lam_in_i(x + e_i); eps part <mu, C' f^n(x)>.
+// One partial per block; blocks past the grid up to ntab - 1 are written zero.
 template <int D>
 __global__ void __launch_bounds__(256) k_adjoint_step(const double* __restrict__ state,
                                                       const double* __restrict__ lin,
                                                       double* __restrict__ lout,
-                                                      double* __restrict__ partials, Geo g,
-                                                      Rates r) {
+                                                      double* __restrict__ partials,
+                                                      int64_t ntab, Geo g, Rates r) {
     constexpr int Q = Lat<D>::Q;
     int c[4];
     double ge = 0.0;
@@ -1041,7 +1042,12 @@ __global__ void __launch_bounds__(256) k_adjoint_step(const double* __restrict__
         for (int i = 0; i < Q; ++i) lout[slot<Q>(i, k)] = lam[i];
     }
     const double s = block_sum(ge);
-    if (threadIdx.x == 0 && threadIdx.y == 0) partials[block_linear()] = s;
+    if (threadIdx.x == 0 && threadIdx.y == 0) {
+        const int64_t b = block_linear();
+        const int64_t nb = (int64_t)gridDim.x * gridDim.y * gridDim.z;
+        partials[b] = s;
+        for (int64_t t = nb + b; t < ntab; t += nb) partials[t] = 0.0;
+    }
 }
 
 // h_a(x) = d L / d g_a(x) for the gradient input of the initialisation:
@@ -1545,7 +1551,14 @@ static int round_slots() {
     return slots;
 }
 
-static int steps_rows(const Geo& g, int nstrips) {
+// Minimum rows per segment: plain passes 8; the passes of an adjoint
+// checkpoint segment (recomputation and reverse sweep) 3, since at the sizes
+// the adjoint runs (512^2) they are short of waves (measured per step of a
+// 45-step segment at 512^2: 15.1 us at 8 rows, 12.9 us at 3).
+constexpr int kMinRows = 8;
+constexpr int kMinRowsSegment = 3;
+
+static int steps_rows(const Geo& g, int nstrips, int min_rows) {
     const int slots = round_slots();
     int64_t per_round = slots / nstrips;
     if (per_round < 1) per_round = 1;
@@ -1555,7 +1568,7 @@ static int steps_rows(const Geo& g, int nstrips) {
         nseg += per_round;
         ly = (g.ny + nseg - 1) / nseg;
     }
-    if (ly < 8) ly = 8;
+    if (ly < min_rows) ly = min_rows;
     if (ly > g.ny) ly = g.ny;
     return (int)ly;
 }
@@ -1565,7 +1578,7 @@ static hipError_t launch_steps_t(const Geo& g, const Rates& r, const double* src
                                  hipStream_t st) {
     const int w = strip_width(S);
     const int nstrips = (g.nx + w - 1) / w;
-    const int ly = steps_rows(g, nstrips);
+    const int ly = steps_rows(g, nstrips, kMinRows);
     const int nseg = (g.ny + ly - 1) / ly;
     hipLaunchKernelGGL(k_steps_d2q9<S>, dim3((unsigned)((int64_t)nstrips * nseg)),
                        dim3(MS_THREADS), 0, st, src, dst, g, r, ly, nstrips);
@@ -1605,7 +1618,7 @@ static hipError_t launch_steps_all_t(const Geo& g, const Rates& r, const double*
                                      int64_t stride, hipStream_t st) {
     const int w = strip_width(S);
     const int nstrips = (g.nx + w - 1) / w;
-    const int ly = steps_rows(g, nstrips);
+    const int ly = steps_rows(g, nstrips, kMinRowsSegment);
     const int nseg = (g.ny + ly - 1) / ly;
     hipLaunchKernelGGL(k_steps_d2q9_all<S>, dim3((unsigned)((int64_t)nstrips * nseg)),
                        dim3(MS_THREADS), 0, st, src, out, stride, g, r, ly, nstrips);
@@ -1626,13 +1639,12 @@ template <int S>
 static int64_t adjoint_steps_blocks_t(const Geo& g) {
     const int w = strip_width(S);
     const int64_t nstrips = (g.nx + w - 1) / w;
-    const int ly = steps_rows(g, (int)nstrips);
+    const int ly = steps_rows(g, (int)nstrips, kMinRowsSegment);
     return nstrips * ((g.ny + ly - 1) / ly);
 }
 
 int64_t adjoint_steps_table(const Geo& g) {
-    return std::max(adjoint_steps_blocks_t<1>(g),
-                    std::max(adjoint_steps_blocks_t<2>(g), adjoint_steps_blocks_t<4>(g)));
+    return std::max(adjoint_steps_blocks_t<2>(g), adjoint_steps_blocks_t<4>(g));
 }
 
 template <int S>
@@ -1641,7 +1653,7 @@ static hipError_t launch_adjoint_steps_t(const Geo& g, const Rates& r, const dou
                                          double* partials, int64_t ntab, hipStream_t st) {
     const int w = strip_width(S);
     const int nstrips = (g.nx + w - 1) / w;
-    const int ly = steps_rows(g, nstrips);
+    const int ly = steps_rows(g, nstrips, kMinRowsSegment);
     const int64_t nb = (int64_t)nstrips * ((g.ny + ly - 1) / ly);
     if (nb > ntab || ntab > (int64_t)INT32_MAX) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_adjoint_steps_d2q9<S>, dim3((unsigned)nb), dim3(MS_THREADS), 0, st,
@@ -1653,7 +1665,6 @@ hipError_t launch_adjoint_steps(int nsteps, const Geo& g, const Rates& r, const 
                                 double* lam_out, const double* ftop, int64_t stride,
                                 double* partials, int64_t ntab, hipStream_t st) {
     switch (nsteps) {
-        case 1: return launch_adjoint_steps_t<1>(g, r, lam_in, lam_out, ftop, stride, partials, ntab, st);
         case 2: return launch_adjoint_steps_t<2>(g, r, lam_in, lam_out, ftop, stride, partials, ntab, st);
         case 4: return launch_adjoint_steps_t<4>(g, r, lam_in, lam_out, ftop, stride, partials, ntab, st);
         default: return hipErrorInvalidValue;
@@ -1742,8 +1753,9 @@ hipError_t launch_macro_adjoint(int d, const Geo& g, const Rates& r, const doubl
 
 hipError_t launch_adjoint_step(int d, const Geo& g, const Rates& r, const double* state,
                                const double* lam_in, double* lam_out, double* partials,
-                               hipStream_t st) {
-    return LBM_LAUNCH(k_adjoint_step, state, lam_in, lam_out, partials, g, r);
+                               int64_t ntab, hipStream_t st) {
+    if (ntab < launch_shape(d, g).nblocks) return hipErrorInvalidValue;
+    return LBM_LAUNCH(k_adjoint_step, state, lam_in, lam_out, partials, ntab, g, r);
 }
 
 hipError_t launch_init_adjoint(int d, const Geo& g, const Rates& r, const double* theta0,
