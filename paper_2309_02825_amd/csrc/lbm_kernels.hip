@@ -541,7 +541,8 @@ k_steps_d2q9_all(const double* __restrict__ src, double* __restrict__ out, int64
 // with e -> -e (a population with e_y = +1 is used in the iteration its row
 // arrives, e_y = -1 two iterations later; e_x = +1 comes from the lane on the
 // right).  Stage j produces lambda^{N-j} from lambda^{N-j+1}; at the nodes the
-// wave owns it also adds the eps part <mu, (dC/deps) f^{N-j}>, with f^{N-j}
+// wave owns it also adds the eps part <mu, (dC/deps) f^{N-j}> (through the
+// dual moments of mu, eps_part_d2q9), with f^{N-j}
 // pulled from its state buffer at ftop - (j - 1) stride (ftop = f^{N-1}).
 // Each lane sums the eps parts of its nodes over all stages and rows in a
 // fixed order; the wave's sum goes to partials[block], and the blocks from
@@ -601,12 +602,7 @@ __device__ __forceinline__ void as_row(AsState<S>& st, double& ge, int k, int ke
         }
         if (j <= ACTIVE) {
             const int rr = k - S - j;  // owned row ys + rr of this stage
-            if (own && rr >= 0 && rr < nrows) {
-                double df[9];
-                collide_deps<2>(st.fp[j - 1], r, df);
-#pragma unroll
-                for (int i = 0; i < 9; ++i) ge += in[i] * df[i];
-            }
+            if (own && rr >= 0 && rr < nrows) ge += eps_part_d2q9(in, st.fp[j - 1], r);
             double lam[9];
             collide_adjoint<2>(in, r, lam);
 #pragma unroll

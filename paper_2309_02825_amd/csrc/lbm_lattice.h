@@ -333,6 +333,30 @@ __device__ __forceinline__ void collide_deps(const double (&f)[Lat<D>::Q], const
     reconstruct<D>(0.0, j, P, Pab, 4.0 * r.dwd * m.theta, df);
 }
 
+// <mu, (dC/deps) f> for D2Q9 through the dual moments nu = M^-T mu (those
+// of collide_adjoint below): (dC/deps) f = M^-1 m' with m' holding
+// -ds1 j_a, -ds21 (P_a - theta/3), -ds22 P_xy and 4 dw_d theta on the
+// c_x^2 c_y^2 row (zero elsewhere), so the product is sum over rows of
+// nu_row m'_row.  Equal to sum_i mu_i df_i of collide_deps up to rounding.
+__device__ __forceinline__ double eps_part_d2q9(const double (&mu)[9], const double (&f)[9],
+                                                const Rates& r) {
+    const double xp = f[1] + f[5] + f[8], xm = f[3] + f[6] + f[7];
+    const double yp = f[2] + f[5] + f[6], ym = f[4] + f[7] + f[8];
+    const double jx = xp - xm, Px = xp + xm, jy = yp - ym, Py = yp + ym;
+    const double th = f[0] + (f[2] + f[4]) + Px;
+    const double Pxy = (f[5] + f[7]) - (f[6] + f[8]);
+    const double sx = mu[1] + mu[3], sy = mu[2] + mu[4];
+    const double se = (mu[5] + mu[7]), sd = (mu[6] + mu[8]);
+    const double nax = 0.5 * (mu[1] - mu[3]), nay = 0.5 * (mu[2] - mu[4]);
+    const double naax = 0.5 * sx - mu[0], naay = 0.5 * sy - mu[0];
+    const double nab = 0.25 * (se - sd);
+    const double naabb = (mu[0] - 0.5 * (sx + sy)) + 0.25 * (se + sd);
+    const double th3 = th * (1.0 / 3.0);
+    return (-r.ds1) * (nax * jx + nay * jy) +
+           (-r.ds21) * (naax * (Px - th3) + naay * (Py - th3)) + (-r.ds22) * (nab * Pxy) +
+           (4.0 * r.dwd) * (naabb * th);
+}
+
 // lam = C^T mu.  With C = M^-1 C_m M and C_m = I - S + S (M w) e_0^T,
 // C^T mu = M^T C_m^T nu with the dual moments nu = M^-T mu:
 //   nu_0   = mu_rest
