@@ -643,6 +643,7 @@ struct lb_batch {
     BatchTile* d_lin;  // linear tiles, for the steps a multi-step mode leaves over
     int64_t nlin;
     int tx, ty;
+    bool off32;  // every instance's state is under 4 GiB
     std::map<std::pair<int64_t, int>, hipGraphExec_t> graphs;
 };
 
@@ -732,6 +733,9 @@ lb_status lb_batch_create(const lb_config* cfgs, int32_t count, void* hip_stream
     b->offsets.resize(count);
     b->elems.resize(count);
     b->pool_elems = lb_batch_layout(cfgs, count, b->offsets.data(), b->elems.data());
+    b->off32 = true;
+    for (int32_t i = 0; i < count; ++i)
+        if ((uint64_t)b->elems[i] * sizeof(double) > 0xffffffffull) b->off32 = false;
     int64_t nodes = 0;
     for (int32_t i = 0; i < count; ++i) {
         b->node_offsets.push_back(nodes);
@@ -834,7 +838,7 @@ static lb_status batch_launch_plain(lb_batch* b, int64_t nsteps, hipStream_t st,
         int64_t n = 0;
         for (; n + S <= nsteps; n += S) {
             LB_HIP(lbm::launch_batch_steps(S, b->d_insts, b->d_tiles, b->ntiles, b->pool[cur],
-                                           b->pool[1 - cur], st),
+                                           b->pool[1 - cur], b->off32, st),
                    "batch multi-step launch");
             cur ^= 1;
         }
@@ -917,7 +921,8 @@ lb_status lb_batch_autotune(lb_batch* b, int32_t steps_per_trial, int32_t* best_
             for (int r = 0; r < reps; ++r) {
                 if (c[0] < 0)
                     LB_HIP(lbm::launch_batch_steps(per_launch, b->d_insts, b->d_tiles, b->ntiles,
-                                                   b->pool[b->cur], b->pool[1 - b->cur], b->stream),
+                                                   b->pool[b->cur], b->pool[1 - b->cur], b->off32,
+                                                   b->stream),
                            "batch multi-step launch");
                 else
                     LB_HIP(lbm::launch_batch_step(b->d_insts, b->d_tiles, b->ntiles, b->tx, b->ty,

@@ -148,7 +148,10 @@ hipError_t launch_batch_step(const BatchInst* insts, const BatchTile* tiles, int
 // batch_strip_width(nsteps) columns (blocks of LW_THREADS threads).
 constexpr int LW_THREADS = 128;
 __host__ __device__ constexpr int batch_strip_width(int nsteps) { return LW_THREADS - 2 * nsteps; }
+// off32: every instance's state is under 4 GiB (32-bit offsets from the
+// instance's start).
 hipError_t launch_batch_steps(int nsteps, const BatchInst* insts, const BatchTile* tiles,
-                              int64_t ntiles, const double* src, double* dst, hipStream_t st);
+                              int64_t ntiles, const double* src, double* dst, bool off32,
+                              hipStream_t st);
 
 }  // namespace lbm

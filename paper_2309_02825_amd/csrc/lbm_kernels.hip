@@ -396,6 +396,47 @@ __global__ void __launch_bounds__(64) k_step_wave1(const double* __restrict__ sr
     if (!PERIODIC && nsteps > 0 && lane < 2) wall_now[lane] = walls[2 * (nsteps - 1) + lane];
 }
 
+// Addressing of a D2Q9 chunked buffer by node index k (population i at
+// slot<9>(i, k)).  MsAddr<true>: the byte offset of population 0 as a 32-bit
+// value from the buffer start, population i then at a base that is the same
+// for the whole wave (buffer + i chunks), held in scalar registers; every
+// access is one load or store with a scalar base and a 32-bit lane offset, and
+// no 64-bit address arithmetic per access (the buffer must be under 4 GiB).
+// MsAddr<false>: 64-bit element indices, any size.  Both address the same
+// element, so the arithmetic and the results do not depend on the choice.
+typedef __attribute__((address_space(1))) char GChar;
+typedef __attribute__((address_space(1))) double GDouble;
+__device__ __forceinline__ GChar* wave_base(const double* p) {
+    const unsigned long long v = (unsigned long long)p;
+    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)v);
+    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(v >> 32));
+    return (GChar*)(((unsigned long long)hi << 32) | lo);
+}
+template <bool OFF32> struct MsAddr;
+template <> struct MsAddr<true> {
+    unsigned off;
+    __device__ __forceinline__ explicit MsAddr(int k)
+        : off((unsigned)((((k >> 12) * 9) << 12) | (k & (CHUNK - 1))) * 8u) {}
+    __device__ __forceinline__ double load(const double* p, int i) const {
+        return *(GDouble*)(wave_base(p + (int64_t)i * CHUNK) + off);
+    }
+    __device__ __forceinline__ void store(double* p, int i, double v) const {
+        __builtin_nontemporal_store(v, (GDouble*)(wave_base(p + (int64_t)i * CHUNK) + off));
+    }
+};
+template <> struct MsAddr<false> {
+    int k;
+    __device__ __forceinline__ explicit MsAddr(int k_) : k(k_) {}
+    __device__ __forceinline__ double load(const double* p, int i) const { return p[slot<9>(i, k)]; }
+    __device__ __forceinline__ void store(double* p, int i, double v) const {
+        __builtin_nontemporal_store(v, p + slot<9>(i, k));
+    }
+};
+// Whether a D2Q9 state buffer of g allows MsAddr<true>.
+__host__ __device__ inline bool ms_off32(const Geo& g) {
+    return (uint64_t)9 * (uint64_t)chunks_of(g.V) * CHUNK * sizeof(double) <= 0xffffffffull;
+}
+
 template <int S>
 struct MsState {
     double pre[9];      // next input row (prefetched)
@@ -407,7 +448,7 @@ struct MsState {
 // (pipeline fill), stage S stores only when ACTIVE == S.  ALL: stage j < S
 // also stores its rows of [ys, ye) to dst - (S - j) stride (the state after
 // j steps, for a caller that keeps every intermediate state).
-template <int S, int P, int ACTIVE, bool ALL>
+template <int S, int P, int ACTIVE, bool ALL, bool OFF32>
 __device__ __forceinline__ void ms_row(MsState<S>& st, int k, int kend,
                                        const double* __restrict__ src, double* __restrict__ dst,
                                        int nx, int ny, int gx, int ys, int x0, const FoldedRates& r,
@@ -418,9 +459,9 @@ __device__ __forceinline__ void ms_row(MsState<S>& st, int k, int kend,
 #pragma unroll
     for (int i = 0; i < 9; ++i) f[i] = st.pre[i];
     if (k < kend) {
-        const int base = wrapi(ys - S + k + 1, ny) * nx + gx;
+        const MsAddr<OFF32> a(wrapi(ys - S + k + 1, ny) * nx + gx);
 #pragma unroll
-        for (int i = 0; i < 9; ++i) st.pre[i] = src[slot<9>(i, base)];
+        for (int i = 0; i < 9; ++i) st.pre[i] = a.load(src, i);
     }
 #pragma unroll
     for (int j = 1; j <= S; ++j) {
@@ -446,9 +487,9 @@ __device__ __forceinline__ void ms_row(MsState<S>& st, int k, int kend,
 #pragma unroll
             for (int i = 0; i < 9; ++i) f[i] = in[i];
             if (j == S && ACTIVE == S && lane >= S && lane < S + W && x0 - S + lane < nx) {
-                const int row = wrapi(ys - 2 * S + k, ny) * nx + x0 - S + lane;
+                const MsAddr<OFF32> a(wrapi(ys - 2 * S + k, ny) * nx + x0 - S + lane);
 #pragma unroll
-                for (int i = 0; i < 9; ++i) __builtin_nontemporal_store(in[i], dst + slot<9>(i, row));
+                for (int i = 0; i < 9; ++i) a.store(dst, i, in[i]);
             }
             if (ALL && j < S) {
                 // row ys + k - S - j of step j; lanes S .. S+W-1 hold valid
@@ -456,31 +497,31 @@ __device__ __forceinline__ void ms_row(MsState<S>& st, int k, int kend,
                 // side per stage)
                 const int rr = k - S - j;
                 if (rr >= 0 && rr < nrows && lane >= S && lane < S + W && x0 - S + lane < nx) {
-                    const int row = (ys + rr) * nx + x0 - S + lane;
+                    const MsAddr<OFF32> a((ys + rr) * nx + x0 - S + lane);
                     double* out = dst - (int64_t)(S - j) * stride;
 #pragma unroll
-                    for (int i = 0; i < 9; ++i)
-                        __builtin_nontemporal_store(in[i], out + slot<9>(i, row));
+                    for (int i = 0; i < 9; ++i) a.store(out, i, in[i]);
                 }
             }
         }
     }
 }
 
-template <int S, int K, bool ALL>
+template <int S, int K, bool ALL, bool OFF32>
 __device__ __forceinline__ void ms_fill(MsState<S>& st, int kend, const double* __restrict__ src,
                                         double* __restrict__ dst, int nx, int ny, int gx, int ys,
                                         int x0, const FoldedRates& r, int nrows, int64_t stride) {
     if constexpr (K < 2 * S) {
-        ms_row<S, K & 1, K / 2, ALL>(st, K, kend, src, dst, nx, ny, gx, ys, x0, r, nrows, stride);
-        ms_fill<S, K + 1, ALL>(st, kend, src, dst, nx, ny, gx, ys, x0, r, nrows, stride);
+        ms_row<S, K & 1, K / 2, ALL, OFF32>(st, K, kend, src, dst, nx, ny, gx, ys, x0, r, nrows,
+                                            stride);
+        ms_fill<S, K + 1, ALL, OFF32>(st, kend, src, dst, nx, ny, gx, ys, x0, r, nrows, stride);
     }
 }
 
 // Advance rows [ys, ye) (ye > ys) of the columns [x0, x0 + 64 - 2S) of one
 // D2Q9 grid by S steps (reads rows ys-S .. ye-1+S and columns x0-S ..
 // x0+63-S, wrapped periodically).  All 64 lanes of the wave must be active.
-template <int S, bool ALL = false>
+template <int S, bool ALL, bool OFF32>
 __device__ __forceinline__ void ms_tile(const double* __restrict__ src, double* __restrict__ dst,
                                         int nx, int ny, const FoldedRates& r, int x0, int ys,
                                         int ye, int64_t stride = 0) {
@@ -488,25 +529,26 @@ __device__ __forceinline__ void ms_tile(const double* __restrict__ src, double* 
     const int kend = ye - ys + 2 * S - 1;  // >= 2S
     MsState<S> st;
     {
-        const int base = wrapi(ys - S, ny) * nx + gx;
+        const MsAddr<OFF32> a(wrapi(ys - S, ny) * nx + gx);
 #pragma unroll
-        for (int i = 0; i < 9; ++i) st.pre[i] = src[slot<9>(i, base)];
+        for (int i = 0; i < 9; ++i) st.pre[i] = a.load(src, i);
     }
 #pragma unroll
     for (int j = 0; j < S; ++j)
 #pragma unroll
         for (int a = 0; a < 3; ++a) st.z[j][a] = st.u[0][j][a] = st.u[1][j][a] = 0.0;
     const int nrows = ye - ys;
-    ms_fill<S, 0, ALL>(st, kend, src, dst, nx, ny, gx, ys, x0, r, nrows, stride);
+    ms_fill<S, 0, ALL, OFF32>(st, kend, src, dst, nx, ny, gx, ys, x0, r, nrows, stride);
     for (int k = 2 * S; k <= kend; k += 2) {
-        ms_row<S, 0, S, ALL>(st, k, kend, src, dst, nx, ny, gx, ys, x0, r, nrows, stride);
+        ms_row<S, 0, S, ALL, OFF32>(st, k, kend, src, dst, nx, ny, gx, ys, x0, r, nrows, stride);
         if (k + 1 <= kend)
-            ms_row<S, 1, S, ALL>(st, k + 1, kend, src, dst, nx, ny, gx, ys, x0, r, nrows, stride);
+            ms_row<S, 1, S, ALL, OFF32>(st, k + 1, kend, src, dst, nx, ny, gx, ys, x0, r, nrows,
+                                        stride);
     }
 }
 
 // Two waves per SIMD: the register budget (256 per wave) holds S = 8.
-template <int S>
+template <int S, bool OFF32>
 __global__ void __launch_bounds__(MS_THREADS) __attribute__((amdgpu_waves_per_eu(2)))
 k_steps_d2q9(const double* __restrict__ src,
                                                            double* __restrict__ dst, Geo g,
@@ -515,12 +557,13 @@ k_steps_d2q9(const double* __restrict__ src,
     const int strip = (int)(t % (unsigned)nstrips);
     const int seg = (int)(t / (unsigned)nstrips);
     const int ys = seg * ly;
-    ms_tile<S>(src, dst, g.nx, g.ny, folded(r), strip * strip_width(S), ys, min(ys + ly, g.ny));
+    ms_tile<S, false, OFF32>(src, dst, g.nx, g.ny, folded(r), strip * strip_width(S), ys,
+                             min(ys + ly, g.ny), 0);
 }
 
 // The same pass writing the state after every one of its S steps: step j to
 // out + (j - 1) stride (the adjoint's recomputation of a checkpoint segment).
-template <int S>
+template <int S, bool OFF32>
 __global__ void __launch_bounds__(MS_THREADS) __attribute__((amdgpu_waves_per_eu(2)))
 k_steps_d2q9_all(const double* __restrict__ src, double* __restrict__ out, int64_t stride, Geo g,
                  Rates r, int ly, int nstrips) {
@@ -528,7 +571,7 @@ k_steps_d2q9_all(const double* __restrict__ src, double* __restrict__ out, int64
     const int strip = (int)(t % (unsigned)nstrips);
     const int seg = (int)(t / (unsigned)nstrips);
     const int ys = seg * ly;
-    ms_tile<S, true>(src, out + (int64_t)(S - 1) * stride, g.nx, g.ny, folded(r),
+    ms_tile<S, true, OFF32>(src, out + (int64_t)(S - 1) * stride, g.nx, g.ny, folded(r),
                      strip * strip_width(S), ys, min(ys + ly, g.ny), stride);
 }
 
@@ -1310,7 +1353,7 @@ struct LwState {
 };
 
 // One iteration k of the march; P = k & 1.
-template <int S, int P>
+template <int S, int P, bool OFF32>
 __device__ __forceinline__ void lw_row(LwState<S>& st, double (&lds)[2][6][LW_THREADS], int k,
                                        int kend, const double* __restrict__ src,
                                        double* __restrict__ dst, int nx, int ny, int gx, int ys,
@@ -1321,9 +1364,9 @@ __device__ __forceinline__ void lw_row(LwState<S>& st, double (&lds)[2][6][LW_TH
 #pragma unroll
     for (int i = 0; i < 9; ++i) f[i] = st.pre[i];
     if (k < kend) {
-        const int base = wrapi(ys - S + k + 1, ny) * nx + gx;
+        const MsAddr<OFF32> a(wrapi(ys - S + k + 1, ny) * nx + gx);
 #pragma unroll
-        for (int i = 0; i < 9; ++i) st.pre[i] = src[slot<9>(i, base)];
+        for (int i = 0; i < 9; ++i) st.pre[i] = a.load(src, i);
     }
 #pragma unroll
     for (int i = 0; i < 9; ++i)
@@ -1363,9 +1406,9 @@ __device__ __forceinline__ void lw_row(LwState<S>& st, double (&lds)[2][6][LW_TH
                     }
                 }
             } else if (tid >= S && tid < S + W && x0 - S + tid < nx) {
-                const int row = wrapi(ys - 2 * S + k, ny) * nx + x0 - S + tid;
+                const MsAddr<OFF32> a(wrapi(ys - 2 * S + k, ny) * nx + x0 - S + tid);
 #pragma unroll
-                for (int i = 0; i < 9; ++i) __builtin_nontemporal_store(in[i], dst + slot<9>(i, row));
+                for (int i = 0; i < 9; ++i) a.store(dst, i, in[i]);
             }
         }
         if (j < S) __syncthreads();
@@ -1377,7 +1420,7 @@ __device__ __forceinline__ void lw_row(LwState<S>& st, double (&lds)[2][6][LW_TH
 // Advance rows [ys, ye) of the columns [x0, x0 + LW_THREADS - 2S) of one
 // D2Q9 grid by S steps (reads rows ys-S .. ye-1+S and columns x0-S ..
 // x0+LW_THREADS-S-1, wrapped periodically).
-template <int S>
+template <int S, bool OFF32>
 __device__ __forceinline__ void lw_tile(const double* __restrict__ src, double* __restrict__ dst,
                                         int nx, int ny, const FoldedRates& r, int x0, int ys, int ye,
                                         double (&lds)[2][6][LW_THREADS]) {
@@ -1385,24 +1428,26 @@ __device__ __forceinline__ void lw_tile(const double* __restrict__ src, double* 
     const int kend = ye - ys + 2 * S - 1;
     LwState<S> st;
     {
-        const int base = wrapi(ys - S, ny) * nx + gx;
+        const MsAddr<OFF32> a(wrapi(ys - S, ny) * nx + gx);
 #pragma unroll
-        for (int i = 0; i < 9; ++i) st.pre[i] = src[slot<9>(i, base)];
+        for (int i = 0; i < 9; ++i) st.pre[i] = a.load(src, i);
     }
 #pragma unroll
     for (int j = 0; j < S; ++j)
 #pragma unroll
         for (int a = 0; a < 3; ++a) st.z[j][a] = st.u[0][j][a] = st.u[1][j][a] = 0.0;
     for (int k = 0; k <= kend; k += 2) {
-        lw_row<S, 0>(st, lds, k, kend, src, dst, nx, ny, gx, ys, x0, r);
-        if (k + 1 <= kend) lw_row<S, 1>(st, lds, k + 1, kend, src, dst, nx, ny, gx, ys, x0, r);
+        lw_row<S, 0, OFF32>(st, lds, k, kend, src, dst, nx, ny, gx, ys, x0, r);
+        if (k + 1 <= kend)
+            lw_row<S, 1, OFF32>(st, lds, k + 1, kend, src, dst, nx, ny, gx, ys, x0, r);
     }
 }
 
 
 // Batched S-step pass: tile (inst, x0, y0, y1) = rows [y0, y1) of the strip
-// at x0 (batch_strip_width(S) columns) of one instance.
-template <int S>
+// at x0 (batch_strip_width(S) columns) of one instance.  OFF32: every
+// instance's state is under 4 GiB (MsAddr<true> from the instance's start).
+template <int S, bool OFF32>
 __global__ void __launch_bounds__(LW_THREADS) k_batch_steps(const BatchInst* __restrict__ insts,
                                                             const BatchTile* __restrict__ tiles,
                                                             const double* __restrict__ src,
@@ -1410,8 +1455,8 @@ __global__ void __launch_bounds__(LW_THREADS) k_batch_steps(const BatchInst* __r
     __shared__ double lds[2][6][LW_THREADS];
     const BatchTile t = tiles[xcd_remap(blockIdx.x, gridDim.x)];
     const BatchInst& in = insts[t.inst];
-    lw_tile<S>(src + in.offset, dst + in.offset, in.nx, in.ny, folded(in.r), t.x0, t.y0, t.pad,
-               lds);
+    lw_tile<S, OFF32>(src + in.offset, dst + in.offset, in.nx, in.ny, folded(in.r), t.x0, t.y0,
+                      t.pad, lds);
 }
 
 template <typename F>
@@ -1576,8 +1621,12 @@ static hipError_t launch_steps_t(const Geo& g, const Rates& r, const double* src
     const int nstrips = (g.nx + w - 1) / w;
     const int ly = steps_rows(g, nstrips, kMinRows);
     const int nseg = (g.ny + ly - 1) / ly;
-    hipLaunchKernelGGL(k_steps_d2q9<S>, dim3((unsigned)((int64_t)nstrips * nseg)),
-                       dim3(MS_THREADS), 0, st, src, dst, g, r, ly, nstrips);
+    if (ms_off32(g))
+        hipLaunchKernelGGL((k_steps_d2q9<S, true>), dim3((unsigned)((int64_t)nstrips * nseg)),
+                           dim3(MS_THREADS), 0, st, src, dst, g, r, ly, nstrips);
+    else
+        hipLaunchKernelGGL((k_steps_d2q9<S, false>), dim3((unsigned)((int64_t)nstrips * nseg)),
+                           dim3(MS_THREADS), 0, st, src, dst, g, r, ly, nstrips);
     return hipGetLastError();
 }
 
@@ -1616,8 +1665,12 @@ static hipError_t launch_steps_all_t(const Geo& g, const Rates& r, const double*
     const int nstrips = (g.nx + w - 1) / w;
     const int ly = steps_rows(g, nstrips, kMinRowsSegment);
     const int nseg = (g.ny + ly - 1) / ly;
-    hipLaunchKernelGGL(k_steps_d2q9_all<S>, dim3((unsigned)((int64_t)nstrips * nseg)),
-                       dim3(MS_THREADS), 0, st, src, out, stride, g, r, ly, nstrips);
+    if (ms_off32(g))
+        hipLaunchKernelGGL((k_steps_d2q9_all<S, true>), dim3((unsigned)((int64_t)nstrips * nseg)),
+                           dim3(MS_THREADS), 0, st, src, out, stride, g, r, ly, nstrips);
+    else
+        hipLaunchKernelGGL((k_steps_d2q9_all<S, false>), dim3((unsigned)((int64_t)nstrips * nseg)),
+                           dim3(MS_THREADS), 0, st, src, out, stride, g, r, ly, nstrips);
     return hipGetLastError();
 }
 
@@ -1775,17 +1828,26 @@ hipError_t launch_finalize_tables(const double* partials, int64_t n, int64_t m, 
     return hipGetLastError();
 }
 
-hipError_t launch_batch_steps(int nsteps, const BatchInst* insts, const BatchTile* tiles,
-                              int64_t ntiles, const double* src, double* dst, hipStream_t st) {
-    if (ntiles <= 0) return hipSuccess;
+template <bool OFF32>
+static hipError_t launch_batch_steps_t(int nsteps, const BatchInst* insts, const BatchTile* tiles,
+                                       int64_t ntiles, const double* src, double* dst,
+                                       hipStream_t st) {
     const dim3 grid((unsigned)ntiles), block(LW_THREADS);
     switch (nsteps) {
-        case 2: hipLaunchKernelGGL(k_batch_steps<2>, grid, block, 0, st, insts, tiles, src, dst); break;
-        case 4: hipLaunchKernelGGL(k_batch_steps<4>, grid, block, 0, st, insts, tiles, src, dst); break;
-        case 8: hipLaunchKernelGGL(k_batch_steps<8>, grid, block, 0, st, insts, tiles, src, dst); break;
+        case 2: hipLaunchKernelGGL((k_batch_steps<2, OFF32>), grid, block, 0, st, insts, tiles, src, dst); break;
+        case 4: hipLaunchKernelGGL((k_batch_steps<4, OFF32>), grid, block, 0, st, insts, tiles, src, dst); break;
+        case 8: hipLaunchKernelGGL((k_batch_steps<8, OFF32>), grid, block, 0, st, insts, tiles, src, dst); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+hipError_t launch_batch_steps(int nsteps, const BatchInst* insts, const BatchTile* tiles,
+                              int64_t ntiles, const double* src, double* dst, bool off32,
+                              hipStream_t st) {
+    if (ntiles <= 0) return hipSuccess;
+    return off32 ? launch_batch_steps_t<true>(nsteps, insts, tiles, ntiles, src, dst, st)
+                 : launch_batch_steps_t<false>(nsteps, insts, tiles, ntiles, src, dst, st);
 }
 
 hipError_t launch_batch_step(const BatchInst* insts, const BatchTile* tiles, int64_t ntiles,

@@ -255,6 +255,37 @@ def test_multi_step_passes_equal_single_steps(grid, steps):
         assert np.array_equal(outs[0], o)
 
 
+# A D2Q9 state of 8192 x 7400 nodes takes 4.37e9 bytes, more than 32-bit byte
+# offsets reach, so its multi-step passes address with 64-bit indices.
+BIG_2D = (8192, 7400)
+
+
+def test_multi_step_passes_beyond_4gib_state():
+    """Passes over a state buffer larger than 4 GiB (64-bit addressing) are
+    bitwise single steps, as the passes over smaller buffers are."""
+    _say("multi-step vs single", BIG_2D, 11)
+    SV = _solver_mod()
+    grid = BIG_2D
+    assert 9 * ((grid[0] * grid[1] + 4095) // 4096) * 4096 * 8 > 2 ** 32
+    dx, nu = 1.0 / grid[0], 0.01
+    dt = 0.2 * dx * dx / nu
+    gen = torch.Generator(device=_dev()).manual_seed(5)
+    th0 = 2.0 + 0.5 * torch.rand(tuple(reversed(grid)), dtype=torch.float64, device=_dev(),
+                                 generator=gen)
+    outs = []
+    for spp in (1, 8):
+        s = SV.Solver(grid, dx, dt, nu, device=_dev())
+        s.set_steps_per_pass(spp)
+        s.init(th0, None)
+        s.step(11)
+        outs.append(s.get_state())
+        s.close()
+    torch.cuda.synchronize()
+    assert torch.equal(outs[0], outs[1])
+    del outs, th0
+    torch.cuda.empty_cache()
+
+
 @pytest.mark.parametrize("grid,steps", [((37, 29, 23), 5), ((5, 3, 2), 4), ((1, 1, 1), 3),
                                          ((64, 9, 40), 8), ((130, 7, 11), 7), ((61, 5, 70), 6)])
 def test_multi_step_passes_equal_single_steps_3d(grid, steps):
@@ -691,6 +722,50 @@ def test_adjoint_segment_equals_single_adjoint_steps(grid, m):
     s.close()
 
 
+def test_adjoint_segment_beyond_4gib_state():
+    """lb_adjoint_segment over state buffers larger than 4 GiB: recomputed
+    states and lambda bitwise equal to single steps and single adjoint
+    steps, the eps gradient equal to rounding."""
+    _say("adjoint segment", BIG_2D, 6)
+    SV = _solver_mod()
+    grid, m = BIG_2D, 6
+    dx, nu = 1.0 / grid[0], 0.01
+    dt = 0.2 * dx * dx / nu
+    s = SV.Solver(grid, dx, dt, nu, device=_dev())
+    shape = (9,) + tuple(reversed(grid))
+    gen = torch.Generator(device=_dev()).manual_seed(6)
+    v = 1.0 + 0.1 * torch.randn(shape, dtype=torch.float64, device=_dev(), generator=gen)
+    s.set_state(v, 0)
+    del v
+    ckpt = s.current().clone()
+    lam0 = torch.randn(shape, dtype=torch.float64, device=_dev(), generator=gen)
+    st = [ckpt]
+    for _ in range(1, m):
+        nxt = s.new_state()
+        s.step_buffers(st[-1], nxt)
+        st.append(nxt)
+    ge_ref = torch.zeros(1, dtype=torch.float64, device=_dev())
+    cur, other = s.to_layout(lam0), s.new_state()
+    for n in range(m - 1, -1, -1):
+        s.adjoint_step(st[n], cur, other, ge_ref)
+        cur, other = other, cur
+    del other
+    ge = torch.zeros(1, dtype=torch.float64, device=_dev())
+    lam_c = s.to_layout(lam0)
+    del lam0
+    work = torch.empty((m - 1) * s.state_elems, dtype=torch.float64, device=_dev())
+    s.adjoint_segment(ckpt, m, work, lam_c, s.new_state(), ge)
+    torch.cuda.synchronize()
+    assert torch.equal(s.from_layout(lam_c), s.from_layout(cur))
+    for j in range(1, m):
+        seg = work[(j - 1) * s.state_elems: j * s.state_elems]
+        assert torch.equal(s.from_layout(seg), s.from_layout(st[j])), j
+    assert abs(ge.item() - ge_ref.item()) <= 1e-12 * max(abs(ge_ref.item()), 1.0)
+    s.close()
+    del st, work, lam_c, cur, ckpt
+    torch.cuda.empty_cache()
+
+
 # ---------------------------------------------------------------------------
 # batched form
 # ---------------------------------------------------------------------------
@@ -752,6 +827,39 @@ def test_batch_multi_step_degenerate_shapes():
         assert np.array_equal(ths[b].cpu().numpy(), th), p.grid
         assert np.array_equal(us[b].cpu().numpy(), u), p.grid
     bs.close()
+
+
+def test_batch_beyond_4gib_instance():
+    """A batch holding an instance whose state is larger than 4 GiB (64-bit
+    addressing in the multi-step tiles) next to a small one; bitwise equal to
+    single-instance runs."""
+    _say("batch with an instance beyond 4 GiB", BIG_2D)
+    SV = _solver_mod()
+    grids = [BIG_2D, (100, 77)]
+    gen = torch.Generator(device=_dev()).manual_seed(9)
+    probs, th0s = [], []
+    for i, g in enumerate(grids):
+        dx, nu = 1.0 / max(g), 0.01
+        probs.append(W.Workload(f"b{i}", g, dx, 0.2 * dx * dx / nu, nu, []))
+        th0s.append(2.0 + 0.5 * torch.rand(tuple(reversed(g)), dtype=torch.float64,
+                                           device=_dev(), generator=gen))
+    bs = SV.BatchSolver(probs, device=_dev())
+    bs.init(th0s, None)
+    bs.set_tile(-8, 64)
+    bs.step(11, graph=True)
+    ths, us = bs.macro()
+    for b, p in enumerate(probs):
+        s = SV.Solver(p.grid, p.dx, p.dt, p.nu, device=_dev())
+        s.init(th0s[b], None)
+        s.step(11)
+        th, u = s.macro()
+        torch.cuda.synchronize()
+        assert torch.equal(ths[b].reshape(th.shape), th), p.grid
+        assert torch.equal(us[b].reshape(u.shape), u), p.grid
+        s.close()
+    bs.close()
+    del ths, us, th0s
+    torch.cuda.empty_cache()
 
 
 def test_batch_full_size_against_exact_modes():
