@@ -44,6 +44,13 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
+def d2_kernel(steps: int, nodes: int) -> str:
+    """Name of the D2Q9 pass kernel as the trace shows it: the variant with
+    32-bit offsets runs when the state buffer is under 4 GiB."""
+    elems = 9 * ((nodes + 4095) // 4096) * 4096
+    return f"k_steps_d2q9<{steps}, {'true' if elems * 8 <= 0xFFFFFFFF else 'false'}>"
+
+
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
     for p in KERNEL_SOURCES:
@@ -371,7 +378,7 @@ def main():
     # bytes of a launch are 144 B per lattice update times its 8V updates,
     # while the pass itself reads and writes the state once (see "traffic")
     per_launch = {2: D2_STEPS_PER_PASS, 3: D3_STEPS_PER_PASS}.get(d, 1)
-    kernel = {2: f"k_steps_d2q9<{D2_STEPS_PER_PASS}>",
+    kernel = {2: d2_kernel(D2_STEPS_PER_PASS, V),
               3: f"k_steps_d3q19<{D3_STEPS_PER_PASS}>"}.get(d, f"k_step<{d}>")
     launch_us = kms * 1e3 * per_launch
     rec = {
@@ -421,7 +428,7 @@ def main():
                 ms = kernel_only(torch, SV, W, wl, 400, dev, steps_per_pass=spp)
                 ml = V / (ms / 1e3) / 1e6
                 sweep[f"steps_per_pass_{spp}"] = {
-                    "kernel": "k_step<2>" if spp == 1 else f"k_steps_d2q9<{spp}>",
+                    "kernel": "k_step<2>" if spp == 1 else d2_kernel(spp, V),
                     "kernel_us_per_step": round(ms * 1e3, 2), "mlups": round(ml, 1),
                     "gbs_algorithmic": round(BYTES_PER_LU[2] * ml / 1e3, 1),
                     "frac": round(BYTES_PER_LU[2] * ml / 1e3 / HBM_PEAK_GBS, 4),
@@ -437,7 +444,7 @@ def main():
             ml = w2.nodes / (ms / 1e3) / 1e6
             gbs = BYTES_PER_LU[w2.d] * ml / 1e3
             forms[name] = {"lattice": {2: "D2Q9", 3: "D3Q19", 4: "D4Q33"}[w2.d],
-                           "kernel": {2: f"k_steps_d2q9<{D2_STEPS_PER_PASS}>",
+                           "kernel": {2: d2_kernel(D2_STEPS_PER_PASS, w2.nodes),
                                       3: f"k_steps_d3q19<{D3_STEPS_PER_PASS}>"}.get(
                                           w2.d, f"k_step<{w2.d}>"),
                            "kernel_us_per_step": round(ms * 1e3, 2),
