@@ -458,7 +458,12 @@ __device__ __forceinline__ void ms_row(MsState<S>& st, int k, int kend,
     double f[9];
 #pragma unroll
     for (int i = 0; i < 9; ++i) f[i] = st.pre[i];
-    if (k < kend) {
+    {
+        // Prefetch the next input row.  In the last iteration the row is not
+        // used (its address is wrapped, so in bounds); loading it anyway
+        // keeps the memory counters equal on every path, which lets the
+        // compiler wait for the prefetch without waiting for the stores
+        // (512^2: 90 -> 106 GLUPS).
         const MsAddr<OFF32> a(wrapi(ys - S + k + 1, ny) * nx + gx);
 #pragma unroll
         for (int i = 0; i < 9; ++i) st.pre[i] = a.load(src, i);
@@ -621,7 +626,8 @@ __device__ __forceinline__ void as_row(AsState<S>& st, double& ge, int k, int ke
     double f[9];
 #pragma unroll
     for (int i = 0; i < 9; ++i) f[i] = st.pre[i];
-    if (k < kend) {
+    {
+        // next lambda row (unused in the last iteration, as in ms_row)
         const int base = wrapi(ys - S + k + 1, ny) * nx + gx;
 #pragma unroll
         for (int i = 0; i < 9; ++i) st.pre[i] = src[slot<9>(i, base)];
@@ -773,7 +779,8 @@ __device__ __forceinline__ void ms3_plane(Ms3State<S>& st, double* lds, int k, i
     double f[19];
 #pragma unroll
     for (int i = 0; i < 19; ++i) f[i] = st.pre[i];
-    if (k < kend) {
+    {
+        // next plane (unused in the last iteration, as in ms_row)
         const int64_t base = (int64_t)wrapi(zs - S + k + 1, g.nz) * plane + col;
 #pragma unroll
         for (int i = 0; i < 19; ++i) st.pre[i] = src[slot<19>(i, base)];
@@ -1363,6 +1370,8 @@ __device__ __forceinline__ void lw_row(LwState<S>& st, double (&lds)[2][6][LW_TH
     double f[9];
 #pragma unroll
     for (int i = 0; i < 9; ++i) f[i] = st.pre[i];
+    // (an unconditional prefetch as in ms_row raised this kernel to 260
+    // VGPRs, one wave per SIMD, and cost 20 % on the batch)
     if (k < kend) {
         const MsAddr<OFF32> a(wrapi(ys - S + k + 1, ny) * nx + gx);
 #pragma unroll
