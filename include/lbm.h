@@ -296,9 +296,12 @@ lb_status lb_batch_init(lb_batch* b, const double* theta0, const double* grad);
  * every mode, so all modes give bitwise identical states):
  *   (-S, rows)  S = 2, 4 or 8 steps per pass over each instance: tiles of
  *               128 - 2S columns x rows rows (1 <= rows <= 65535) that keep
- *               the intermediate steps on chip; a run of n steps takes n / S
- *               such passes and n mod S linear-tile single steps.  (-8, 64)
- *               is the default of a new batch;
+ *               the intermediate steps on chip (two waves per tile, sharing
+ *               through LDS); a run of n steps takes n / S such passes and
+ *               n mod S linear-tile single steps.  (-8, 64) is the default of
+ *               a new batch;
+ *   (-16-S, rows)  the same with tiles of 64 - 2S columns, one wave per tile
+ *               (the march of lb_step's D2Q9 passes);
  *   (0, 0)      one step per pass, linear tiles of 256 consecutive node
  *               indices of one instance (crossing row ends);
  *   (tx, ty)    one step per pass, tx x ty rectangles with tx*ty = 256 and tx

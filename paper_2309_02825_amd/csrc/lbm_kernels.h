@@ -149,9 +149,11 @@ hipError_t launch_batch_step(const BatchInst* insts, const BatchTile* tiles, int
 constexpr int LW_THREADS = 128;
 __host__ __device__ constexpr int batch_strip_width(int nsteps) { return LW_THREADS - 2 * nsteps; }
 // off32: every instance's state is under 4 GiB (32-bit offsets from the
-// instance's start).
+// instance's start).  one_wave: tiles are strips of strip_width(nsteps)
+// columns run by the one-wave march of k_steps_d2q9; otherwise strips of
+// batch_strip_width(nsteps) columns run by the two-wave LDS routine.
 hipError_t launch_batch_steps(int nsteps, const BatchInst* insts, const BatchTile* tiles,
                               int64_t ntiles, const double* src, double* dst, bool off32,
-                              hipStream_t st);
+                              bool one_wave, hipStream_t st);
 
 }  // namespace lbm

@@ -1468,6 +1468,18 @@ __global__ void __launch_bounds__(LW_THREADS) k_batch_steps(const BatchInst* __r
                       t.pad, lds);
 }
 
+// The same pass with the one-wave march of k_steps_d2q9: tile (inst, x0,
+// y0, y1) = rows [y0, y1) of the strip at x0 (strip_width(S) columns).
+template <int S, bool OFF32>
+__global__ void __launch_bounds__(MS_THREADS) __attribute__((amdgpu_waves_per_eu(2)))
+k_batch_steps_w(const BatchInst* __restrict__ insts, const BatchTile* __restrict__ tiles,
+                const double* __restrict__ src, double* __restrict__ dst) {
+    const BatchTile t = tiles[xcd_remap(blockIdx.x, gridDim.x)];
+    const BatchInst& in = insts[t.inst];
+    ms_tile<S, false, OFF32>(src + in.offset, dst + in.offset, in.nx, in.ny, folded(in.r), t.x0,
+                             t.y0, t.pad, 0);
+}
+
 template <typename F>
 hipError_t dispatch(int d, F&& f) {
     switch (d) {
@@ -1840,7 +1852,17 @@ hipError_t launch_finalize_tables(const double* partials, int64_t n, int64_t m, 
 template <bool OFF32>
 static hipError_t launch_batch_steps_t(int nsteps, const BatchInst* insts, const BatchTile* tiles,
                                        int64_t ntiles, const double* src, double* dst,
-                                       hipStream_t st) {
+                                       bool one_wave, hipStream_t st) {
+    if (one_wave) {
+        const dim3 grid((unsigned)ntiles), block(MS_THREADS);
+        switch (nsteps) {
+            case 2: hipLaunchKernelGGL((k_batch_steps_w<2, OFF32>), grid, block, 0, st, insts, tiles, src, dst); break;
+            case 4: hipLaunchKernelGGL((k_batch_steps_w<4, OFF32>), grid, block, 0, st, insts, tiles, src, dst); break;
+            case 8: hipLaunchKernelGGL((k_batch_steps_w<8, OFF32>), grid, block, 0, st, insts, tiles, src, dst); break;
+            default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
     const dim3 grid((unsigned)ntiles), block(LW_THREADS);
     switch (nsteps) {
         case 2: hipLaunchKernelGGL((k_batch_steps<2, OFF32>), grid, block, 0, st, insts, tiles, src, dst); break;
@@ -1853,10 +1875,11 @@ static hipError_t launch_batch_steps_t(int nsteps, const BatchInst* insts, const
 
 hipError_t launch_batch_steps(int nsteps, const BatchInst* insts, const BatchTile* tiles,
                               int64_t ntiles, const double* src, double* dst, bool off32,
-                              hipStream_t st) {
+                              bool one_wave, hipStream_t st) {
     if (ntiles <= 0) return hipSuccess;
-    return off32 ? launch_batch_steps_t<true>(nsteps, insts, tiles, ntiles, src, dst, st)
-                 : launch_batch_steps_t<false>(nsteps, insts, tiles, ntiles, src, dst, st);
+    return off32 ? launch_batch_steps_t<true>(nsteps, insts, tiles, ntiles, src, dst, one_wave, st)
+                 : launch_batch_steps_t<false>(nsteps, insts, tiles, ntiles, src, dst, one_wave,
+                                               st);
 }
 
 hipError_t launch_batch_step(const BatchInst* insts, const BatchTile* tiles, int64_t ntiles,

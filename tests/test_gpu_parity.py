@@ -782,7 +782,8 @@ def test_batch_matches_single_instance_runs():
     # segments taller than some, odd counts that end on a linear-tile step)
     plan = ((64, 4, 10, True), (256, 1, 10, False), (16, 16, 10, True), (0, 0, 10, True),
             (-8, 16, 19, True), (-4, 5, 6, False), (-2, 64, 3, True), (-8, 1, 5, False),
-            (-8, 200, 8, True))
+            (-8, 200, 8, True), (-24, 16, 19, True), (-20, 5, 6, False), (-18, 64, 3, True),
+            (-24, 1, 5, False), (-24, 200, 8, True))
     for tx, ty, n, graph in plan:
         bs.set_tile(tx, ty)
         bs.step(n, graph=graph)
@@ -794,6 +795,27 @@ def test_batch_matches_single_instance_runs():
                             want_f=False)
         assert np.array_equal(ths[b].cpu().numpy(), th), b
         assert np.array_equal(us[b].cpu().numpy(), u), b
+    bs.close()
+
+
+def test_batch_rejects_invalid_tile_modes():
+    """Tile modes outside (0,0), (-S, rows), (-16-S, rows) with S in {2,4,8}
+    and rows in [1,65535], and 256-thread power-of-two rectangles, are
+    rejected and leave the batch usable."""
+    _say("batch tile validation")
+    SV = _solver_mod()
+    insts = W.batch_instances(count=2, seed=3, lmin=20, lmax=40, nsteps=4)
+    bs = SV.BatchSolver(insts, device=_dev())
+    th0s = [torch.from_numpy(W.evaluate(p.modes, p.grid, p.dx)[0]) for p in insts]
+    bs.init(th0s, None)
+    for tx, ty in ((-3, 5), (-16, 5), (-17, 5), (-26, 5), (-24, 0), (-24, 65536), (-2, -1),
+                   (32, 4), (0, 1), (512, 1), (24, 10)):
+        with pytest.raises(Exception):
+            bs.set_tile(tx, ty)
+    for tx, ty in ((-2, 1), (-18, 1), (-20, 65535), (-24, 7), (16, 16), (256, 1), (0, 0)):
+        bs.set_tile(tx, ty)
+    bs.step(3)
+    torch.cuda.synchronize()
     bs.close()
 
 
@@ -815,7 +837,8 @@ def test_batch_multi_step_degenerate_shapes():
     bs = SV.BatchSolver(probs, device=_dev())
     bs.init(th0s, None)
     total = 0
-    for tx, ty, n in ((-8, 64, 9), (-2, 2, 4), (-8, 200, 21), (-4, 3, 7), (-8, 1, 8)):
+    for tx, ty, n in ((-8, 64, 9), (-2, 2, 4), (-8, 200, 21), (-4, 3, 7), (-8, 1, 8),
+                      (-24, 64, 9), (-18, 2, 4), (-24, 200, 21), (-20, 3, 7), (-24, 1, 8)):
         bs.set_tile(tx, ty)
         bs.step(n, graph=True)
         total += n
@@ -847,11 +870,13 @@ def test_batch_beyond_4gib_instance():
     bs.init(th0s, None)
     bs.set_tile(-8, 64)
     bs.step(11, graph=True)
+    bs.set_tile(-24, 64)
+    bs.step(9, graph=True)
     ths, us = bs.macro()
     for b, p in enumerate(probs):
         s = SV.Solver(p.grid, p.dx, p.dt, p.nu, device=_dev())
         s.init(th0s[b], None)
-        s.step(11)
+        s.step(20)
         th, u = s.macro()
         torch.cuda.synchronize()
         assert torch.equal(ths[b].reshape(th.shape), th), p.grid
