@@ -272,7 +272,9 @@ def velocity(theta0: torch.Tensor, nu: torch.Tensor, grid, dx: float, dt: float,
 
 class BatchSolver:
     """Independent 2-D periodic instances of different sizes and viscosities
-    advanced together by one tile-table kernel per step (hipGraph-captured)."""
+    advanced together: each launch runs one tile-table kernel over every
+    instance (one step per launch, or S steps per launch in the multi-step
+    tile modes), and a run of steps is captured once into a hipGraph."""
 
     def __init__(self, problems: Sequence, device: Optional[torch.device] = None,
                  stream: Optional[torch.cuda.Stream] = None):
@@ -310,6 +312,9 @@ class BatchSolver:
         L.lb_batch_init(self.h, self._th, self._gr)
 
     def set_tile(self, tx: int, ty: int):
+        """Tile mode (see lb_batch_set_tile): (-S, rows) two-wave strips,
+        (-16-S, rows) one-wave strips, S in {2, 4, 8}; (0, 0) linear tiles;
+        (tx, ty) rectangles of 256 nodes."""
         L.lb_batch_set_tile(self.h, tx, ty)
 
     def autotune(self, steps_per_trial: int = 3):
