@@ -449,7 +449,7 @@ struct MsState {
 // also stores its rows of [ys, ye) to dst - (S - j) stride (the state after
 // j steps, for a caller that keeps every intermediate state).
 template <int S, int P, int ACTIVE, bool ALL, bool OFF32>
-__device__ __forceinline__ void ms_row(MsState<S>& st, int k, int kend,
+__device__ __forceinline__ void ms_row(MsState<S>& st, int k,
                                        const double* __restrict__ src, double* __restrict__ dst,
                                        int nx, int ny, int gx, int ys, int x0, const FoldedRates& r,
                                        int nrows, int64_t stride) {
@@ -513,13 +513,12 @@ __device__ __forceinline__ void ms_row(MsState<S>& st, int k, int kend,
 }
 
 template <int S, int K, bool ALL, bool OFF32>
-__device__ __forceinline__ void ms_fill(MsState<S>& st, int kend, const double* __restrict__ src,
+__device__ __forceinline__ void ms_fill(MsState<S>& st, const double* __restrict__ src,
                                         double* __restrict__ dst, int nx, int ny, int gx, int ys,
                                         int x0, const FoldedRates& r, int nrows, int64_t stride) {
     if constexpr (K < 2 * S) {
-        ms_row<S, K & 1, K / 2, ALL, OFF32>(st, K, kend, src, dst, nx, ny, gx, ys, x0, r, nrows,
-                                            stride);
-        ms_fill<S, K + 1, ALL, OFF32>(st, kend, src, dst, nx, ny, gx, ys, x0, r, nrows, stride);
+        ms_row<S, K & 1, K / 2, ALL, OFF32>(st, K, src, dst, nx, ny, gx, ys, x0, r, nrows, stride);
+        ms_fill<S, K + 1, ALL, OFF32>(st, src, dst, nx, ny, gx, ys, x0, r, nrows, stride);
     }
 }
 
@@ -543,12 +542,11 @@ __device__ __forceinline__ void ms_tile(const double* __restrict__ src, double* 
 #pragma unroll
         for (int a = 0; a < 3; ++a) st.z[j][a] = st.u[0][j][a] = st.u[1][j][a] = 0.0;
     const int nrows = ye - ys;
-    ms_fill<S, 0, ALL, OFF32>(st, kend, src, dst, nx, ny, gx, ys, x0, r, nrows, stride);
+    ms_fill<S, 0, ALL, OFF32>(st, src, dst, nx, ny, gx, ys, x0, r, nrows, stride);
     for (int k = 2 * S; k <= kend; k += 2) {
-        ms_row<S, 0, S, ALL, OFF32>(st, k, kend, src, dst, nx, ny, gx, ys, x0, r, nrows, stride);
+        ms_row<S, 0, S, ALL, OFF32>(st, k, src, dst, nx, ny, gx, ys, x0, r, nrows, stride);
         if (k + 1 <= kend)
-            ms_row<S, 1, S, ALL, OFF32>(st, k + 1, kend, src, dst, nx, ny, gx, ys, x0, r, nrows,
-                                        stride);
+            ms_row<S, 1, S, ALL, OFF32>(st, k + 1, src, dst, nx, ny, gx, ys, x0, r, nrows, stride);
     }
 }
 
@@ -615,7 +613,7 @@ __device__ __forceinline__ void as_load_f(double (&fn)[9], const double* __restr
 }
 
 template <int S, int P, int ACTIVE>
-__device__ __forceinline__ void as_row(AsState<S>& st, double& ge, int k, int kend,
+__device__ __forceinline__ void as_row(AsState<S>& st, double& ge, int k,
                                        const double* __restrict__ src, double* __restrict__ dst,
                                        const double* __restrict__ ftop, int64_t stride, int nx,
                                        int ny, int gx, int ys, int x0, int nrows, const Rates& r) {
@@ -673,14 +671,13 @@ __device__ __forceinline__ void as_row(AsState<S>& st, double& ge, int k, int ke
 }
 
 template <int S, int K>
-__device__ __forceinline__ void as_fill(AsState<S>& st, double& ge, int kend,
+__device__ __forceinline__ void as_fill(AsState<S>& st, double& ge,
                                         const double* __restrict__ src, double* __restrict__ dst,
                                         const double* __restrict__ ftop, int64_t stride, int nx,
                                         int ny, int gx, int ys, int x0, int nrows, const Rates& r) {
     if constexpr (K < 2 * S) {
-        as_row<S, K & 1, K / 2>(st, ge, K, kend, src, dst, ftop, stride, nx, ny, gx, ys, x0, nrows,
-                                r);
-        as_fill<S, K + 1>(st, ge, kend, src, dst, ftop, stride, nx, ny, gx, ys, x0, nrows, r);
+        as_row<S, K & 1, K / 2>(st, ge, K, src, dst, ftop, stride, nx, ny, gx, ys, x0, nrows, r);
+        as_fill<S, K + 1>(st, ge, src, dst, ftop, stride, nx, ny, gx, ys, x0, nrows, r);
     }
 }
 
@@ -714,12 +711,11 @@ k_adjoint_steps_d2q9(const double* __restrict__ src, double* __restrict__ dst,
         for (int i = 0; i < 9; ++i) st.fp[j][i] = 0.0;
     }
     double ge = 0.0;
-    as_fill<S, 0>(st, ge, kend, src, dst, ftop, stride, nx, ny, gx, ys, x0, nrows, r);
+    as_fill<S, 0>(st, ge, src, dst, ftop, stride, nx, ny, gx, ys, x0, nrows, r);
     for (int k = 2 * S; k <= kend; k += 2) {
-        as_row<S, 0, S>(st, ge, k, kend, src, dst, ftop, stride, nx, ny, gx, ys, x0, nrows, r);
+        as_row<S, 0, S>(st, ge, k, src, dst, ftop, stride, nx, ny, gx, ys, x0, nrows, r);
         if (k + 1 <= kend)
-            as_row<S, 1, S>(st, ge, k + 1, kend, src, dst, ftop, stride, nx, ny, gx, ys, x0, nrows,
-                            r);
+            as_row<S, 1, S>(st, ge, k + 1, src, dst, ftop, stride, nx, ny, gx, ys, x0, nrows, r);
     }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) ge += __shfl_xor(ge, o, 64);
@@ -770,7 +766,7 @@ struct Ms3State {
 };
 
 template <int S, int P>
-__device__ __forceinline__ void ms3_plane(Ms3State<S>& st, double* lds, int k, int kend,
+__device__ __forceinline__ void ms3_plane(Ms3State<S>& st, double* lds, int k,
                                           const double* __restrict__ src, double* __restrict__ dst,
                                           const Geo& g, int col, int zs, int x0, int y0,
                                           const FoldedRates& r) {
@@ -864,8 +860,8 @@ __global__ void __launch_bounds__(M3_THREADS) k_steps_d3q19(const double* __rest
         for (int a = 0; a < M3_ZP; ++a) st.u[0][j][a] = st.u[1][j][a] = 0.0;
     }
     for (int k = 0; k <= kend; k += 2) {
-        ms3_plane<S, 0>(st, lds, k, kend, src, dst, g, col, zs, x0, y0, fr);
-        if (k + 1 <= kend) ms3_plane<S, 1>(st, lds, k + 1, kend, src, dst, g, col, zs, x0, y0, fr);
+        ms3_plane<S, 0>(st, lds, k, src, dst, g, col, zs, x0, y0, fr);
+        if (k + 1 <= kend) ms3_plane<S, 1>(st, lds, k + 1, src, dst, g, col, zs, x0, y0, fr);
     }
 }
 
