@@ -19,8 +19,8 @@
  *     torch tensors).  A solver borrows the pointers given to it and must be
  *     destroyed before they are freed.  The library owns only its host-side
  *     solver object and a few small device tables (parameters, reduction
- *     partials), allocated at creation (lb_adjoint_segment grows one table
- *     of per-step partials on demand) and freed by lb_destroy.
+ *     partials), allocated at creation (lb_adjoint_segment grows a table
+ *     of per-launch partials on demand) and freed by lb_destroy.
  *   - Work is enqueued asynchronously on the HIP stream given at creation
  *     (NULL = the default stream); the host returns before the GPU finishes.
  *   - Grid: n[a] nodes along x_a (x_0 fastest); unused dimensions must be 1.
