@@ -1,0 +1,93 @@
+"""Host-side logic that runs without a GPU: the sqrt(T) checkpoint schedule,
+the seeded workload recipes and the bench's naming of the pass variant."""
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+
+sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+
+from paper_2309_02825_amd import workloads as W  # noqa: E402
+
+
+def _segments(n, nseg=None):
+    from paper_2309_02825_amd import solver as SV
+    return SV.checkpoint_segments(n, nseg)
+
+
+@pytest.mark.parametrize("n", [0, 1, 2, 7, 60, 100, 2000, 10007])
+def test_checkpoint_schedule_covers_the_run(n):
+    starts = _segments(n)
+    assert starts[0] == 0
+    assert all(b > a for a, b in zip(starts, starts[1:]))
+    if n == 0:
+        assert starts == [0]
+        return
+    assert starts[-1] < n
+    lens = [b - a for a, b in zip(starts, starts[1:] + [n])]
+    assert sum(lens) == n and min(lens) >= 1
+    # about sqrt(n) segments of about sqrt(n) steps
+    assert len(starts) <= math.ceil(math.sqrt(n)) and max(lens) <= math.ceil(math.sqrt(n)) + 1
+
+
+@pytest.mark.parametrize("n,nseg", [(60, 1), (37, 5), (10, 20)])
+def test_checkpoint_schedule_with_segment_count(n, nseg):
+    starts = _segments(n, nseg)
+    lens = [b - a for a, b in zip(starts, starts[1:] + [n])]
+    assert sum(lens) == n and len(starts) <= nseg and min(lens) >= 1
+
+
+def test_batch_recipe():
+    insts = W.batch_instances()
+    assert len(insts) == 512
+    Ls = np.array([p.grid[0] for p in insts])
+    nus = np.array([p.nu for p in insts])
+    assert all(p.grid[0] == p.grid[1] for p in insts)
+    assert Ls.min() >= 64 and Ls.max() <= 1024
+    assert nus.min() >= 1e-3 and nus.max() <= 1e-1
+    for p in insts:
+        eps = p.nu * p.dt / (p.dx * p.dx)
+        assert abs(eps - 4.0 * p.nu) <= 1e-12 * eps
+        assert abs(p.dx - 1.0 / p.grid[0]) == 0.0
+    # about 2e8 nodes (E[L^2] for L ~ U{64..1024} is about 3.73e5)
+    assert 1.7e8 < (Ls.astype(np.int64) ** 2).sum() < 2.2e8
+    # seeded: the same instances every time, different with another seed
+    again = W.batch_instances()
+    assert [p.grid for p in again] == [p.grid for p in insts]
+    assert [p.nu for p in again] == [p.nu for p in insts]
+    other = W.batch_instances(seed=1)
+    assert [p.grid for p in other] != [p.grid for p in insts]
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 3])
+def test_random_fields_stay_positive(seed):
+    modes = W.random_fourier_modes(np.random.Generator(np.random.PCG64(seed)))
+    th, _ = W.evaluate(modes, (64, 64), 1.0 / 64, with_grad=False)
+    assert th.min() >= 1.5 - 0.99 - 1e-12
+    assert th.max() <= 1.5 + 0.99 + 1e-12
+
+
+def test_adjoint_and_heat_recipes():
+    tgt, gue = W.adjoint_problem()
+    for p in (tgt, gue):
+        assert p.grid == (512, 512) and p.nsteps == 2000 and p.nu == 0.02
+        assert abs(p.nu * p.dt / (p.dx * p.dx) - 0.2) < 1e-14
+    assert tgt.modes != gue.modes
+    for n in (1024, 4096):
+        wl = W.heat_2d(n)
+        assert wl.nsteps == 10000 and abs(wl.nu * wl.dt / wl.dx ** 2 - 0.2) < 1e-14
+    for n in (256, 512):
+        wl = W.heat_3d(n)
+        assert wl.nsteps == 2000 and abs(wl.nu * wl.dt / wl.dx ** 2 - 0.1) < 1e-14
+    wl = W.heat_1d(64)
+    assert wl.nsteps == 256 and abs(wl.nsteps * wl.dt - 0.1) < 1e-14
+
+
+def test_bench_names_the_pass_variant():
+    import bench
+    # a 4096^2 state (1.2 GB) takes 32-bit offsets, 8192 x 7400 (4.37 GB) does not
+    assert bench.d2_kernel(8, 4096 * 4096) == "k_steps_d2q9<8, true>"
+    assert bench.d2_kernel(8, 8192 * 7400) == "k_steps_d2q9<8, false>"
+    assert bench.d2_kernel(4, 1024 * 1024) == "k_steps_d2q9<4, true>"
