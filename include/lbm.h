@@ -23,6 +23,9 @@
  *     of per-launch partials on demand) and freed by lb_destroy.
  *   - Work is enqueued asynchronously on the HIP stream given at creation
  *     (NULL = the default stream); the host returns before the GPU finishes.
+ *   - One solver or batch object must not be used from two host threads at
+ *     once (it keeps its buffer roles and tables); separate objects are
+ *     independent and may run on different threads and streams.
  *   - Grid: n[a] nodes along x_a (x_0 fastest); unused dimensions must be 1.
  *     Node index k = x0 + n0*(x1 + n1*(x2 + n2*x3)), V = n0*n1*n2*n3 nodes,
  *     node spacing dx, time step dt, lattice speed c = dx/dt, eps = nu*dt/dx^2.
