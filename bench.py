@@ -59,6 +59,13 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
+def shard(wl, parts: int):
+    """The slab of wl that one of ``parts`` GPUs would own along the slowest axis."""
+    from paper_2309_02825_amd import workloads as W
+    grid = wl.grid[:-1] + (wl.grid[-1] // parts,)
+    return W.Workload(f"{wl.name}_slab{grid[-1]}", grid, wl.dx, wl.dt, wl.nu, wl.modes, wl.nsteps)
+
+
 def workload(name: str):
     from paper_2309_02825_amd import workloads as W
     table = {
@@ -67,6 +74,10 @@ def workload(name: str):
         "heat3d_256": lambda: W.heat_3d(256, 2000),
         "heat3d_512": lambda: W.heat_3d(512, 2000),
         "heat4d_64": lambda: W.heat_4d(64, 200),
+        # one GPU's share of a run split 8 ways along the slowest axis (the
+        # kernel at the shard's shape; periodic here, with no exchange)
+        "heat2d_4096_shard8": lambda: shard(W.heat_2d(4096, 10000), 8),
+        "heat3d_512_shard8": lambda: shard(W.heat_3d(512, 2000), 8),
     }
     return table[name]()
 
@@ -435,7 +446,8 @@ def main():
                     "lb_steps_timed": 400}
             forms[wl.name + "_steps_per_pass"] = sweep
             log("steps per pass", sweep)
-        for name in ("heat2d_1024", "heat3d_256", "heat3d_512", "heat4d_64"):
+        for name in ("heat2d_1024", "heat3d_256", "heat3d_512", "heat4d_64", "heat2d_4096_shard8",
+                     "heat3d_512_shard8"):
             if name == args.workload or not want("grids"):
                 continue
             w2 = workload(name)
