@@ -91,3 +91,13 @@ def test_bench_names_the_pass_variant():
     assert bench.d2_kernel(8, 4096 * 4096) == "k_steps_d2q9<8, true>"
     assert bench.d2_kernel(8, 8192 * 7400) == "k_steps_d2q9<8, false>"
     assert bench.d2_kernel(4, 1024 * 1024) == "k_steps_d2q9<4, true>"
+
+
+def test_bench_refuses_more_than_one_gpu():
+    import subprocess
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    p = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=300)
+    assert p.returncode == 2
+    assert "one GPU only" in p.stderr
+    assert p.stdout.strip() == ""  # no JSON line
