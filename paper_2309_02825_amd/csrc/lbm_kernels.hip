@@ -461,9 +461,11 @@ __device__ __forceinline__ void ms_row(MsState<S>& st, int k,
     {
         // Prefetch the next input row.  In the last iteration the row is not
         // used (its address is wrapped, so in bounds); loading it anyway
-        // keeps the memory counters equal on every path, which lets the
-        // compiler wait for the prefetch without waiting for the stores
-        // (512^2: 90 -> 106 GLUPS).
+        // keeps the memory counters equal on both sides of the branch a
+        // conditional load would need, so the wait at the row start is not
+        // widened by a missing load (512^2: 90 -> 106 GLUPS).  The masked
+        // stores of stage S still make that wait cover the previous row's
+        // stores; two waves per SIMD hide it.
         const MsAddr<OFF32> a(wrapi(ys - S + k + 1, ny) * nx + gx);
 #pragma unroll
         for (int i = 0; i < 9; ++i) st.pre[i] = a.load(src, i);
