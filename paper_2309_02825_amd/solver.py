@@ -32,6 +32,21 @@ def _field(x: torch.Tensor, shape, device, name: str) -> torch.Tensor:
     return x.contiguous()
 
 
+def _buffer(x: torch.Tensor, min_elems: int, device, name: str) -> torch.Tensor:
+    """A device buffer the kernels index directly: contiguous float64 on
+    ``device`` with at least ``min_elems`` elements (a smaller one would be
+    read or written past its end).  Returned as is, never copied, because the
+    kernels may write into it."""
+    if not isinstance(x, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if x.dtype != F64 or x.device != device or not x.is_contiguous():
+        raise ValueError(f"{name}: expected a contiguous float64 tensor on {device}, got "
+                         f"{x.dtype} on {x.device}" + ("" if x.is_contiguous() else " (not contiguous)"))
+    if x.numel() < min_elems:
+        raise ValueError(f"{name}: needs at least {min_elems} elements, got {x.numel()}")
+    return x
+
+
 class Solver:
     """One problem (Sec. III.A scheme) on one GPU: periodic, or with
     bounded=True a 1-D interval whose end nodes carry a prescribed theta
@@ -113,6 +128,8 @@ class Solver:
         L.lb_set_option(self.h, L.LB_OPT_STEPS_PER_PASS, int(n))
 
     def step_buffers(self, src: torch.Tensor, dst: torch.Tensor):
+        src = _buffer(src, self.state_elems, self.device, "src")
+        dst = _buffer(dst, self.state_elems, self.device, "dst")
         L.lb_step_buffers(self.h, src, dst)
 
     @property
@@ -129,6 +146,7 @@ class Solver:
         if state is None:
             L.lb_macro(self.h, theta, u)
         else:
+            state = _buffer(state, self.state_elems, self.device, "state")
             L.lb_macro_buffer(self.h, state, theta, u)
         return theta, u
 
@@ -151,26 +169,49 @@ class Solver:
 
     def from_layout(self, buf: torch.Tensor) -> torch.Tensor:
         """Chunked buffer -> dense (q, *shape) array (no stream shift)."""
+        buf = _buffer(buf, self.state_elems, self.device, "buf")
         out = torch.empty((self.q,) + self.shape, dtype=F64, device=self.device)
         L.lb_layout_to_dense(self.h, buf, out)
         return out
 
     # -- adjoint ----------------------------------------------------------
     def macro_adjoint(self, state, g_theta, g_u, g_eps):
+        state = _buffer(state, self.state_elems, self.device, "state")
+        if g_theta is not None:
+            g_theta = _field(g_theta, self.shape, self.device, "g_theta")
+        if g_u is not None:
+            g_u = _field(g_u, (self.d,) + self.shape, self.device, "g_u")
+        g_eps = _buffer(g_eps, 1, self.device, "g_eps") if g_eps is not None else None
         lam = self.new_state()
         L.lb_macro_adjoint(self.h, state, g_theta, g_u, lam, g_eps)
         return lam
 
     def adjoint_step(self, state_n, lam_in, lam_out, g_eps):
+        state_n = _buffer(state_n, self.state_elems, self.device, "state_n")
+        lam_in = _buffer(lam_in, self.state_elems, self.device, "lam_in")
+        lam_out = _buffer(lam_out, self.state_elems, self.device, "lam_out")
+        g_eps = _buffer(g_eps, 1, self.device, "g_eps") if g_eps is not None else None
         L.lb_adjoint_step(self.h, state_n, lam_in, lam_out, g_eps)
 
     def adjoint_segment(self, ckpt, m: int, work, lam, lam_tmp, g_eps):
         """Recompute m - 1 states after the checkpoint into ``work`` and run
         m reverse steps; ``lam`` holds dL/df at the segment end on entry and
         dL/df at the checkpoint on return."""
+        m = int(m)
+        ckpt = _buffer(ckpt, self.state_elems, self.device, "ckpt")
+        if m > 1:
+            work = _buffer(work, (m - 1) * self.state_elems, self.device, "work")
+        lam = _buffer(lam, self.state_elems, self.device, "lam")
+        lam_tmp = _buffer(lam_tmp, self.state_elems, self.device, "lam_tmp")
+        g_eps = _buffer(g_eps, 1, self.device, "g_eps") if g_eps is not None else None
         L.lb_adjoint_segment(self.h, ckpt, m, work, lam, lam_tmp, g_eps)
 
     def init_adjoint(self, theta0, grad, lam0, g_eps, want_grad: bool = False):
+        theta0 = _field(theta0, self.shape, self.device, "theta0")
+        if grad is not None:
+            grad = _field(grad, (self.d,) + self.shape, self.device, "grad")
+        lam0 = _buffer(lam0, self.state_elems, self.device, "lam0")
+        g_eps = _buffer(g_eps, 1, self.device, "g_eps") if g_eps is not None else None
         g_theta0 = torch.empty(self.shape, dtype=F64, device=self.device)
         g_grad = (torch.empty((self.d,) + self.shape, dtype=F64, device=self.device)
                   if (grad is not None and want_grad) else None)
@@ -307,6 +348,15 @@ class BatchSolver:
         return torch.cat([f.reshape(-1) for f in fields]).to(self.device, F64).contiguous()
 
     def init(self, theta0s: Sequence[torch.Tensor], grads: Optional[Sequence[torch.Tensor]] = None):
+        if len(theta0s) != len(self.grids):
+            raise ValueError(f"theta0s: expected {len(self.grids)} fields, got {len(theta0s)}")
+        if grads is not None and len(grads) != len(self.grids):
+            raise ValueError(f"grads: expected {len(self.grids)} fields, got {len(grads)}")
+        for b, (nx, ny) in enumerate(self.grids):
+            if theta0s[b].numel() != nx * ny:
+                raise ValueError(f"theta0s[{b}]: expected {nx * ny} values, got {theta0s[b].numel()}")
+            if grads is not None and grads[b].numel() != 2 * nx * ny:
+                raise ValueError(f"grads[{b}]: expected {2 * nx * ny} values, got {grads[b].numel()}")
         self._th = self.pack(theta0s)
         self._gr = self.pack(grads) if grads is not None else None
         L.lb_batch_init(self.h, self._th, self._gr)

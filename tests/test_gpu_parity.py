@@ -206,6 +206,56 @@ def test_set_state_roundtrip_and_step_buffers():
     s.close()
 
 
+def test_solver_rejects_undersized_buffers():
+    """Buffers that the kernels index directly are checked on the host:
+    too small, wrong dtype or on another device raises before any launch, and
+    the solver stays usable."""
+    _say("solver buffer checks")
+    SV = _solver_mod()
+    grid = (40, 28)
+    dx, dt, nu, th0, _ = _problem(grid, "random")
+    s = SV.Solver(grid, dx, dt, nu, device=_dev())
+    s.init(torch.from_numpy(th0).to(_dev()), None)
+    short = torch.empty(s.state_elems - 1, dtype=torch.float64, device=_dev())
+    good = s.new_state()
+    f32 = torch.empty(s.state_elems, dtype=torch.float32, device=_dev())
+    host = torch.empty(s.state_elems, dtype=torch.float64)
+    ge = torch.zeros(1, dtype=torch.float64, device=_dev())
+    with pytest.raises(ValueError):
+        s.step_buffers(short, good)
+    with pytest.raises(ValueError):
+        s.step_buffers(good, f32)
+    with pytest.raises(ValueError):
+        s.macro(host)
+    with pytest.raises(ValueError):
+        s.from_layout(short)
+    with pytest.raises(ValueError):
+        s.adjoint_step(good, good.clone(), short, ge)
+    with pytest.raises(ValueError):
+        s.adjoint_segment(s.current().clone(), 4,
+                          torch.empty(2 * s.state_elems, dtype=torch.float64, device=_dev()),
+                          good, s.new_state(), ge)
+    with pytest.raises(ValueError):
+        s.macro_adjoint(s.current(), None,
+                        torch.zeros((2, 27, 40), dtype=torch.float64, device=_dev()), ge)
+    s.step(3)
+    th, u = s.macro()
+    torch.cuda.synchronize()
+    assert bool(torch.isfinite(th).all()) and bool(torch.isfinite(u).all())
+    s.close()
+    insts = W.batch_instances(count=2, seed=3, lmin=20, lmax=40, nsteps=4)
+    bs = SV.BatchSolver(insts, device=_dev())
+    th0s = [torch.from_numpy(W.evaluate(p.modes, p.grid, p.dx)[0]) for p in insts]
+    with pytest.raises(ValueError):
+        bs.init([th0s[0], th0s[1][:-1]], None)
+    with pytest.raises(ValueError):
+        bs.init(th0s[:1], None)
+    bs.init(th0s, None)
+    bs.step(2)
+    torch.cuda.synchronize()
+    bs.close()
+
+
 def test_resident_1d_run_equals_per_step_launches():
     """Small 1-D grids run all steps in one launch (one wave with the state in
     registers for periodic grids of 64, 128 and 256 nodes, LDS-resident

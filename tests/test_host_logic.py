@@ -101,3 +101,21 @@ def test_bench_refuses_more_than_one_gpu():
     assert p.returncode == 2
     assert "one GPU only" in p.stderr
     assert p.stdout.strip() == ""  # no JSON line
+
+
+def test_solver_buffer_checks_reject_bad_buffers():
+    # the check every Solver method applies before a kernel indexes a buffer
+    import torch
+    from paper_2309_02825_amd import solver as SV
+    cpu = torch.device("cpu")
+    ok = torch.zeros(10, dtype=torch.float64)
+    assert SV._buffer(ok, 10, cpu, "x") is ok  # returned as is: kernels write into it
+    assert SV._buffer(ok, 4, cpu, "x") is ok
+    with pytest.raises(ValueError, match="at least 11"):
+        SV._buffer(ok, 11, cpu, "x")
+    with pytest.raises(ValueError, match="float64"):
+        SV._buffer(torch.zeros(10, dtype=torch.float32), 10, cpu, "x")
+    with pytest.raises(ValueError, match="not contiguous"):
+        SV._buffer(torch.zeros(20, dtype=torch.float64)[::2], 10, cpu, "x")
+    with pytest.raises(TypeError):
+        SV._buffer([0.0] * 10, 10, cpu, "x")
