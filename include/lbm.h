@@ -153,7 +153,10 @@ lb_status lb_init(lb_solver* s, const double* theta0, const double* grad_theta0,
 lb_status lb_theta_from_velocity(lb_solver* s, const double* u0, double* theta0, double* grad);
 
 /* Advance nsteps >= 0 time steps (evolution equation of Sec. III.A: collide in
- * moment space, then stream), alternating the two buffers. */
+ * moment space, then stream), alternating the two buffers.  How the steps are
+ * grouped into launches (passes of several steps, see LB_OPT_STEPS_PER_PASS;
+ * on 1-D grids of up to 2048 nodes the whole run in one launch) never changes
+ * the result: it is bitwise that of single steps. */
 lb_status lb_step(lb_solver* s, int64_t nsteps);
 
 /* LB_FLAG_BOUNDED solvers: advance nsteps >= 0 time steps on the interval.
@@ -166,14 +169,17 @@ lb_status lb_step(lb_solver* s, int64_t nsteps);
 lb_status lb_step_bounded(lb_solver* s, int64_t nsteps, const double* walls);
 
 /* Options of a solver (lb_set_option).
- * LB_OPT_STEPS_PER_PASS (default 8): on D2Q9, the most time steps lb_step
- * advances with one pass over the state in HBM (temporal blocking: row strips
- * march through LDS and registers, all steps on chip).  A run of nsteps is
- * split greedily into passes of 8, 4 and 2 steps (within the limit) and
- * single steps; the result is bitwise that of single steps.  Values below 2
- * make every step a separate launch; others are rounded down to 2, 4 or 8.
- * Other lattices always take single steps.  Unknown options are
- * LB_ERR_INVALID_ARG. */
+ * LB_OPT_STEPS_PER_PASS (default 8): the most time steps lb_step advances with
+ * one pass over the state in HBM (temporal blocking: the intermediate steps
+ * stay on chip).  D2Q9: a run of nsteps is split greedily into passes of 8,
+ * 4 and 2 steps (within the limit) and single steps; one wave marches down a
+ * strip of columns, neighbouring columns exchange populations by lane shifts
+ * and rows are delayed in registers.  D3Q19: passes of 2 steps (x-y tiles
+ * marching along z, populations exchanged through LDS) and a single step for
+ * an odd remainder, whenever the limit is 2 or more.  Values below 2 make
+ * every step a separate launch; others are rounded down to 2, 4 or 8.  D1Q3
+ * and D4Q33 take single steps.  Every grouping gives bitwise the result of
+ * single steps.  Unknown options are LB_ERR_INVALID_ARG. */
 enum { LB_OPT_STEPS_PER_PASS = 1 };
 lb_status lb_set_option(lb_solver* s, int32_t option, int32_t value);
 
@@ -246,10 +252,11 @@ lb_status lb_adjoint_step(lb_solver* s, const double* state_n, const double* lam
  * (m - 1 consecutive state buffers of lb_state_bytes each; may be NULL when
  * m = 1), bitwise as single steps would (on D2Q9 by multi-step passes that
  * store every step, up to LB_OPT_STEPS_PER_PASS steps each), then applies
- * the adjoint steps for n = n0+m-1 down to n0.  lambda: in dL/df^{n0+m}, out dL/df^{n0}; lambda_tmp is a second
- * state buffer used as the ping-pong partner.  lambda on return is bitwise
- * that of m lb_adjoint_step calls.  On D2Q9 the reverse sweep runs in passes
- * of up to min(4, LB_OPT_STEPS_PER_PASS) adjoint steps (the forward passes' one-wave
+ * the adjoint steps for n = n0+m-1 down to n0.  lambda holds dL/df^{n0+m}
+ * on entry and dL/df^{n0} on return; lambda_tmp is a second state buffer
+ * used as the ping-pong partner.  lambda on return is bitwise that of m
+ * lb_adjoint_step calls.  On D2Q9 the reverse sweep runs in passes of up to
+ * min(4, LB_OPT_STEPS_PER_PASS) adjoint steps (the forward passes' one-wave
  * march with every velocity reversed); each wave sums the eps parts of its
  * nodes in a fixed order, so *g_eps is deterministic but rounded differently
  * from the single calls.  Other lattices take one adjoint step per launch
