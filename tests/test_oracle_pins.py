@@ -207,6 +207,33 @@ def test_spectral_evaluator_matches_direct_oracle(d, grid, steps):
     assert np.max(np.abs(u - us) / scale[None]) < 1e-14
 
 
+@pytest.mark.parametrize("seed", range(24))
+def test_spectral_matches_direct_oracle_random_cases(seed):
+    """Property form of the check above: lattice, grid (3..9 nodes per axis,
+    odd and even), eps across the accepted range of the lattice (D1Q3 up to
+    2, D2Q9 up to 0.48, D3Q19 up to 1/4), step count and modes all drawn at
+    random.  Any mistake in the direct oracle's velocity table, moment rows,
+    rates, weights, initialisation or streaming shows up as a mismatch with
+    the Fourier-space evaluation, which shares none of that code."""
+    rng = np.random.default_rng(1000 + seed)
+    d = int(rng.integers(1, 4))
+    grid = tuple(int(rng.integers(3, 10)) for _ in range(d))
+    eps_max = {1: 2.0, 2: 0.48, 3: 0.25}[d]
+    eps = float(rng.uniform(0.02, eps_max))
+    dx, nu = 1.0 / grid[0], float(rng.uniform(0.005, 0.1))
+    dt = eps * dx * dx / nu
+    steps = int(rng.integers(1, 40))
+    modes = _random_modes(d, grid, 4, rng)
+    th0, g0 = W.evaluate(modes, grid, dx)
+    f = O.run(O.init(th0, g0, dx, dt, nu), dx, dt, nu, steps)
+    sol = S.ModeSolution(grid, dx, dt, nu, modes, steps)
+    fs = S.to_field(sol.state(S.all_points(grid)).astype(np.float64), grid)
+    assert max_rel(f, fs) < 1e-12, (d, grid, eps, steps)
+    th, _ = O.macro(f, dx, dt, nu)
+    ths, _ = sol.macro(S.all_points(grid))
+    assert max_rel(th, S.to_field(ths.astype(np.float64), grid)) < 1e-12, (d, grid, eps, steps)
+
+
 def _fd_scheme_poly(d, eps, kappa):
     """Coefficients p_0..p_q of the macroscopic finite-difference scheme of
     Sec. III.B for one Fourier mode:
