@@ -131,6 +131,41 @@ def test_parity_with_direct_oracle(name, grid, nsteps, kind):
         assert np.max(np.abs(u_g[a] - u_o[a])) <= TOL_U * den, (name, a)
 
 
+@pytest.mark.parametrize("seed", range(12))
+def test_parity_random_shapes_and_pass_lengths(seed):
+    """Seeded random 2-D and 3-D cases: grid sizes from 1 to a few strips or
+    tiles wide (ragged against every strip and tile width), eps across the
+    accepted range, step counts that leave remainders for every pass length,
+    and a random pass limit.  The state matches the oracle, and equals
+    bitwise the run with one step per launch."""
+    rng = np.random.default_rng(500 + seed)
+    d = 2 if seed < 8 else 3
+    grid = ((int(rng.integers(1, 200)), int(rng.integers(1, 90))) if d == 2
+            else tuple(int(rng.integers(1, 40)) for _ in range(3)))
+    eps = float(rng.uniform(0.02, 0.48 if d == 2 else 0.25))
+    nsteps = int(rng.integers(1, 41))
+    spp = int(rng.choice([2, 4, 8]))
+    _say("random", seed, grid, round(eps, 4), nsteps, spp)
+    dx, nu = 1.0 / max(grid), 0.01
+    dt = eps * dx * dx / nu
+    th0 = W.random_smooth_field(rng, tuple(reversed(grid)))
+    f_o = O.run(O.init(th0, O.grad_fd4(th0, dx), dx, dt, nu), dx, dt, nu, nsteps)
+    SV = _solver_mod()
+    outs = []
+    for p in (spp, 1):
+        s = SV.Solver(grid, dx, dt, nu, device=_dev())
+        s.set_steps_per_pass(p)
+        s.init(torch.from_numpy(np.ascontiguousarray(th0)).to(_dev()), None)
+        s.step(nsteps)
+        outs.append(s.get_state())
+        torch.cuda.synchronize()
+        s.close()
+    assert torch.equal(outs[0], outs[1]), (grid, nsteps, spp)
+    f_g = outs[0].cpu().numpy()
+    print(f"[gpu-case] random {seed}: f {max_rel(f_g, f_o):.2e}", flush=True)
+    assert max_rel(f_g, f_o) <= TOL_F, (grid, eps, nsteps, spp)
+
+
 @pytest.mark.parametrize("example,level", [(2, 1), (3, 0), (4, 0)])
 def test_theta_from_velocity_matches_oracle(example, level):
     """Burgers front end on the GPU (inverse Cole-Hopf from the paper's initial
