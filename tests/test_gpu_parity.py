@@ -883,6 +883,45 @@ def test_batch_matches_single_instance_runs():
     bs.close()
 
 
+BATCH_TILES = ((0, 0), (16, 16), (64, 4), (256, 1), (-2, 7), (-4, 33), (-8, 1), (-8, 64),
+               (-8, 300), (-18, 5), (-20, 40), (-24, 16), (-24, 1))
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_batch_random_instances_and_tile_plans(seed):
+    """Seeded random batches of non-square instances (1 to 260 by 1 to 120
+    nodes, eps over the accepted range, gradients by differences) advanced by a
+    random plan of tile modes, step counts and graph use: every instance ends
+    bitwise equal to its own single-instance run."""
+    _say("batch random", seed)
+    SV = _solver_mod()
+    rng = np.random.default_rng(900 + seed)
+    count = int(rng.integers(1, 13))
+    insts, th0s = [], []
+    for b in range(count):
+        grid = (int(rng.integers(1, 261)), int(rng.integers(1, 121)))
+        dx, nu = 1.0 / max(grid), float(rng.uniform(0.005, 0.05))
+        dt = float(rng.uniform(0.02, 0.48)) * dx * dx / nu
+        insts.append(W.Workload(f"r{seed}_{b}", grid, dx, dt, nu, [], 0))
+        th0s.append(torch.from_numpy(W.random_smooth_field(rng, (grid[1], grid[0]))))
+    plan = [(BATCH_TILES[int(i)], int(rng.integers(1, 13)), bool(rng.integers(0, 2)))
+            for i in rng.choice(len(BATCH_TILES), size=3, replace=False)]
+    _say("batch random", seed, [p.grid for p in insts], plan)
+    bs = SV.BatchSolver(insts, device=_dev())
+    bs.init(th0s, None)
+    for (tx, ty), n, graph in plan:
+        bs.set_tile(tx, ty)
+        bs.step(n, graph=graph)
+    total = sum(n for _t, n, _g in plan)
+    ths, us = bs.macro()
+    torch.cuda.synchronize()
+    for b, p in enumerate(insts):
+        th, u, _ = _gpu_run(p.grid, p.dx, p.dt, p.nu, th0s[b].numpy(), None, total, want_f=False)
+        assert np.array_equal(ths[b].cpu().numpy(), th), (b, p.grid)
+        assert np.array_equal(us[b].cpu().numpy(), u), (b, p.grid)
+    bs.close()
+
+
 def test_batch_rejects_invalid_tile_modes():
     """Tile modes outside (0,0), (-S, rows), (-16-S, rows) with S in {2,4,8}
     and rows in [1,65535], and 256-thread power-of-two rectangles, are
