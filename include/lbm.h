@@ -328,8 +328,9 @@ lb_status lb_batch_autotune(lb_batch* b, int32_t steps_per_trial, int32_t* best_
                             int32_t* best_ty);
 
 /* Advance every instance nsteps.  With use_graph != 0 the nsteps launches
- * are captured once into a hipGraph (cached per nsteps) and replayed with a
- * single hipGraphLaunch. */
+ * are captured once into a hipGraph (cached per nsteps and starting pool, up
+ * to 16 graphs; capturing a 17th first waits for the batch's stream and
+ * clears the cache) and replayed with a single hipGraphLaunch. */
 lb_status lb_batch_step(lb_batch* b, int64_t nsteps, int32_t use_graph);
 
 /* theta (packed V_b per instance) and u (packed 2 x V_b per instance, at

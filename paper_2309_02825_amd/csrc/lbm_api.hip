@@ -664,6 +664,10 @@ static void drop_graphs(lb_batch* b) {
     b->graphs.clear();
 }
 
+// Graphs kept per batch (one per step count and starting pool); a new one
+// beyond this clears the cache once the work already enqueued has finished.
+constexpr size_t kMaxCachedGraphs = 16;
+
 // Tile tables.  tx == 0: 256 consecutive node indices of one instance;
 // multi-step modes: S-step tiles of mode_width(tx) columns x ty rows (y1 in
 // .pad), ordered strip-fastest within an instance so that neighbouring strips
@@ -887,6 +891,11 @@ lb_status lb_batch_step(lb_batch* b, int64_t nsteps, int32_t use_graph) {
         auto key = std::make_pair(nsteps, b->cur);
         auto it = b->graphs.find(key);
         if (it == b->graphs.end()) {
+            if (b->graphs.size() >= kMaxCachedGraphs) {
+                // a cached graph may still be running on the stream
+                LB_HIP(hipStreamSynchronize(b->stream), "hipStreamSynchronize");
+                drop_graphs(b);
+            }
             hipGraph_t graph = nullptr;
             LB_HIP(hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal),
                    "hipStreamBeginCapture");

@@ -922,6 +922,29 @@ def test_batch_random_instances_and_tile_plans(seed):
     bs.close()
 
 
+def test_batch_graph_cache_beyond_its_limit():
+    """Twenty different step counts, each captured into its own graph: the
+    cache is cleared when it holds sixteen, and the run stays bitwise equal
+    to the same steps launched without graphs."""
+    _say("batch graph cache")
+    SV = _solver_mod()
+    insts = W.batch_instances(count=3, seed=11, lmin=30, lmax=90, nsteps=4)
+    th0s = [torch.from_numpy(W.evaluate(p.modes, p.grid, p.dx)[0]) for p in insts]
+    outs = []
+    for graph in (True, False):
+        bs = SV.BatchSolver(insts, device=_dev())
+        bs.init(th0s, None)
+        bs.set_tile(-8, 16)
+        for n in range(1, 21):
+            bs.step(n, graph=graph)
+        ths, us = bs.macro()
+        torch.cuda.synchronize()
+        outs.append([t.cpu() for t in ths] + [u.cpu() for u in us])
+        bs.close()
+    for a, b in zip(*outs):
+        assert torch.equal(a, b)
+
+
 def test_batch_rejects_invalid_tile_modes():
     """Tile modes outside (0,0), (-S, rows), (-16-S, rows) with S in {2,4,8}
     and rows in [1,65535], and 256-thread power-of-two rectangles, are
