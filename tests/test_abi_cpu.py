@@ -139,3 +139,14 @@ def test_bounded_flag_validation():
     for fn, args in [(L.lb_step_bounded, (0, 1, None))]:
         with pytest.raises(L.LBError):
             fn(*args)
+
+
+def test_binding_fails_loudly_without_library(monkeypatch):
+    # no CPU fallback: without the built HIP library every entry point refuses
+    from paper_2309_02825_amd import lbm
+    monkeypatch.setattr(lbm, "LIBPATH", "/nonexistent/liblbm_hip.so")
+    monkeypatch.setattr(lbm, "_lib", None)
+    with pytest.raises(RuntimeError, match="no fallback"):
+        lbm.library()
+    with pytest.raises(RuntimeError, match="no fallback"):
+        lbm.lb_num_populations(2)
