@@ -46,9 +46,12 @@ def log(*a):
 
 def d2_kernel(steps: int, nodes: int) -> str:
     """Name of the D2Q9 pass kernel as the trace shows it: the variant with
-    32-bit offsets runs when the state buffer is under 4 GiB."""
-    elems = 9 * ((nodes + 4095) // 4096) * 4096
-    return f"k_steps_d2q9<{steps}, {'true' if elems * 8 <= 0xFFFFFFFF else 'false'}>"
+    cached stores runs when both state buffers fit in the 256 MB Infinity
+    Cache, the one with 32-bit offsets when a state buffer is under 4 GiB."""
+    state_bytes = 9 * ((nodes + 4095) // 4096) * 4096 * 8
+    if 2 * state_bytes <= 256 << 20:
+        return f"k_steps_d2q9_cached<{steps}, true>"
+    return f"k_steps_d2q9<{steps}, {'true' if state_bytes <= 0xFFFFFFFF else 'false'}>"
 
 
 def kernel_source_hash() -> str:

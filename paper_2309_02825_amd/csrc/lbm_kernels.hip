@@ -423,6 +423,9 @@ template <> struct MsAddr<true> {
     __device__ __forceinline__ void store(double* p, int i, double v) const {
         __builtin_nontemporal_store(v, (GDouble*)(wave_base(p + (int64_t)i * CHUNK) + off));
     }
+    __device__ __forceinline__ void store_cached(double* p, int i, double v) const {
+        *(GDouble*)(wave_base(p + (int64_t)i * CHUNK) + off) = v;
+    }
 };
 template <> struct MsAddr<false> {
     int k;
@@ -431,10 +434,23 @@ template <> struct MsAddr<false> {
     __device__ __forceinline__ void store(double* p, int i, double v) const {
         __builtin_nontemporal_store(v, p + slot<9>(i, k));
     }
+    __device__ __forceinline__ void store_cached(double* p, int i, double v) const {
+        p[slot<9>(i, k)] = v;
+    }
 };
 // Whether a D2Q9 state buffer of g allows MsAddr<true>.
 __host__ __device__ inline bool ms_off32(const Geo& g) {
     return (uint64_t)9 * (uint64_t)chunks_of(g.V) * CHUNK * sizeof(double) <= 0xffffffffull;
+}
+
+// Whether the plain D2Q9 passes write with cached stores: both state buffers
+// fit in the 256 MB Infinity Cache, so the next pass finds its input there.
+// Otherwise non-temporal stores are faster (8 steps per pass, GLUPS
+// non-temporal / cached: 1024^2 196 / 207, 1280^2 216 / 247, 1448^2
+// (288 MiB) 215 / 220, 1600^2 (352 MiB) 231 / 223, 4096^2 280 / 266).
+constexpr uint64_t kInfinityCacheBytes = 256ull << 20;
+inline bool d2q9_cached_stores(const Geo& g) {
+    return 2ull * 9ull * (uint64_t)chunks_of(g.V) * CHUNK * sizeof(double) <= kInfinityCacheBytes;
 }
 
 template <int S>
@@ -447,8 +463,9 @@ struct MsState {
 // One iteration k of the march; P = k & 1; stages above ACTIVE are skipped
 // (pipeline fill), stage S stores only when ACTIVE == S.  ALL: stage j < S
 // also stores its rows of [ys, ye) to dst - (S - j) stride (the state after
-// j steps, for a caller that keeps every intermediate state).
-template <int S, int P, int ACTIVE, bool ALL, bool OFF32>
+// j steps, for a caller that keeps every intermediate state).  NT: stage S
+// writes with non-temporal stores (otherwise through the caches).
+template <int S, int P, int ACTIVE, bool ALL, bool OFF32, bool NT = true>
 __device__ __forceinline__ void ms_row(MsState<S>& st, int k,
                                        const double* __restrict__ src, double* __restrict__ dst,
                                        int nx, int ny, int gx, int ys, int x0, const FoldedRates& r,
@@ -496,7 +513,12 @@ __device__ __forceinline__ void ms_row(MsState<S>& st, int k,
             if (j == S && ACTIVE == S && lane >= S && lane < S + W && x0 - S + lane < nx) {
                 const MsAddr<OFF32> a(wrapi(ys - 2 * S + k, ny) * nx + x0 - S + lane);
 #pragma unroll
-                for (int i = 0; i < 9; ++i) a.store(dst, i, in[i]);
+                for (int i = 0; i < 9; ++i) {
+                    if constexpr (NT)
+                        a.store(dst, i, in[i]);
+                    else
+                        a.store_cached(dst, i, in[i]);
+                }
             }
             if (ALL && j < S) {
                 // row ys + k - S - j of step j; lanes S .. S+W-1 hold valid
@@ -514,20 +536,21 @@ __device__ __forceinline__ void ms_row(MsState<S>& st, int k,
     }
 }
 
-template <int S, int K, bool ALL, bool OFF32>
+template <int S, int K, bool ALL, bool OFF32, bool NT = true>
 __device__ __forceinline__ void ms_fill(MsState<S>& st, const double* __restrict__ src,
                                         double* __restrict__ dst, int nx, int ny, int gx, int ys,
                                         int x0, const FoldedRates& r, int nrows, int64_t stride) {
     if constexpr (K < 2 * S) {
-        ms_row<S, K & 1, K / 2, ALL, OFF32>(st, K, src, dst, nx, ny, gx, ys, x0, r, nrows, stride);
-        ms_fill<S, K + 1, ALL, OFF32>(st, src, dst, nx, ny, gx, ys, x0, r, nrows, stride);
+        ms_row<S, K & 1, K / 2, ALL, OFF32, NT>(st, K, src, dst, nx, ny, gx, ys, x0, r, nrows,
+                                                stride);
+        ms_fill<S, K + 1, ALL, OFF32, NT>(st, src, dst, nx, ny, gx, ys, x0, r, nrows, stride);
     }
 }
 
 // Advance rows [ys, ye) (ye > ys) of the columns [x0, x0 + 64 - 2S) of one
 // D2Q9 grid by S steps (reads rows ys-S .. ye-1+S and columns x0-S ..
 // x0+63-S, wrapped periodically).  All 64 lanes of the wave must be active.
-template <int S, bool ALL, bool OFF32>
+template <int S, bool ALL, bool OFF32, bool NT = true>
 __device__ __forceinline__ void ms_tile(const double* __restrict__ src, double* __restrict__ dst,
                                         int nx, int ny, const FoldedRates& r, int x0, int ys,
                                         int ye, int64_t stride = 0) {
@@ -544,11 +567,12 @@ __device__ __forceinline__ void ms_tile(const double* __restrict__ src, double* 
 #pragma unroll
         for (int a = 0; a < 3; ++a) st.z[j][a] = st.u[0][j][a] = st.u[1][j][a] = 0.0;
     const int nrows = ye - ys;
-    ms_fill<S, 0, ALL, OFF32>(st, src, dst, nx, ny, gx, ys, x0, r, nrows, stride);
+    ms_fill<S, 0, ALL, OFF32, NT>(st, src, dst, nx, ny, gx, ys, x0, r, nrows, stride);
     for (int k = 2 * S; k <= kend; k += 2) {
-        ms_row<S, 0, S, ALL, OFF32>(st, k, src, dst, nx, ny, gx, ys, x0, r, nrows, stride);
+        ms_row<S, 0, S, ALL, OFF32, NT>(st, k, src, dst, nx, ny, gx, ys, x0, r, nrows, stride);
         if (k + 1 <= kend)
-            ms_row<S, 1, S, ALL, OFF32>(st, k + 1, src, dst, nx, ny, gx, ys, x0, r, nrows, stride);
+            ms_row<S, 1, S, ALL, OFF32, NT>(st, k + 1, src, dst, nx, ny, gx, ys, x0, r, nrows,
+                                            stride);
     }
 }
 
@@ -564,6 +588,20 @@ k_steps_d2q9(const double* __restrict__ src,
     const int ys = seg * ly;
     ms_tile<S, false, OFF32>(src, dst, g.nx, g.ny, folded(r), strip * strip_width(S), ys,
                              min(ys + ly, g.ny), 0);
+}
+
+// The same pass with cached stores, for grids whose two states fit in the
+// Infinity Cache (the next pass then reads its input from there).
+template <int S, bool OFF32>
+__global__ void __launch_bounds__(MS_THREADS) __attribute__((amdgpu_waves_per_eu(2)))
+k_steps_d2q9_cached(const double* __restrict__ src, double* __restrict__ dst, Geo g, Rates r,
+                    int ly, int nstrips) {
+    const unsigned t = xcd_remap(blockIdx.x, gridDim.x);
+    const int strip = (int)(t % (unsigned)nstrips);
+    const int seg = (int)(t / (unsigned)nstrips);
+    const int ys = seg * ly;
+    ms_tile<S, false, OFF32, false>(src, dst, g.nx, g.ny, folded(r), strip * strip_width(S), ys,
+                                    min(ys + ly, g.ny), 0);
 }
 
 // The same pass writing the state after every one of its S steps: step j to
@@ -1640,12 +1678,16 @@ static hipError_t launch_steps_t(const Geo& g, const Rates& r, const double* src
     const int nstrips = (g.nx + w - 1) / w;
     const int ly = steps_rows(g, nstrips, kMinRows);
     const int nseg = (g.ny + ly - 1) / ly;
-    if (ms_off32(g))
-        hipLaunchKernelGGL((k_steps_d2q9<S, true>), dim3((unsigned)((int64_t)nstrips * nseg)),
-                           dim3(MS_THREADS), 0, st, src, dst, g, r, ly, nstrips);
+    const dim3 grid((unsigned)((int64_t)nstrips * nseg));
+    if (d2q9_cached_stores(g))  // both states fit in 256 MB, so under 4 GiB
+        hipLaunchKernelGGL((k_steps_d2q9_cached<S, true>), grid, dim3(MS_THREADS), 0, st, src, dst,
+                           g, r, ly, nstrips);
+    else if (ms_off32(g))
+        hipLaunchKernelGGL((k_steps_d2q9<S, true>), grid, dim3(MS_THREADS), 0, st, src, dst, g, r,
+                           ly, nstrips);
     else
-        hipLaunchKernelGGL((k_steps_d2q9<S, false>), dim3((unsigned)((int64_t)nstrips * nseg)),
-                           dim3(MS_THREADS), 0, st, src, dst, g, r, ly, nstrips);
+        hipLaunchKernelGGL((k_steps_d2q9<S, false>), grid, dim3(MS_THREADS), 0, st, src, dst, g, r,
+                           ly, nstrips);
     return hipGetLastError();
 }
 
