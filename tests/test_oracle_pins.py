@@ -12,6 +12,9 @@ Each test checks the oracle against something other than itself:
   * fourth-order convergence to the closed-form heat solution, with negative
     controls that fail when the initialisation or the velocity formula is
     altered;
+  * fourth-order convergence of grad theta read from the non-equilibrium
+    moment, and the Cole-Hopf identity u = -2 nu grad(theta)/theta between it
+    and the velocity formula;
   * the discrete adjoint by dot-product tests and central differences.
 """
 import math
@@ -386,6 +389,82 @@ def test_grad_fd4_order_and_transpose():
     lhs = np.sum(O.grad_fd4(a, 0.3) * b)
     rhs = np.sum(a * O.grad_fd4_transpose(b, 0.3))
     assert abs(lhs - rhs) < 1e-12 * abs(lhs)
+
+
+# --------------------------------------------------------------------------
+# gradient of theta from the non-equilibrium first moment (Sec. III.C)
+# --------------------------------------------------------------------------
+
+def _grad_errors(wl, post_collision=False):
+    """RMSE and max error of the oracle's grad theta against the closed-form
+    gradient of the heat solution at the end of the run."""
+    th0, g0 = W.evaluate(wl.modes, wl.grid, wl.dx)
+    f = O.run(O.init(th0, g0, wl.dx, wl.dt, wl.nu), wl.dx, wl.dt, wl.nu, wl.nsteps)
+    if post_collision:
+        C, _ = O.collision_matrix(wl.d, wl.eps)
+        f = np.einsum("ik,k...->i...", C, f)
+    g = O.grad_theta(f, wl.dx, wl.dt, wl.nu)
+    modes_t = W.decay_modes(wl.modes, wl.grid, wl.dx, wl.nu, wl.nsteps * wl.dt)
+    _, ge = W.evaluate(modes_t, wl.grid, wl.dx)
+    return rmse(g, ge), float(np.abs(g - ge).max())
+
+
+@pytest.mark.parametrize("case", ["heat1d", "ex2_eps0.1", "ex2_eps0.3", "ex3_eps0.15"])
+def test_grad_theta_fourth_order(case):
+    """Sec. III.C states that the gradient read from the non-equilibrium
+    first moment is fourth-order accurate: under diffusive scaling (dx/2,
+    dt/4) its error against the exact gradient of the heat solution falls by
+    about 16 per level.  A sign error, a wrong c_s^2 or a wrong factor s1
+    leaves an O(1) relative error and fails the bound on the finest level."""
+    if case == "heat1d":
+        wls = [W.heat_1d(n) for n in (16, 32, 64, 128)]
+        lo, hi = 15.5, 16.5
+    elif case.startswith("ex2"):
+        eps = float(case.split("eps")[1])
+        wls = [W.paper_example2(lvl, eps) for lvl in (0, 1, 2)]
+        lo, hi = 15.5, 16.5
+    else:
+        # D3Q19: levels 0-1 are still pre-asymptotic (ratio ~17.6)
+        wls = [W.paper_example3(lvl, 0.15) for lvl in (0, 1)]
+        lo, hi = 15.0, 18.5
+    errs = [_grad_errors(wl) for wl in wls]
+    for v in range(2):
+        ratios = [errs[i][v] / errs[i + 1][v] for i in range(len(errs) - 1)]
+        assert all(lo < r < hi for r in ratios), (case, v, ratios)
+    # the error is a small fraction of the gradient itself on the finest level
+    wl = wls[-1]
+    _, ge = W.evaluate(W.decay_modes(wl.modes, wl.grid, wl.dx, wl.nu, wl.nsteps * wl.dt),
+                       wl.grid, wl.dx)
+    assert errs[-1][1] < 1e-2 * np.abs(ge).max()
+
+
+def test_grad_theta_negative_control_post_collision():
+    """Reading the gradient from the post-collision distribution (the wrong
+    reading of which f enters the formula) gives an O(1) error that does not
+    fall with the grid: the convergence test above would catch it."""
+    e = [_grad_errors(W.heat_1d(n), post_collision=True)[1] for n in (32, 64)]
+    assert e[1] > 0.5 * e[0] and e[1] > 1.0
+
+
+@pytest.mark.parametrize("d,shape", [(1, (13,)), (2, (9, 7)), (3, (5, 6, 4)), (4, (3, 4, 3, 5))])
+def test_grad_theta_cole_hopf_identity(d, shape):
+    """Sec. II: u = -2 nu grad(theta)/theta.  With grad theta from the
+    non-equilibrium moment this must equal the velocity formula of
+    Sec. III.C, u = (2 - s1) sum_k c_k f^ne_k / theta, for any distribution
+    (since 2 - s1 = 6 eps s1 and c_s^2 = c^2/3), up to rounding relative to
+    (2 - s1) c sum|f| / theta."""
+    rng = np.random.default_rng(31 + d)
+    dx, nu = 0.07, 0.015
+    dt = (0.21 if d < 3 else 0.11) * dx * dx / nu
+    q = 1 + 2 * d * d
+    f = rng.uniform(0.05, 0.3, size=(q,) + shape)
+    g = O.grad_theta(f, dx, dt, nu)
+    th, u = O.macro(f, dx, dt, nu)
+    s1 = O.lattice(d, nu * dt / dx ** 2).s[1]
+    scale = (2 - s1) * (dx / dt) * np.abs(f).sum(axis=0) / th
+    assert np.max(np.abs(-2 * nu * g / th[None] - u) / scale[None]) < 1e-14
+    # and grad theta is not identically zero on such data
+    assert np.abs(g).max() > 1e-3 * np.max(3 * s1 / dx * np.abs(f).sum(axis=0))
 
 
 # --------------------------------------------------------------------------
