@@ -194,16 +194,22 @@ int64_t lb_steps_taken(const lb_solver* s);
 
 /* Macroscopic output at the current time t = steps * dt from the
  * pre-collision distribution (Sec. III.C):
- *   theta = sum_i f_i,
- *   u_a   = (2 - s1) sum_i c_{ia} f^ne_i / theta,  f^ne = f - w theta,
- * which equals -2 nu d_a theta / theta with the fourth-order gradient
- * d_a theta = -(s1/(dt c_s^2)) sum_i c_{ia} f^ne_i.  theta (V) or u (d x V)
- * may be NULL.  LB_FLAG_BOUNDED: the end nodes' distribution is completed
- * with the current boundary theta, so theta there equals it. */
-lb_status lb_macro(lb_solver* s, double* theta, double* u);
+ *   theta        = sum_i f_i,
+ *   grad_theta_a = -(s1/(dt c_s^2)) sum_i c_{ia} f^ne_i,  f^ne = f - w theta,
+ *                  the fourth-order gradient read from the non-equilibrium
+ *                  first moment (Theorem 1 and the formula after it);
+ *                  c_s^2 = c^2/3 on every lattice here,
+ *   u_a          = -2 nu grad_theta_a / theta = (2 - s1) sum_i c_{ia} f^ne_i / theta
+ *                  (Cole-Hopf, Sec. II; the two forms agree since 2 - s1 = 6 eps s1).
+ * theta (V), u (d x V) and grad_theta (d x V, component a along x_a) may each
+ * be NULL; with all three NULL the call does nothing.  LB_FLAG_BOUNDED: the
+ * end nodes' distribution is completed with the current boundary theta, so
+ * theta there equals it. */
+lb_status lb_macro(lb_solver* s, double* theta, double* u, double* grad_theta);
 
 /* Same as lb_macro for an explicit state buffer in the storage layout. */
-lb_status lb_macro_buffer(lb_solver* s, const double* state, double* theta, double* u);
+lb_status lb_macro_buffer(lb_solver* s, const double* state, double* theta, double* u,
+                          double* grad_theta);
 
 /* Copy the current pre-collision distribution to f_out in the dense
  * canonical layout (q planes of V doubles, f_out[i*V + k] = f_i(node k)).
@@ -271,10 +277,14 @@ lb_status lb_adjoint_segment(lb_solver* s, const double* ckpt, int64_t m, double
  * is written to g_grad (d x V, may be NULL); if grad_theta0 == NULL the
  * fourth-order difference stencil is transposed into g_theta0.  theta0 and
  * grad_theta0 are the inputs given to lb_init; the eps dependence of the
- * initial state is added to *g_eps. */
+ * initial state is added to *g_eps.  This is the last call of a reverse
+ * sweep, so g_nu (one device double, may be NULL) then receives
+ * dL/dnu = (dt/dx^2) * (*g_eps), the whole gradient with respect to the
+ * viscosity (eps = nu dt/dx^2 is the only place nu enters the scheme).
+ * g_nu must not be g_eps. */
 lb_status lb_init_adjoint(lb_solver* s, const double* theta0, const double* grad_theta0,
                           const double* lambda0, double* g_theta0, double* g_grad,
-                          double* g_eps);
+                          double* g_eps, double* g_nu);
 
 /* Destroy a solver (does not free the caller's buffers).  NULL is allowed. */
 lb_status lb_destroy(lb_solver* s);

@@ -72,6 +72,9 @@ Rates make_rates(int d, double dx, double dt, double nu) {
     r.R4wd = 4.0 * r.wd;
     r.c = dx / dt;
     r.ucoef = (2.0 - r.s1) * r.c;
+    // grad theta = -(s1/(dt c_s^2)) sum_i c_i f^ne_i (Sec. III.C) with c_i = c e_i
+    // and c_s^2 = c^2/3 on every lattice here
+    r.gcoef = -3.0 * r.s1 / dx;
     r.dx = dx;
     r.inv_s1_m1 = 1.0 / r.s1 - 1.0;
     r.inv12dx = 1.0 / (12.0 * dx);
@@ -415,26 +418,28 @@ lb_status lb_step_buffers(lb_solver* s, const double* src, double* dst) {
 double* lb_current_state(const lb_solver* s) { return s ? s->buf[s->cur] : nullptr; }
 int64_t lb_steps_taken(const lb_solver* s) { return s ? s->steps : -1; }
 
-lb_status lb_macro_buffer(lb_solver* s, const double* state, double* theta, double* u) {
+lb_status lb_macro_buffer(lb_solver* s, const double* state, double* theta, double* u,
+                          double* grad_theta) {
     if (!s || !state) return fail(LB_ERR_INVALID_ARG, "NULL argument");
     lb_status st = not_bounded(s, "lb_macro_buffer is periodic only (use lb_macro)");
     if (st != LB_OK) return st;
-    if (!theta && !u) return LB_OK;
-    LB_HIP(lbm::launch_macro(s->d, s->g, s->r, state, theta, u, s->stream), "macro launch");
+    if (!theta && !u && !grad_theta) return LB_OK;
+    LB_HIP(lbm::launch_macro(s->d, s->g, s->r, state, theta, u, grad_theta, s->stream),
+           "macro launch");
     return LB_OK;
 }
 
-lb_status lb_macro(lb_solver* s, double* theta, double* u) {
+lb_status lb_macro(lb_solver* s, double* theta, double* u, double* grad_theta) {
     if (!s) return fail(LB_ERR_INVALID_ARG, "solver is NULL");
     if (!s->inited) return fail(LB_ERR_STATE, "lb_macro before lb_init/lb_set_state");
     if (s->bounded) {
-        if (!theta && !u) return LB_OK;
-        LB_HIP(lbm::launch_macro_wall1(s->g, s->r, s->buf[s->cur], theta, u, s->wall_now,
-                                       s->stream),
+        if (!theta && !u && !grad_theta) return LB_OK;
+        LB_HIP(lbm::launch_macro_wall1(s->g, s->r, s->buf[s->cur], theta, u, grad_theta,
+                                       s->wall_now, s->stream),
                "macro launch");
         return LB_OK;
     }
-    return lb_macro_buffer(s, s->buf[s->cur], theta, u);
+    return lb_macro_buffer(s, s->buf[s->cur], theta, u, grad_theta);
 }
 
 lb_status lb_get_state(lb_solver* s, double* f_out) {
@@ -604,15 +609,19 @@ lb_status lb_adjoint_segment(lb_solver* s, const double* ckpt, int64_t m, double
 
 lb_status lb_init_adjoint(lb_solver* s, const double* theta0, const double* grad_theta0,
                           const double* lambda0, double* g_theta0, double* g_grad,
-                          double* g_eps) {
+                          double* g_eps, double* g_nu) {
     if (!s || !theta0 || !lambda0 || !g_theta0 || !g_eps)
         return fail(LB_ERR_INVALID_ARG, "NULL argument");
+    if (g_nu == g_eps) return fail(LB_ERR_INVALID_ARG, "g_nu and g_eps must differ");
     lb_status st = not_bounded(s, "the adjoint is periodic only");
     if (st != LB_OK) return st;
     LB_HIP(lbm::launch_init_adjoint(s->d, s->g, s->r, theta0, grad_theta0, lambda0, g_theta0,
                                     g_grad, s->partials, s->stream),
            "init_adjoint launch");
-    LB_HIP(lbm::launch_finalize(s->partials, s->npartials, g_eps, s->stream), "finalize");
+    // eps = nu dt / dx^2, so dL/dnu = (dt / dx^2) dL/deps
+    const double nu_scale = s->cfg.dt / (s->cfg.dx * s->cfg.dx);
+    LB_HIP(lbm::launch_finalize(s->partials, s->npartials, g_eps, s->stream, g_nu, nu_scale),
+           "finalize");
     return LB_OK;
 }
 
@@ -989,7 +998,8 @@ lb_status lb_batch_macro(lb_batch* b, double* theta, double* u) {
         Geo g = make_geo(&b->cfgs[i]);
         const int64_t no = b->node_offsets[i];
         LB_HIP(lbm::launch_macro(2, g, b->insts[i].r, b->pool[b->cur] + b->offsets[i],
-                                 theta ? theta + no : nullptr, u ? u + 2 * no : nullptr, b->stream),
+                                 theta ? theta + no : nullptr, u ? u + 2 * no : nullptr, nullptr,
+                                 b->stream),
                "batch macro launch");
     }
     return LB_OK;

@@ -78,15 +78,16 @@ hipError_t launch_step_resident1(const Geo& g, const Rates& r, const double* src
 hipError_t launch_step_wall1(const Geo& g, const Rates& r, const double* src, double* dst,
                              const double* wall, hipStream_t st);
 hipError_t launch_macro_wall1(const Geo& g, const Rates& r, const double* state, double* theta,
-                              double* u, const double* wall, hipStream_t st);
+                              double* u, double* grad, const double* wall, hipStream_t st);
 hipError_t launch_get_state_wall1(const Geo& g, const double* state, double* dense,
                                   const double* wall, hipStream_t st);
 hipError_t launch_wall_from_dense1(const Geo& g, const double* dense, double* wall,
                                    hipStream_t st);
 hipError_t launch_init(int d, const Geo& g, const Rates& r, const double* theta0,
                        const double* grad, double* dst, hipStream_t st);
+// theta (V), u (d x V) and grad theta (d x V) at the state; any may be NULL.
 hipError_t launch_macro(int d, const Geo& g, const Rates& r, const double* state, double* theta,
-                        double* u, hipStream_t st);
+                        double* u, double* grad, hipStream_t st);
 hipError_t launch_get_state(int d, const Geo& g, const double* state, double* dense,
                             hipStream_t st);
 hipError_t launch_set_state(int d, const Geo& g, const double* dense, double* state,
@@ -115,7 +116,9 @@ hipError_t launch_adjoint_step(int d, const Geo& g, const Rates& r, const double
 hipError_t launch_init_adjoint(int d, const Geo& g, const Rates& r, const double* theta0,
                                const double* grad, const double* lambda0, double* g_theta0,
                                double* g_grad, double* partials, hipStream_t st);
-hipError_t launch_finalize(const double* partials, int64_t n, double* g_eps, hipStream_t st);
+// With g_nu != NULL it then also writes *g_nu = nu_scale * *g_eps.
+hipError_t launch_finalize(const double* partials, int64_t n, double* g_eps, hipStream_t st,
+                           double* g_nu = nullptr, double nu_scale = 0.0);
 // nsteps (2 or 4) D2Q9 adjoint steps in one pass: lam_out = lambda^{N-nsteps}
 // from lam_in = lambda^N, with f^{N-j} at ftop - (j-1) stride; writes a table of
 // exactly ntab eps partials (ntab >= adjoint_steps_table(g)).  lam_out is

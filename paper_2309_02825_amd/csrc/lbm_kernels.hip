@@ -150,9 +150,11 @@ __global__ void __launch_bounds__(256) k_step(const double* __restrict__ src,
 // With walls != NULL the interval is bounded (wall_pull1): step s forms the
 // distribution of the time whose boundary theta is wall_now (s = 0) or
 // walls[2(s-1) .. 2(s-1)+1]; at the end wall_now takes the last pair.
+// src and dst may be the same buffer (an even step count ends where it
+// started): every load of src happens before the first store to dst, so the
+// pointers carry no __restrict__.
 template <int T, int PER>
-__global__ void __launch_bounds__(T) k_step_resident1(const double* __restrict__ src,
-                                                      double* __restrict__ dst, int n,
+__global__ void __launch_bounds__(T) k_step_resident1(const double* src, double* dst, int n,
                                                       int64_t nsteps, Rates r,
                                                       const double* __restrict__ walls,
                                                       double* __restrict__ wall_now) {
@@ -230,10 +232,11 @@ __global__ void __launch_bounds__(256) k_step_wall1(const double* __restrict__ s
     for (int i = 0; i < 3; ++i) __builtin_nontemporal_store(f[i], dst + slot<3>(i, x));
 }
 
-// theta and u as k_macro<1>, from the bounded-interval distribution.
+// theta, u and grad theta as k_macro<1>, from the bounded-interval distribution.
 __global__ void __launch_bounds__(256) k_macro_wall1(const double* __restrict__ src,
                                                      double* __restrict__ theta,
-                                                     double* __restrict__ u, int n, Rates r,
+                                                     double* __restrict__ u,
+                                                     double* __restrict__ grad, int n, Rates r,
                                                      const double* __restrict__ wall) {
     const int x = (int)(blockIdx.x * blockDim.x + threadIdx.x);
     if (x >= n) return;
@@ -243,12 +246,12 @@ __global__ void __launch_bounds__(256) k_macro_wall1(const double* __restrict__ 
 #pragma unroll
     for (int i = 0; i < 3; ++i) th += f[i];
     if (theta) theta[x] = th;
-    if (u) {
-        const double inv = r.ucoef / th;
+    if (u || grad) {
         double j = 0.0;
 #pragma unroll
         for (int i = 0; i < 3; ++i) j = LBM_SADD(j, Lat<1>::E[i][0], f[i]);
-        u[x] = j * inv;
+        if (u) u[x] = j * (r.ucoef / th);
+        if (grad) grad[x] = r.gcoef * j;
     }
 }
 
@@ -340,9 +343,10 @@ __device__ __forceinline__ double lane_rotate(double x) {
 // nodes then take the wall rule of wall_pull1).  No LDS and no barrier; the
 // arithmetic is that of k_step<1> / k_step_resident1.
 // ---------------------------------------------------------------------------
+// src and dst may be the same buffer, as for k_step_resident1.
 template <int PER, bool PERIODIC>
-__global__ void __launch_bounds__(64) k_step_wave1(const double* __restrict__ src,
-                                                   double* __restrict__ dst, int n, int64_t nsteps,
+__global__ void __launch_bounds__(64) k_step_wave1(const double* src, double* dst, int n,
+                                                   int64_t nsteps,
                                                    Rates r, const double* __restrict__ walls,
                                                    double* __restrict__ wall_now) {
     const int lane = threadIdx.x;
@@ -960,10 +964,13 @@ __global__ void __launch_bounds__(256) k_init(const double* __restrict__ th0,
 // ---------------------------------------------------------------------------
 // macroscopic output, state conversions
 // ---------------------------------------------------------------------------
+// theta = sum f, u_a = (2 - s1) c j_a / theta and grad_a theta = -(3 s1/dx) j_a
+// with j_a = sum_i e_{ia} f_i (Sec. III.C; sum_i e_i w_i = 0, so j needs no
+// equilibrium subtracted).  Any of the three outputs may be NULL.
 template <int D>
 __global__ void __launch_bounds__(256) k_macro(const double* __restrict__ src,
                                                double* __restrict__ theta, double* __restrict__ u,
-                                               Geo g, Rates r) {
+                                               double* __restrict__ grad, Geo g, Rates r) {
     constexpr int Q = Lat<D>::Q;
     int c[4];
     if (!thread_node<D>(g, c)) return;
@@ -976,14 +983,15 @@ __global__ void __launch_bounds__(256) k_macro(const double* __restrict__ src,
     for (int i = 0; i < Q; ++i) th += f[i];
     const int k = node_index(g, c);
     if (theta) theta[k] = th;
-    if (u) {
+    if (u || grad) {
         const double inv = r.ucoef / th;
 #pragma unroll
         for (int a = 0; a < D; ++a) {
             double j = 0.0;
 #pragma unroll
             for (int i = 0; i < Q; ++i) j = LBM_SADD(j, Lat<D>::E[i][a], f[i]);
-            u[(int64_t)a * g.V + k] = j * inv;
+            if (u) u[(int64_t)a * g.V + k] = j * inv;
+            if (grad) grad[(int64_t)a * g.V + k] = r.gcoef * j;
         }
     }
 }
@@ -1218,12 +1226,18 @@ __global__ void __launch_bounds__(256) k_init_adjoint(const double* __restrict__
     if (threadIdx.x == 0 && threadIdx.y == 0) partials[block_linear()] = s;
 }
 
+// *g_eps += sum of the partials; then, if g_nu != NULL, *g_nu = nu_scale * *g_eps
+// (dL/dnu = (dt/dx^2) dL/deps, since eps = nu dt/dx^2).
 __global__ void __launch_bounds__(256) k_finalize(const double* __restrict__ partials, int64_t n,
-                                                  double* g_eps) {
+                                                  double* g_eps, double* g_nu, double nu_scale) {
     double v = 0.0;
     for (int64_t i = threadIdx.x; i < n; i += 256) v += partials[i];
     const double s = block_sum(v);
-    if (threadIdx.x == 0) *g_eps += s;
+    if (threadIdx.x == 0) {
+        const double ge = *g_eps + s;
+        *g_eps = ge;
+        if (g_nu) *g_nu = nu_scale * ge;
+    }
 }
 
 // The reductions of k_finalize for m tables: block j sums table j with the
@@ -1600,10 +1614,10 @@ hipError_t launch_step_wall1(const Geo& g, const Rates& r, const double* src, do
 }
 
 hipError_t launch_macro_wall1(const Geo& g, const Rates& r, const double* state, double* theta,
-                              double* u, const double* wall, hipStream_t st) {
+                              double* u, double* grad, const double* wall, hipStream_t st) {
     if (g.nx < 2 || g.ny != 1 || g.nz != 1 || g.nw != 1 || !wall) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_macro_wall1, grid_1d(g.nx), dim3(256), 0, st, state, theta, u, g.nx, r,
-                       wall);
+    hipLaunchKernelGGL(k_macro_wall1, grid_1d(g.nx), dim3(256), 0, st, state, theta, u, grad, g.nx,
+                       r, wall);
     return hipGetLastError();
 }
 
@@ -1801,8 +1815,8 @@ hipError_t launch_init(int d, const Geo& g, const Rates& r, const double* theta0
 }
 
 hipError_t launch_macro(int d, const Geo& g, const Rates& r, const double* state, double* theta,
-                        double* u, hipStream_t st) {
-    return LBM_LAUNCH(k_macro, state, theta, u, g, r);
+                        double* u, double* grad, hipStream_t st) {
+    return LBM_LAUNCH(k_macro, state, theta, u, grad, g, r);
 }
 
 hipError_t launch_get_state(int d, const Geo& g, const double* state, double* dense,
@@ -1878,8 +1892,9 @@ hipError_t launch_init_adjoint(int d, const Geo& g, const Rates& r, const double
     return LBM_LAUNCH(k_init_adjoint, theta0, grad, lambda0, g_theta0, g_grad, partials, g, r);
 }
 
-hipError_t launch_finalize(const double* partials, int64_t n, double* g_eps, hipStream_t st) {
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, st, partials, n, g_eps);
+hipError_t launch_finalize(const double* partials, int64_t n, double* g_eps, hipStream_t st,
+                           double* g_nu, double nu_scale) {
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, st, partials, n, g_eps, g_nu, nu_scale);
     return hipGetLastError();
 }
 

@@ -39,6 +39,7 @@ struct Rates {
     double one_m_s1, one_m_s21, one_m_s22;
     double R4wd;             // 4 w_d (equilibrium of the c_a^2 c_b^2 moments per theta)
     double ucoef;            // (2 - s1) dx / dt
+    double gcoef;            // -3 s1 / dx: grad theta = gcoef * sum_i e_i f_i (c_s^2 = c^2/3)
     double dx;               // node spacing
     double inv_s1_m1;        // 1/s1 - 1
     double inv12dx;          // 1 / (12 dx)

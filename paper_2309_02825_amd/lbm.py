@@ -84,15 +84,15 @@ def _load():
         "lb_step_buffers": ([_vp, _vp, _vp], st),
         "lb_current_state": ([_vp], _vp),
         "lb_steps_taken": ([_vp], I64),
-        "lb_macro": ([_vp, _vp, _vp], st),
-        "lb_macro_buffer": ([_vp, _vp, _vp, _vp], st),
+        "lb_macro": ([_vp, _vp, _vp, _vp], st),
+        "lb_macro_buffer": ([_vp, _vp, _vp, _vp, _vp], st),
         "lb_get_state": ([_vp, _vp], st),
         "lb_set_state": ([_vp, _vp, I64], st),
         "lb_theta_from_velocity": ([_vp, _vp, _vp, _vp], st),
         "lb_macro_adjoint": ([_vp, _vp, _vp, _vp, _vp, _vp], st),
         "lb_adjoint_step": ([_vp, _vp, _vp, _vp, _vp], st),
         "lb_adjoint_segment": ([_vp, _vp, I64, _vp, _vp, _vp, _vp], st),
-        "lb_init_adjoint": ([_vp, _vp, _vp, _vp, _vp, _vp, _vp], st),
+        "lb_init_adjoint": ([_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp], st),
         "lb_destroy": ([_vp], st),
         "lb_batch_layout": ([_cp, I32, _vp, _vp], I64),
         "lb_batch_create": ([_cp, I32, _vp, _vp, _vp, ctypes.POINTER(_vp)], st),
@@ -198,12 +198,12 @@ def lb_steps_taken(h: int) -> int:
     return _load().lb_steps_taken(h)
 
 
-def lb_macro(h: int, theta=None, u=None):
-    _check(_load().lb_macro(h, _ptr(theta), _ptr(u)))
+def lb_macro(h: int, theta=None, u=None, grad_theta=None):
+    _check(_load().lb_macro(h, _ptr(theta), _ptr(u), _ptr(grad_theta)))
 
 
-def lb_macro_buffer(h: int, state, theta=None, u=None):
-    _check(_load().lb_macro_buffer(h, _ptr(state), _ptr(theta), _ptr(u)))
+def lb_macro_buffer(h: int, state, theta=None, u=None, grad_theta=None):
+    _check(_load().lb_macro_buffer(h, _ptr(state), _ptr(theta), _ptr(u), _ptr(grad_theta)))
 
 
 def lb_get_state(h: int, f_out):
@@ -240,9 +240,9 @@ def lb_adjoint_segment(h: int, ckpt, m: int, work, lam, lam_tmp, g_eps):
                                       _ptr(lam_tmp), _ptr(g_eps)))
 
 
-def lb_init_adjoint(h: int, theta0, grad, lam0, g_theta0, g_grad, g_eps):
+def lb_init_adjoint(h: int, theta0, grad, lam0, g_theta0, g_grad, g_eps, g_nu=None):
     _check(_load().lb_init_adjoint(h, _ptr(theta0), _ptr(grad), _ptr(lam0), _ptr(g_theta0),
-                                   _ptr(g_grad), _ptr(g_eps)))
+                                   _ptr(g_grad), _ptr(g_eps), _ptr(g_nu)))
 
 
 def lb_destroy(h: int):

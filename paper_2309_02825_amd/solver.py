@@ -140,15 +140,20 @@ class Solver:
         ptr = L.lb_current_state(self.h)
         return self.bufs[0] if ptr == self.bufs[0].data_ptr() else self.bufs[1]
 
-    def macro(self, state: Optional[torch.Tensor] = None):
+    def macro(self, state: Optional[torch.Tensor] = None, with_grad: bool = False):
+        """(theta, u) at the current time (or of ``state``); with
+        ``with_grad=True`` (theta, u, grad theta), the gradient read from the
+        non-equilibrium first moment (Sec. III.C)."""
         theta = torch.empty(self.shape, dtype=F64, device=self.device)
         u = torch.empty((self.d,) + self.shape, dtype=F64, device=self.device)
+        grad = (torch.empty((self.d,) + self.shape, dtype=F64, device=self.device)
+                if with_grad else None)
         if state is None:
-            L.lb_macro(self.h, theta, u)
+            L.lb_macro(self.h, theta, u, grad)
         else:
             state = _buffer(state, self.state_elems, self.device, "state")
-            L.lb_macro_buffer(self.h, state, theta, u)
-        return theta, u
+            L.lb_macro_buffer(self.h, state, theta, u, grad)
+        return (theta, u, grad) if with_grad else (theta, u)
 
     def get_state(self) -> torch.Tensor:
         out = torch.empty((self.q,) + self.shape, dtype=F64, device=self.device)
@@ -206,16 +211,20 @@ class Solver:
         g_eps = _buffer(g_eps, 1, self.device, "g_eps") if g_eps is not None else None
         L.lb_adjoint_segment(self.h, ckpt, m, work, lam, lam_tmp, g_eps)
 
-    def init_adjoint(self, theta0, grad, lam0, g_eps, want_grad: bool = False):
+    def init_adjoint(self, theta0, grad, lam0, g_eps, want_grad: bool = False, g_nu=None):
+        """Adjoint of init: returns (dL/dtheta0, dL/dgrad or None).  If ``g_nu``
+        (one device double) is given, the library writes dL/dnu into it from
+        the accumulated ``g_eps``."""
         theta0 = _field(theta0, self.shape, self.device, "theta0")
         if grad is not None:
             grad = _field(grad, (self.d,) + self.shape, self.device, "grad")
         lam0 = _buffer(lam0, self.state_elems, self.device, "lam0")
         g_eps = _buffer(g_eps, 1, self.device, "g_eps") if g_eps is not None else None
+        g_nu = _buffer(g_nu, 1, self.device, "g_nu") if g_nu is not None else None
         g_theta0 = torch.empty(self.shape, dtype=F64, device=self.device)
         g_grad = (torch.empty((self.d,) + self.shape, dtype=F64, device=self.device)
                   if (grad is not None and want_grad) else None)
-        L.lb_init_adjoint(self.h, theta0, grad, lam0, g_theta0, g_grad, g_eps)
+        L.lb_init_adjoint(self.h, theta0, grad, lam0, g_theta0, g_grad, g_eps, g_nu)
         return g_theta0, g_grad
 
 
@@ -293,8 +302,9 @@ class VelocityFunction(torch.autograd.Function):
         for k in range(len(starts) - 1, -1, -1):
             s.adjoint_segment(ctx.ckpts[k], ends[k] - starts[k], work, lam, lam_other, g_eps)
         del work
-        g_theta0, _ = s.init_adjoint(theta0, None, lam, g_eps)
-        g_nu = g_eps.reshape(()) * (ctx.dt / (ctx.dx * ctx.dx))
+        g_nu = torch.empty(1, dtype=F64, device=theta0.device)
+        g_theta0, _ = s.init_adjoint(theta0, None, lam, g_eps, g_nu=g_nu)
+        g_nu = g_nu.reshape(())
         s.close()
         ctx.solver = None
         ctx.ckpts = None

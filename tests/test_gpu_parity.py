@@ -45,19 +45,48 @@ def max_rel(a, b):
     return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
 
 
-def _gpu_run(grid, dx, dt, nu, theta0, grad, nsteps, want_f=True):
+def _gpu_run(grid, dx, dt, nu, theta0, grad, nsteps, want_f=True, want_grad=False):
     SV = _solver_mod()
     s = SV.Solver(grid, dx, dt, nu, device=_dev())
     th0 = torch.from_numpy(np.ascontiguousarray(theta0)).to(_dev())
     gr = None if grad is None else torch.from_numpy(np.ascontiguousarray(grad)).to(_dev())
     s.init(th0, gr)
     s.step(nsteps)
-    th, u = s.macro()
+    th, u, g = s.macro(with_grad=True)
     f = s.get_state() if want_f else None
     torch.cuda.synchronize()
     out = (th.cpu().numpy(), u.cpu().numpy(), None if f is None else f.cpu().numpy())
+    if want_grad:
+        out = out + (g.cpu().numpy(),)
     s.close()
     return out
+
+
+def _roundoff_scales(f, dx, dt, nu):
+    """Per-node scales of the rounding in u and grad theta.  Both are a first
+    moment j = sum_i e_i f_i divided or multiplied by a coefficient, and j is
+    a difference of populations of size |f|: u = (2 - s1) c j / theta rounds
+    to about eps_mach (2 - s1) c sum|f| / theta, and grad theta = -(3 s1/dx) j
+    to about eps_mach (3 s1/dx) sum|f|, however small u itself has become."""
+    d = f.ndim - 1
+    s1 = O.lattice(d, nu * dt / dx ** 2).s[1]
+    af = np.abs(f).sum(axis=0)
+    th = f.sum(axis=0)
+    return (2 - s1) * (dx / dt) * af / th, 3 * s1 / dx * af
+
+
+def _assert_moment_close(got, ref, scale, what):
+    """Per node and component: |got - ref| <= TOL_U |ref_a|_inf + TOL_F scale.
+    The first term is the norm-wise 1e-11 bound; the second admits rounding
+    at the level the f bound (1e-13) allows, which dominates only once the
+    field has decayed to near its rounding scale (e.g. Example 3 at t = 2,
+    |u| ~ 4e-8 against populations of O(1))."""
+    umax = np.max(np.abs(ref))
+    for a in range(ref.shape[0]):
+        den = max(np.max(np.abs(ref[a])), 1e-3 * umax)
+        err = np.abs(got[a] - ref[a])
+        bound = TOL_U * den + TOL_F * scale
+        assert np.all(err <= bound), (what, a, float(np.max(err / bound)))
 
 
 CASES = [
@@ -72,11 +101,11 @@ CASES = [
     ("2d_degenerate_7x1", (7, 1), 9, "random"),
     ("2d_ex2_level0", (40, 40), 100, "ex2"),
     ("3d_ragged_20x17x9", (20, 17, 9), 25, "random"),
-    ("3d_ex3_level0", (20, 20, 20), 10, "ex3"),
+    ("3d_ex3_level0", (20, 20, 20), 50, "ex3"),
     ("3d_cos_33x5x4", (33, 5, 4), 12, "cos"),
     ("4d_ragged_6x5x4x7", (6, 5, 4, 7), 9, "random"),
     ("4d_cos_9x5x6x5", (9, 5, 6, 5), 5, "cos"),
-    ("4d_ex4_level0", (20, 20, 20, 20), 8, "ex4"),
+    ("4d_ex4_level0", (20, 20, 20, 20), 40, "ex4"),
 ]
 
 
@@ -118,17 +147,17 @@ def test_parity_with_direct_oracle(name, grid, nsteps, kind):
     grad_o = g0 if g0 is not None else O.grad_fd4(th0, dx)
     f_o = O.run(O.init(th0, grad_o, dx, dt, nu), dx, dt, nu, nsteps)
     th_o, u_o = O.macro(f_o, dx, dt, nu)
-    th_g, u_g, f_g = _gpu_run(grid, dx, dt, nu, th0, g0, nsteps)
+    g_o = O.grad_theta(f_o, dx, dt, nu)
+    th_g, u_g, f_g, g_g = _gpu_run(grid, dx, dt, nu, th0, g0, nsteps, want_grad=True)
     print(f"[gpu-case] {name}: f {max_rel(f_g, f_o):.2e} theta {max_rel(th_g, th_o):.2e} "
-          f"u {max_rel(u_g, u_o):.2e}", flush=True)
+          f"u {max_rel(u_g, u_o):.2e} grad {max_rel(g_g, g_o):.2e}", flush=True)
     assert max_rel(f_g, f_o) <= TOL_F, name
     assert max_rel(th_g, th_o) <= TOL_THETA, name
-    # per component; a component that vanishes identically (an axis with one
-    # node) holds only round-off and is measured against the whole field
-    umax = np.max(np.abs(u_o))
-    for a in range(len(grid)):
-        den = max(np.max(np.abs(u_o[a])), 1e-3 * umax)
-        assert np.max(np.abs(u_g[a] - u_o[a])) <= TOL_U * den, (name, a)
+    # per component (a component that vanishes identically, an axis with one
+    # node, is measured against the whole field) with the rounding floor
+    su, sg = _roundoff_scales(f_o, dx, dt, nu)
+    _assert_moment_close(u_g, u_o, su, (name, "u"))
+    _assert_moment_close(g_g, g_o, sg, (name, "grad theta"))
 
 
 @pytest.mark.parametrize("seed", range(12))
@@ -442,10 +471,14 @@ def test_fourth_order_convergence_on_gpu():
     for n in (16, 32, 64, 128):
         wl = W.heat_1d(n)
         th0, g0 = W.evaluate(wl.modes, wl.grid, wl.dx)
-        th, u, _ = _gpu_run(wl.grid, wl.dx, wl.dt, wl.nu, th0, g0, wl.nsteps, want_f=False)
+        th, u, _, g = _gpu_run(wl.grid, wl.dx, wl.dt, wl.nu, th0, g0, wl.nsteps, want_f=False,
+                               want_grad=True)
         te, ue = W.exact(wl, wl.nsteps * wl.dt)
-        errs.append((np.sqrt(np.mean((th - te) ** 2)), np.sqrt(np.mean((u - ue) ** 2))))
-    for v in range(2):
+        _, ge = W.evaluate(W.decay_modes(wl.modes, wl.grid, wl.dx, wl.nu, wl.nsteps * wl.dt),
+                           wl.grid, wl.dx)
+        errs.append((np.sqrt(np.mean((th - te) ** 2)), np.sqrt(np.mean((u - ue) ** 2)),
+                     np.sqrt(np.mean((g - ge) ** 2))))
+    for v in range(3):
         crs = [math.log2(errs[i][v] / errs[i + 1][v]) for i in range(3)]
         assert all(3.85 < c < 4.15 for c in crs), crs
 
@@ -467,8 +500,13 @@ def _full_size_case(wl, nsteps, count=20000):
     th0, g0 = W.evaluate(wl.modes, wl.grid, wl.dx, xp=torch, device=_dev())
     s.init(th0, g0)
     s.step(nsteps)
-    th, u = s.macro()
+    th, u, g = s.macro(with_grad=True)
     torch.cuda.synchronize()
+    # Cole-Hopf identity between the two outputs at every node: both come
+    # from the same first moment, so they agree to a few ulp of u
+    uc = -2.0 * wl.nu * g / th[None]
+    assert float(torch.max(torch.abs(uc - u) / (torch.abs(u) + 1e-300 + 1e-3 * torch.abs(u).max()))) < 1e-13
+    del uc, g
     pts = _sample_points(wl.grid, count, 99)
     idx = tuple(torch.as_tensor(pts[:, a], device=_dev()) for a in reversed(range(wl.d)))
     th_s = th[idx].cpu().numpy()
@@ -509,18 +547,20 @@ def _bounded_gpu(wl, th0, g0, walls, chunks=None, want_f=False):
     for n in (chunks or [walls.shape[0]]):
         s.step_bounded(w[done:done + n].contiguous())
         done += n
-    th, u = s.macro()
+    th, u, g = s.macro(with_grad=True)
     f = s.get_state() if want_f else None
     torch.cuda.synchronize()
     out = (th.cpu().numpy(), u.cpu().numpy(), None if f is None else f.cpu().numpy())
     assert s.steps == walls.shape[0]
     s.close()
+    _bounded_gpu.last_grad = g.cpu().numpy()
     return out
 
 
 def _bounded_oracle(wl, th0, g0, walls):
     f = O.run_dirichlet1(O.init(th0, g0, wl.dx, wl.dt, wl.nu), wl.dx, wl.dt, wl.nu, walls)
     th, u = O.macro(f, wl.dx, wl.dt, wl.nu)
+    _bounded_oracle.last_grad = O.grad_theta(f, wl.dx, wl.dt, wl.nu)
     return th, u, f
 
 
@@ -537,6 +577,7 @@ def test_bounded_example1_matches_oracle(eps, level):
     th_o, u_o, _ = _bounded_oracle(wl, th0, g0, walls)
     assert max_rel(th_g, th_o) <= TOL_THETA
     assert max_rel(u_g[0], u_o[0]) <= TOL_U
+    assert max_rel(_bounded_gpu.last_grad, _bounded_oracle.last_grad) <= TOL_U
     x = np.arange(wl.grid[0]) * wl.dx
     te, ue = W.example1_exact(wl.nu, x, wl.nsteps * wl.dt)
     printed = {r[0]: r[2] for r in read_table("table1.txt") if r[1] == "theta"}[eps][level]
