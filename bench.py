@@ -40,6 +40,21 @@ KERNEL_SOURCES = [os.path.join(ROOT, "paper_2309_02825_amd", "csrc", n)
                   for n in ("lbm_kernels.hip", "lbm_lattice.h", "lbm_kernels.h")]
 
 
+def pass_roofline(d: int, nodes: int, steps_per_launch: int, us_per_step: float) -> dict:
+    """Roofline of one launch of a pass kernel.  A pass reads the q
+    populations of every node once and writes them once, whatever the number
+    of time steps it advances: 2 q 8 bytes per node and pass are its
+    algorithmic bytes, so `frac` is a true fraction of the HBM peak.  The
+    per-update figure (2 q 8 bytes per lattice update, what a one-step pass
+    would move for the same updates) is kept as `lu_equivalent_gbs`."""
+    launch_s = us_per_step * steps_per_launch * 1e-6
+    pass_bytes = BYTES_PER_LU[d] * nodes
+    gbs = pass_bytes / launch_s / 1e9
+    return {"bytes_per_launch": pass_bytes, "kernel_us_per_launch": round(launch_s * 1e6, 3),
+            "achieved_gbs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
+            "lu_equivalent_gbs": round(gbs * steps_per_launch, 1)}
+
+
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
@@ -267,72 +282,173 @@ def form_batched(torch, SV, W, dev):
     nodes = bs.total_nodes
     bs.close()
     mlups = nodes * 1000 / (ms / 1e3) / 1e6
+    # launches of the graph: passes of S steps in a mode (-S, rows) or
+    # (-16-S, rows), the remainder as single steps; each launch reads and
+    # writes every instance's state once (144 B per node)
+    S = (-tile[0] - 16 if tile[0] < -16 else -tile[0]) if tile[0] < 0 else 1
+    launches = 1000 // S + 1000 % S
+    pass_bytes = 144 * nodes
+    gbs = launches * pass_bytes / (ms / 1e3) / 1e9
     return {"instances": len(insts), "total_nodes": nodes, "lb_steps": 1000,
             "launch": "one hipGraph of tile-table kernels (S steps per launch for tile "
-                      "(-S, rows))", "tile": list(tile),
-            "graph_ms": round(ms, 3), "wall_s": round(wall, 4), "mlups": round(mlups, 1),
-            "gbs_algorithmic": round(mlups * 144 / 1e3, 1)}
+                      "(-S, rows))", "tile": list(tile), "lb_steps_per_launch": S,
+            "launches": launches, "graph_ms": round(ms, 3), "wall_s": round(wall, 4),
+            "mlups": round(mlups, 1), "bytes_per_launch": pass_bytes,
+            "achieved_gbs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
+            "lu_equivalent_gbs": round(mlups * 144 / 1e3, 1)}
 
 
-def form_adjoint(torch, SV, W, dev):
-    tgt, gue = W.adjoint_problem()
+def adjoint_backward_bytes(V: int, starts, nsteps: int, spp: int = D2_STEPS_PER_PASS,
+                           max_reverse: int = 4) -> int:
+    """Algorithmic HBM bytes of the D2Q9 backward sweep (one node's 9
+    populations are 72 B), following the launch plan of lb_adjoint_segment:
+    a recomputation pass of S steps reads its input state once and writes
+    all S states; a reverse pass of S steps reads and writes lambda once and
+    reads the S states it needs; single steps move three states.  The seed
+    (lb_macro_adjoint: state and g_u read, lambda written) and the adjoint of
+    the initialisation (lambda read, theta0 read, g_theta0 written) are
+    included."""
+    st = 72 * V
+    total = st + 16 * V + st
+    ends = list(starts[1:]) + [nsteps]
+    for b, e in zip(starts, ends):
+        m = e - b
+        j = 1
+        p = spp
+        while p >= 2:
+            while j + p <= m:
+                total += st * (1 + p)
+                j += p
+            p //= 2
+        total += 2 * st * max(m - j, 0)
+        left = m - 1
+        plan = []
+        p = min(spp, max_reverse)
+        while p >= 1:
+            while left >= p:
+                plan.append(p)
+                left -= p
+            p //= 2
+        plan.append(1)
+        for p in plan:
+            total += 3 * st if p == 1 else st * (2 + p)
+    total += st + 2 * 8 * V
+    return total
+
+
+def form_adjoint(torch, SV, W, dev, n: int = 512, lb_steps: int = 2000):
+    """Differentiable u(T) at n x n (nu = 0.02, eps = 0.2, lb_steps steps,
+    sqrt(T) checkpoints): the forward alone and forward + backward, timed with
+    HIP events on the stream the library launches on; the backward's
+    algorithmic bytes give its bandwidth and HBM fraction."""
+    tgt, gue = W.adjoint_problem(n=n, nsteps=lb_steps)
     dx, dt, nu, N = gue.dx, gue.dt, gue.nu, gue.nsteps
     th_t, _ = W.evaluate(tgt.modes, tgt.grid, tgt.dx, xp=torch, device=dev, with_grad=False)
     th0, _ = W.evaluate(gue.modes, gue.grid, gue.dx, xp=torch, device=dev, with_grad=False)
     nu_t = torch.tensor(nu, dtype=torch.float64, device=dev)
     with torch.no_grad():
         u_target = SV.velocity(th_t, nu_t, gue.grid, dx, dt, N)
+    stream = torch.cuda.current_stream()
 
     def fwd_only():
         with torch.no_grad():
             return SV.velocity(th0, nu_t, gue.grid, dx, dt, N)
 
-    def fwd_bwd():
+    def fwd_bwd(tb=None):
         a = th0.clone().requires_grad_(True)
         b = nu_t.clone().requires_grad_(True)
         u = SV.velocity(a, b, gue.grid, dx, dt, N)
         loss = ((u - u_target) ** 2).sum()
+        if tb:
+            tb.start()
         loss.backward()
+        if tb:
+            tb.stop()
         return loss, a.grad, b.grad
 
     fwd_only()
     fwd_bwd()
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
+    tf = Timer(torch, stream)
+    tf.start()
     fwd_only()
+    tf.stop()
+    tfb, tb = Timer(torch, stream), Timer(torch, stream)
+    tfb.start()
+    loss, g_th, g_nu = fwd_bwd(tb)
+    tfb.stop()
     torch.cuda.synchronize()
-    t_f = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    loss, g_th, g_nu = fwd_bwd()
-    torch.cuda.synchronize()
-    t_fb = time.perf_counter() - t0
+    t_f, t_fb, t_b = tf.total_ms() / 1e3, tfb.total_ms() / 1e3, tb.total_ms() / 1e3
     V = gue.nodes
-    return {"grid": list(gue.grid), "lb_steps": N, "checkpoints": len(SV.checkpoint_segments(N)),
-            "forward_s": round(t_f, 4), "forward_backward_s": round(t_fb, 4),
-            "backward_over_forward": round((t_fb - t_f) / t_f, 3),
+    starts = SV.checkpoint_segments(N)
+    bwd_bytes = adjoint_backward_bytes(V, starts, N)
+    bwd_gbs = bwd_bytes / t_b / 1e9
+    return {"grid": list(gue.grid), "lb_steps": N, "checkpoints": len(starts),
+            "timing": "HIP events on the launch stream",
+            "forward_s": round(t_f, 5), "forward_backward_s": round(t_fb, 5),
+            "backward_s": round(t_b, 5),
+            "backward_over_forward": round(t_b / t_f, 3),
             "mlups_forward": round(V * N / t_f / 1e6, 1),
+            "backward_algorithmic_bytes": bwd_bytes,
+            "backward_bytes_per_node_step": round(bwd_bytes / (V * N), 1),
+            "backward_achieved_gbs": round(bwd_gbs, 1),
+            "backward_frac": round(bwd_gbs / HBM_PEAK_GBS, 4),
             "loss": float(loss.item()), "dL_dnu": float(g_nu.item()),
             "grad_theta0_norm": float(g_th.norm().item())}
 
 
-def cpu_baseline(wl, budget_s: float = 12.0):
-    import numpy as np  # noqa: F401
-    from oracle import oracle as O
-    from paper_2309_02825_amd import workloads as W
-    th0, g0 = W.evaluate(wl.modes, wl.grid, wl.dx)
-    f = O.init(th0, g0, wl.dx, wl.dt, wl.nu)
+def host_cpu():
+    """CPU model (from /proc/cpuinfo) and the logical CPUs this process may use."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count()
+    return model, avail
+
+
+def _oracle_rate(O, f, wl, budget_s, max_steps):
+    """MLUPS of oracle_run single steps from f until budget_s or max_steps."""
     steps = 0
     t0 = time.perf_counter()
     while True:
         f = O.run(f, wl.dx, wl.dt, wl.nu, 1)
         steps += 1
         el = time.perf_counter() - t0
-        if el >= budget_s or steps >= 50:
+        if el >= budget_s or steps >= max_steps:
             break
-    mlups = wl.nodes * steps / el / 1e6
-    return {"value": round(mlups, 3), "unit": "MLUPS", "cores": O.num_threads(), "kind": "oracle",
+    return wl.nodes * steps / el / 1e6, steps, el
+
+
+def cpu_baseline(wl, budget_s: float = 12.0, budget_1core_s: float = 8.0):
+    """The CPU oracle (C, OpenMP over nodes) on a bounded sample of the
+    workload: all the threads OpenMP gives it, then one thread."""
+    import numpy as np  # noqa: F401
+    from oracle import oracle as O
+    from paper_2309_02825_amd import workloads as W
+    th0, g0 = W.evaluate(wl.modes, wl.grid, wl.dx)
+    f = O.init(th0, g0, wl.dx, wl.dt, wl.nu)
+    cores = O.num_threads()
+    mlups, steps, el = _oracle_rate(O, f, wl, budget_s, 50)
+    O.set_threads(1)
+    try:
+        mlups1, steps1, el1 = _oracle_rate(O, f, wl, budget_1core_s, 50)
+    finally:
+        O.set_threads(cores)
+    model, avail = host_cpu()
+    return {"value": round(mlups, 3), "unit": "MLUPS", "cores": cores, "kind": "oracle",
+            "value_1core": round(mlups1, 3), "cpu_model": model, "cpus_available": avail,
             "sample": f"oracle_run (C, OpenMP) on the {wl.name} workload: {steps} of its "
-                      f"{wl.nsteps} time steps, initialisation excluded, {el:.1f} s"}
+                      f"{wl.nsteps} time steps on {cores} threads ({el:.1f} s), then {steps1} "
+                      f"on 1 thread ({el1:.1f} s); initialisation excluded"}
 
 
 def main():
@@ -349,6 +465,10 @@ def main():
     ap.add_argument("--forms", default="all",
                     help="comma-separated subset of the forms to run: steps_per_pass, grids, "
                          "heat1d, example1, batched, adjoint (default all)")
+    ap.add_argument("--adjoint-n", type=int, default=512,
+                    help="side of the adjoint form's square grid (default 512)")
+    ap.add_argument("--adjoint-steps", type=int, default=2000,
+                    help="LB steps of the adjoint form (default 2000)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="first run a plain 1 GiB device copy (reference for HBM counters)")
     args = ap.parse_args()
@@ -384,17 +504,18 @@ def main():
     wall, kms = solve_timed(torch, SV, W, wl, args.steps, args.warmup, dev)
     V = wl.nodes
     mlups = V * wl.nsteps * args.steps / wall / 1e6
-    achieved = BYTES_PER_LU[d] * V / (kms / 1e3) / 1e9
-    log(f"{mlups:.1f} MLUPS, kernel {kms * 1e3:.2f} us/step, {achieved:.1f} GB/s")
     traffic = traffic_for(args.workload, wl.nsteps)
     lattice = {1: "D1Q3", 2: "D2Q9", 3: "D3Q19", 4: "D4Q33"}[d]
-    # D2Q9 runs eight LB steps per launch (temporal blocking); the algorithmic
-    # bytes of a launch are 144 B per lattice update times its 8V updates,
-    # while the pass itself reads and writes the state once (see "traffic")
+    # D2Q9 runs eight LB steps per launch and D3Q19 two (temporal blocking):
+    # a launch reads and writes the state once (2 q 8 bytes per node), which is
+    # what the roofline fraction is taken against
     per_launch = {2: D2_STEPS_PER_PASS, 3: D3_STEPS_PER_PASS}.get(d, 1)
     kernel = {2: d2_kernel(D2_STEPS_PER_PASS, V),
               3: f"k_steps_d3q19<{D3_STEPS_PER_PASS}>"}.get(d, f"k_step<{d}>")
-    launch_us = kms * 1e3 * per_launch
+    pr = pass_roofline(d, V, per_launch, kms * 1e3)
+    launch_us = pr["kernel_us_per_launch"]
+    log(f"{mlups:.1f} MLUPS, kernel {launch_us:.2f} us per launch of {per_launch} steps, "
+        f"{pr['achieved_gbs']:.1f} GB/s ({pr['frac']:.3f} of HBM)")
     rec = {
         "metric": METRIC,
         "value": round(mlups, 1),
@@ -411,12 +532,16 @@ def main():
         "config": {"workload": wl.name, "lattice": lattice, "grid": list(wl.grid),
                    "lb_steps_per_step": wl.nsteps, "nu": wl.nu, "eps": round(wl.eps, 6),
                    "theta0": "2 + prod cos(2 pi x_a)", "parallelism": "single GPU"},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic, "kernel": kernel,
+        "roofline": {"bound": "hbm", "achieved": pr["achieved_gbs"], "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": pr["frac"], "traffic": traffic, "kernel": kernel,
                      "lb_steps_per_launch": per_launch,
-                     "kernel_us_per_launch": round(launch_us, 3),
-                     "bytes_per_lu": BYTES_PER_LU[d],
+                     "kernel_us_per_launch": launch_us,
+                     "algorithmic_bytes_per_launch": pr["bytes_per_launch"],
+                     "algorithmic_unit": f"node-pass: the {2 * {1: 3, 2: 9, 3: 19, 4: 33}[d]} "
+                                         f"populations of a node read and written once",
+                     "lu_equivalent_gbs": pr["lu_equivalent_gbs"],
+                     "traffic_over_algorithmic": (round(traffic / pr["bytes_per_launch"], 4)
+                                                  if traffic else None),
                      "hbm_frac_measured": (round(traffic / (launch_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)
                                            if traffic else None)},
     }
@@ -425,11 +550,6 @@ def main():
         rec["roofline"]["fp64"] = {"flops_per_lu": FLOPS_PER_LU_D2Q9,
                                    "achieved_tflops": round(tf, 2), "peak_tflops": FP64_PEAK_TFLOPS,
                                    "frac": round(tf / FP64_PEAK_TFLOPS, 4)}
-        if per_launch > 1:
-            # measured, not derived: a pass that skipped its halo reads ran no
-            # faster, so HBM bytes do not set its time
-            rec["roofline"]["limit"] = ("instruction issue and latency at two waves per SIMD, "
-                                        "not HBM: fewer bytes per launch do not shorten it")
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         rec["cpu_baseline"] = cpu_baseline(wl)
@@ -449,9 +569,7 @@ def main():
                 sweep[f"steps_per_pass_{spp}"] = {
                     "kernel": "k_step<2>" if spp == 1 else d2_kernel(spp, V),
                     "kernel_us_per_step": round(ms * 1e3, 2), "mlups": round(ml, 1),
-                    "gbs_algorithmic": round(BYTES_PER_LU[2] * ml / 1e3, 1),
-                    "frac": round(BYTES_PER_LU[2] * ml / 1e3 / HBM_PEAK_GBS, 4),
-                    "lb_steps_timed": 400}
+                    "lb_steps_timed": 400, **pass_roofline(2, V, spp, ms * 1e3)}
             forms[wl.name + "_steps_per_pass"] = sweep
             log("steps per pass", sweep)
         for name in ("heat2d_1024", "heat3d_256", "heat3d_512", "heat4d_64", "heat2d_4096_shard8",
@@ -462,21 +580,26 @@ def main():
             n = {2: 2000, 3: 400, 4: 100}[w2.d]
             ms = kernel_only(torch, SV, W, w2, n, dev)
             ml = w2.nodes / (ms / 1e3) / 1e6
-            gbs = BYTES_PER_LU[w2.d] * ml / 1e3
+            spl = {2: D2_STEPS_PER_PASS, 3: D3_STEPS_PER_PASS}.get(w2.d, 1)
             forms[name] = {"lattice": {2: "D2Q9", 3: "D3Q19", 4: "D4Q33"}[w2.d],
                            "kernel": {2: d2_kernel(D2_STEPS_PER_PASS, w2.nodes),
                                       3: f"k_steps_d3q19<{D3_STEPS_PER_PASS}>"}.get(
                                           w2.d, f"k_step<{w2.d}>"),
+                           "lb_steps_per_launch": spl,
                            "kernel_us_per_step": round(ms * 1e3, 2),
-                           "mlups": round(ml, 1), "gbs_algorithmic": round(gbs, 1),
-                           "frac": round(gbs / HBM_PEAK_GBS, 4), "lb_steps_timed": n}
+                           "mlups": round(ml, 1), "lb_steps_timed": n,
+                           **pass_roofline(w2.d, w2.nodes, spl, ms * 1e3)}
+            tr = traffic_for(name, n)
+            if tr:
+                forms[name]["traffic"] = tr
+                forms[name]["traffic_over_algorithmic"] = round(
+                    tr / forms[name]["bytes_per_launch"], 4)
             if w2.d == 3:
                 ms1 = kernel_only(torch, SV, W, w2, n, dev, steps_per_pass=1)
                 ml1 = w2.nodes / (ms1 / 1e3) / 1e6
                 forms[name]["single_step"] = {
                     "kernel": "k_step<3>", "kernel_us_per_step": round(ms1 * 1e3, 2),
-                    "mlups": round(ml1, 1),
-                    "frac": round(BYTES_PER_LU[3] * ml1 / 1e3 / HBM_PEAK_GBS, 4)}
+                    "mlups": round(ml1, 1), **pass_roofline(3, w2.nodes, 1, ms1 * 1e3)}
             log(name, forms[name])
         if want("heat1d"):
             forms["heat1d_sweep"] = form_heat1d(torch, SV, W, dev)
@@ -492,7 +615,7 @@ def main():
             forms["batched"] = b
             log("batched", b)
         if want("adjoint"):
-            a = form_adjoint(torch, SV, W, dev)
+            a = form_adjoint(torch, SV, W, dev, args.adjoint_n, args.adjoint_steps)
             forms["adjoint"] = a
             log("adjoint", a)
         rec["forms"] = forms
