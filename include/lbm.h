@@ -272,6 +272,30 @@ lb_status lb_adjoint_step(lb_solver* s, const double* state_n, const double* lam
 lb_status lb_adjoint_segment(lb_solver* s, const double* ckpt, int64_t m, double* work,
                              double* lambda, double* lambda_tmp, double* g_eps);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * segment as lb_adjoint_segment, with the same arguments and bitwise the
+ * same lambda and *g_eps, but the per-launch partials tables live in a fixed
+ * device array of LB_SEGMENT_SCRATCH_DOUBLES doubles (16 MiB) that the
+ * library declares at file scope, so the call allocates and frees nothing.
+ * Each GPU holds its own copy of that array from the moment the library is
+ * loaded until the process ends; its address on a device is looked up when
+ * a solver is created there.  A segment of m steps needs nt * (T+1)
+ * doubles: on D2Q9 T is the larger of the reverse passes' block count (64-wide
+ * strips times row segments) and the per-node kernels' block count B, and nt
+ * is the number of reverse launches, at most ceil((m-1)/4) + 2 with the
+ * default LB_OPT_STEPS_PER_PASS (m when it is 1); on the other lattices
+ * T = B and nt = m.  A segment needing more returns
+ * LB_ERR_INVALID_ARG before anything is launched (use lb_adjoint_segment or
+ * shorter segments).  Every entry of the tables is written before it is
+ * read, so nothing needs clearing between calls.  All solvers on one GPU
+ * share its array: calls of this function that overlap in time on one GPU
+ * (different host threads, or different streams whose work overlaps) race
+ * and give wrong gradients; serialise them. */
+#define LB_SEGMENT_SCRATCH_DOUBLES (2 * 1024 * 1024)
+lb_status lb_adjoint_segment_static(lb_solver* s, const double* ckpt, int64_t m, double* work,
+                                    double* lambda, double* lambda_tmp, double* g_eps);
+
 /* Adjoint of lb_init: given lambda0 = dL/df^0 (canonical) writes g_theta0 (V).
  * If grad_theta0 != NULL the gradient input was independent and its adjoint
  * is written to g_grad (d x V, may be NULL); if grad_theta0 == NULL the

@@ -6,6 +6,7 @@
 #include <climits>
 #include <cmath>
 #include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <utility>
@@ -155,6 +156,37 @@ int64_t elements_of(const lb_config* c) {
 
 }  // namespace
 
+// Fixed device array behind lb_adjoint_segment_static: the partials tables
+// of one checkpoint segment.  Every GPU the library runs on holds its own
+// copy for the life of the process.  In host code `scratch` names a host-side
+// stand-in, not device memory: its device address comes from
+// hipGetSymbolAddress, taken once per device (scratch_address) and used
+// everywhere host code needs the array.
+static __device__ __align__(256) double scratch[LB_SEGMENT_SCRATCH_DOUBLES];
+
+namespace {
+
+std::mutex g_scratch_mu;
+std::map<int, double*> g_scratch_addr;  // device ordinal -> address of its copy
+
+// Address of the current device's copy of `scratch` (looked up once per device).
+lb_status scratch_address(double** out) {
+    *out = nullptr;
+    int dev = -1;
+    LB_HIP(hipGetDevice(&dev), "hipGetDevice");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    auto it = g_scratch_addr.find(dev);
+    if (it == g_scratch_addr.end()) {
+        void* p = nullptr;
+        LB_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+        it = g_scratch_addr.emplace(dev, static_cast<double*>(p)).first;
+    }
+    *out = it->second;
+    return LB_OK;
+}
+
+}  // namespace
+
 struct lb_solver {
     lb_config cfg;
     int d, q;
@@ -173,6 +205,7 @@ struct lb_solver {
     double* wall_now;    // bounded: theta at the two end nodes at the current time
     double* seg_partials;  // lb_adjoint_segment: one partials table per launch
     int64_t seg_cap;       // doubles seg_partials holds
+    double* scratch;       // this device's copy of `scratch` (lb_adjoint_segment_static)
 };
 
 // Make s->seg_partials hold at least n doubles.
@@ -258,6 +291,14 @@ lb_status lb_create(const lb_config* cfg, void* hip_stream, double* f_a, double*
     s->wall_now = nullptr;
     s->seg_partials = nullptr;
     s->seg_cap = 0;
+    s->scratch = nullptr;
+    // set-up of lb_adjoint_segment_static: the device copy of the scratch
+    // array of the device current at creation (the solver's device)
+    lb_status sst = scratch_address(&s->scratch);
+    if (sst != LB_OK) {
+        delete s;
+        return sst;
+    }
     hipError_t e = hipMalloc((void**)&s->partials, sizeof(double) * (size_t)s->npartials);
     if (e == hipSuccess) e = hipMalloc((void**)&s->flag, sizeof(int));
     if (e == hipSuccess && s->bounded) e = hipMalloc((void**)&s->wall_now, 2 * sizeof(double));
@@ -519,16 +560,41 @@ lb_status lb_adjoint_step(lb_solver* s, const double* state_n, const double* lam
     return LB_OK;
 }
 
-lb_status lb_adjoint_segment(lb_solver* s, const double* ckpt, int64_t m, double* work,
-                             double* lambda, double* lambda_tmp, double* g_eps) {
-    if (!s || !ckpt || !lambda || !lambda_tmp || !g_eps)
-        return fail(LB_ERR_INVALID_ARG, "NULL argument");
-    if (m < 0) return fail(LB_ERR_INVALID_ARG, "m must be >= 0");
-    if (m > 1 && !work) return fail(LB_ERR_INVALID_ARG, "work is NULL");
-    if (lambda == lambda_tmp) return fail(LB_ERR_INVALID_ARG, "lambda == lambda_tmp");
-    lb_status st = not_bounded(s, "the adjoint is periodic only");
-    if (st != LB_OK) return st;
-    if (m == 0) return LB_OK;
+}  // extern "C"
+
+// Launch plan of one checkpoint segment: the reverse passes and the size of
+// the partials tables they write (one table per launch plus one sum each).
+struct SegmentPlan {
+    std::vector<int> reverse;  // D2Q9: adjoint steps per launch, in launch order
+    int64_t T = 0;             // doubles per table
+    int64_t ntables = 0;
+    int64_t doubles() const { return ntables * (T + 1); }
+};
+
+static SegmentPlan segment_plan(const lb_solver* s, int64_t m) {
+    SegmentPlan p;
+    if (s->d == 2) {
+        // reverse sweep in passes of up to steps_per_pass (at most 4) adjoint
+        // steps over n0+m-1 .. n0+1, then the step at the checkpoint
+        int64_t left = m - 1;
+        for (int pass = std::min(s->steps_per_pass, lbm::MAX_ADJOINT_STEPS_PER_PASS); pass >= 1;
+             pass /= 2)
+            for (; left >= pass; left -= pass) p.reverse.push_back(pass);
+        p.reverse.push_back(1);
+        p.T = std::max(lbm::adjoint_steps_table(s->g), s->npartials);
+        p.ntables = (int64_t)p.reverse.size();
+    } else {
+        p.T = s->npartials;
+        p.ntables = m;
+    }
+    return p;
+}
+
+// One checkpoint segment (lb_adjoint_segment); `tables` holds plan.doubles()
+// doubles, every one of which the launches write before it is read.
+static lb_status run_segment(lb_solver* s, const SegmentPlan& plan, const double* ckpt, int64_t m,
+                             double* work, double* lambda, double* lambda_tmp, double* g_eps,
+                             double* tables) {
     const int64_t se = elements_of(&s->cfg);
     // forward recomputation of the segment's states f^{n0+1} .. f^{n0+m-1}
     // (bitwise single steps): on D2Q9 by multi-step passes that store the
@@ -552,59 +618,84 @@ lb_status lb_adjoint_segment(lb_solver* s, const double* ckpt, int64_t m, double
     }
     double* lin = lambda;
     double* lout = lambda_tmp;
+    const int64_t T = plan.T, nt = plan.ntables;
     if (s->d == 2) {
-        // reverse sweep in passes of up to steps_per_pass (at most 4) adjoint steps over
-        // n0+m-1 .. n0+1 (their states are consecutive in work), then the
-        // step at the checkpoint; every launch leaves a table of T partials
-        std::vector<int> plan;
-        int64_t left = m - 1;
-        for (int pass = std::min(s->steps_per_pass, lbm::MAX_ADJOINT_STEPS_PER_PASS); pass >= 1;
-             pass /= 2)
-            for (; left >= pass; left -= pass) plan.push_back(pass);
-        plan.push_back(1);
-        const int64_t T = std::max(lbm::adjoint_steps_table(s->g), s->npartials);
-        const int64_t nt = (int64_t)plan.size();
-        st = reserve_seg_partials(s, nt * (T + 1));
-        if (st != LB_OK) return st;
+        // the states of n0+m-1 .. n0+1 are consecutive in work; every launch
+        // leaves a full table of T partials
         int64_t N = m;  // lin holds lambda^{n0+N}
         for (int64_t t = 0; t < nt; ++t) {
             const double* ftop = N == 1 ? ckpt : work + (N - 2) * se;  // f^{n0+N-1}
-            if (plan[t] == 1)
-                LB_HIP(lbm::launch_adjoint_step(2, s->g, s->r, ftop, lin, lout,
-                                                s->seg_partials + t * T, T, s->stream),
+            const int steps = plan.reverse[(size_t)t];
+            if (steps == 1)
+                LB_HIP(lbm::launch_adjoint_step(2, s->g, s->r, ftop, lin, lout, tables + t * T, T,
+                                                s->stream),
                        "adjoint_step launch");
             else
-                LB_HIP(lbm::launch_adjoint_steps(plan[t], s->g, s->r, lin, lout, ftop, se,
-                                                 s->seg_partials + t * T, T, s->stream),
+                LB_HIP(lbm::launch_adjoint_steps(steps, s->g, s->r, lin, lout, ftop, se,
+                                                 tables + t * T, T, s->stream),
                        "adjoint multi-step launch");
             std::swap(lin, lout);
-            N -= plan[t];
+            N -= steps;
         }
-        LB_HIP(lbm::launch_finalize_tables(s->seg_partials, T, nt, s->seg_partials + nt * T,
-                                           g_eps, s->stream),
-               "finalize");
     } else {
         // one adjoint step per launch; step j leaves its block partials in
         // table j, and one reduction adds the tables in the order of the steps
-        st = reserve_seg_partials(s, m * (s->npartials + 1));
-        if (st != LB_OK) return st;
         for (j = m - 1; j >= 0; --j) {
             const double* fn = j == 0 ? ckpt : work + (j - 1) * se;
-            LB_HIP(lbm::launch_adjoint_step(s->d, s->g, s->r, fn, lin, lout,
-                                            s->seg_partials + j * s->npartials, s->npartials,
+            LB_HIP(lbm::launch_adjoint_step(s->d, s->g, s->r, fn, lin, lout, tables + j * T, T,
                                             s->stream),
                    "adjoint_step launch");
             std::swap(lin, lout);
         }
-        LB_HIP(lbm::launch_finalize_tables(s->seg_partials, s->npartials, m,
-                                           s->seg_partials + m * s->npartials, g_eps, s->stream),
-               "finalize");
     }
+    LB_HIP(lbm::launch_finalize_tables(tables, T, nt, tables + nt * T, g_eps, s->stream),
+           "finalize");
     if (lin != lambda)
         LB_HIP(hipMemcpyAsync(lambda, lin, sizeof(double) * (size_t)se, hipMemcpyDeviceToDevice,
                               s->stream),
                "hipMemcpyAsync");
     return LB_OK;
+}
+
+static lb_status check_segment_args(lb_solver* s, const double* ckpt, int64_t m,
+                                    const double* lambda, const double* lambda_tmp,
+                                    const double* g_eps) {
+    if (!s || !ckpt || !lambda || !lambda_tmp || !g_eps)
+        return fail(LB_ERR_INVALID_ARG, "NULL argument");
+    if (m < 0) return fail(LB_ERR_INVALID_ARG, "m must be >= 0");
+    if (lambda == lambda_tmp) return fail(LB_ERR_INVALID_ARG, "lambda == lambda_tmp");
+    return not_bounded(s, "the adjoint is periodic only");
+}
+
+extern "C" {
+
+lb_status lb_adjoint_segment(lb_solver* s, const double* ckpt, int64_t m, double* work,
+                             double* lambda, double* lambda_tmp, double* g_eps) {
+    lb_status st = check_segment_args(s, ckpt, m, lambda, lambda_tmp, g_eps);
+    if (st != LB_OK) return st;
+    if (m > 1 && !work) return fail(LB_ERR_INVALID_ARG, "work is NULL");
+    if (m == 0) return LB_OK;
+    const SegmentPlan plan = segment_plan(s, m);
+    st = reserve_seg_partials(s, plan.doubles());
+    if (st != LB_OK) return st;
+    return run_segment(s, plan, ckpt, m, work, lambda, lambda_tmp, g_eps, s->seg_partials);
+}
+
+lb_status lb_adjoint_segment_static(lb_solver* s, const double* ckpt, int64_t m, double* work,
+                                    double* lambda, double* lambda_tmp, double* g_eps) {
+    lb_status st = check_segment_args(s, ckpt, m, lambda, lambda_tmp, g_eps);
+    if (st != LB_OK) return st;
+    if (m == 0) return LB_OK;
+    const SegmentPlan plan = segment_plan(s, m);
+    if (plan.doubles() > LB_SEGMENT_SCRATCH_DOUBLES)
+        return fail(LB_ERR_INVALID_ARG,
+                    "segment needs " + std::to_string(plan.doubles()) +
+                        " doubles of partials, more than the fixed scratch array holds (" +
+                        std::to_string((long long)LB_SEGMENT_SCRATCH_DOUBLES) +
+                        "): use lb_adjoint_segment or a shorter segment");
+    if (m > 1 && !work) return fail(LB_ERR_INVALID_ARG, "work is NULL");
+    if (!s->scratch) return fail(LB_ERR_STATE, "no scratch address for this solver's device");
+    return run_segment(s, plan, ckpt, m, work, lambda, lambda_tmp, g_eps, s->scratch);
 }
 
 lb_status lb_init_adjoint(lb_solver* s, const double* theta0, const double* grad_theta0,

@@ -92,6 +92,7 @@ def _load():
         "lb_macro_adjoint": ([_vp, _vp, _vp, _vp, _vp, _vp], st),
         "lb_adjoint_step": ([_vp, _vp, _vp, _vp, _vp], st),
         "lb_adjoint_segment": ([_vp, _vp, I64, _vp, _vp, _vp, _vp], st),
+        "lb_adjoint_segment_static": ([_vp, _vp, I64, _vp, _vp, _vp, _vp], st),
         "lb_init_adjoint": ([_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp], st),
         "lb_destroy": ([_vp], st),
         "lb_batch_layout": ([_cp, I32, _vp, _vp], I64),
@@ -238,6 +239,11 @@ def lb_adjoint_step(h: int, state_n, lam_in, lam_out, g_eps):
 def lb_adjoint_segment(h: int, ckpt, m: int, work, lam, lam_tmp, g_eps):
     _check(_load().lb_adjoint_segment(h, _ptr(ckpt), int(m), _ptr(work), _ptr(lam),
                                       _ptr(lam_tmp), _ptr(g_eps)))
+
+
+def lb_adjoint_segment_static(h: int, ckpt, m: int, work, lam, lam_tmp, g_eps):
+    _check(_load().lb_adjoint_segment_static(h, _ptr(ckpt), int(m), _ptr(work), _ptr(lam),
+                                             _ptr(lam_tmp), _ptr(g_eps)))
 
 
 def lb_init_adjoint(h: int, theta0, grad, lam0, g_theta0, g_grad, g_eps, g_nu=None):
