@@ -179,8 +179,19 @@ lb_status lb_step_bounded(lb_solver* s, int64_t nsteps, const double* walls);
  * an odd remainder, whenever the limit is 2 or more.  Values below 2 make
  * every step a separate launch; others are rounded down to 2, 4 or 8.  D1Q3
  * and D4Q33 take single steps.  Every grouping gives bitwise the result of
- * single steps.  Unknown options are LB_ERR_INVALID_ARG. */
-enum { LB_OPT_STEPS_PER_PASS = 1 };
+ * single steps.  Unknown options are LB_ERR_INVALID_ARG.
+ *
+ * LB_OPT_CHECK_INTERVAL (default 0 = off): failure detection while stepping.
+ * With value k > 0, lb_step counts the steps it runs (across calls; lb_init
+ * and lb_set_state restart the count) and, at the end of the first launch
+ * that brings the count to k or more, checks theta = sum_i f_i at every node
+ * of the current state and restarts the count.  If some theta is not finite
+ * or not positive (a diverged run, or a corrupted state: the Cole-Hopf
+ * velocity divides by theta, Sec. II), lb_step returns LB_ERR_NONFINITE at
+ * once; the state and step counter are those after that launch.  A check
+ * reads the state once and synchronises the stream.  Bounded solvers
+ * (lb_step_bounded) are not checked. */
+enum { LB_OPT_STEPS_PER_PASS = 1, LB_OPT_CHECK_INTERVAL = 2 };
 lb_status lb_set_option(lb_solver* s, int32_t option, int32_t value);
 
 /* One time step from an explicit source buffer to an explicit destination

@@ -201,6 +201,8 @@ struct lb_solver {
     int64_t npartials;
     int* flag;
     int steps_per_pass;  // LB_OPT_STEPS_PER_PASS: 1, 2, 4 or 8
+    int64_t check_interval;  // LB_OPT_CHECK_INTERVAL: 0 (off) or steps between state checks
+    int64_t since_check;     // steps lb_step has run since the last state check
     bool bounded;        // LB_FLAG_BOUNDED
     double* wall_now;    // bounded: theta at the two end nodes at the current time
     double* seg_partials;  // lb_adjoint_segment: one partials table per launch
@@ -284,6 +286,8 @@ lb_status lb_create(const lb_config* cfg, void* hip_stream, double* f_a, double*
     s->steps = 0;
     s->inited = false;
     s->steps_per_pass = lbm::MAX_STEPS_PER_PASS;
+    s->check_interval = 0;
+    s->since_check = 0;
     s->npartials = lbm::launch_shape(s->d, s->g).nblocks;
     s->partials = nullptr;
     s->flag = nullptr;
@@ -333,6 +337,26 @@ static lb_status check_theta(lb_solver* s, const double* theta, int64_t n) {
     return LB_OK;
 }
 
+// LB_OPT_CHECK_INTERVAL: after `steps` more steps, check the current state
+// once the interval is reached (synchronises the stream).
+static lb_status after_steps(lb_solver* s, int64_t steps) {
+    if (s->check_interval <= 0) return LB_OK;
+    s->since_check += steps;
+    if (s->since_check < s->check_interval) return LB_OK;
+    s->since_check = 0;
+    LB_HIP(hipMemsetAsync(s->flag, 0, sizeof(int), s->stream), "hipMemsetAsync");
+    LB_HIP(lbm::launch_check_state(s->d, s->g, s->buf[s->cur], s->flag, s->stream),
+           "check_state launch");
+    int h = 0;
+    LB_HIP(hipMemcpyAsync(&h, s->flag, sizeof(int), hipMemcpyDeviceToHost, s->stream),
+           "hipMemcpyAsync");
+    LB_HIP(hipStreamSynchronize(s->stream), "hipStreamSynchronize");
+    if (h)
+        return fail(LB_ERR_NONFINITE, "theta is not finite and positive at some node after step " +
+                                          std::to_string((long long)s->steps));
+    return LB_OK;
+}
+
 lb_status lb_init(lb_solver* s, const double* theta0, const double* grad_theta0,
                   int32_t check) {
     if (!s || !theta0) return fail(LB_ERR_INVALID_ARG, "solver and theta0 must not be NULL");
@@ -354,6 +378,7 @@ lb_status lb_init(lb_solver* s, const double* theta0, const double* grad_theta0,
     }
     s->cur = 0;
     s->steps = 0;
+    s->since_check = 0;
     s->inited = true;
     return LB_OK;
 }
@@ -372,9 +397,10 @@ lb_status lb_step(lb_solver* s, int64_t nsteps) {
                "resident step launch");
         s->cur = dst;
         s->steps += nsteps;
-        return LB_OK;
+        return after_steps(s, nsteps);
     }
     int64_t n = 0;
+    lb_status st = LB_OK;
     if (s->d == 2) {
         for (int pass = s->steps_per_pass; pass >= 2; pass /= 2) {
             for (; n + pass <= nsteps; n += pass) {
@@ -383,6 +409,7 @@ lb_status lb_step(lb_solver* s, int64_t nsteps) {
                        "multi-step launch");
                 s->cur ^= 1;
                 s->steps += pass;
+                if ((st = after_steps(s, pass)) != LB_OK) return st;
             }
         }
     } else if (s->d == 3 && s->steps_per_pass >= lbm::MAX_STEPS_PER_PASS_3D) {
@@ -393,6 +420,7 @@ lb_status lb_step(lb_solver* s, int64_t nsteps) {
                    "multi-step launch");
             s->cur ^= 1;
             s->steps += pass;
+            if ((st = after_steps(s, pass)) != LB_OK) return st;
         }
     }
     for (; n < nsteps; ++n) {
@@ -400,6 +428,7 @@ lb_status lb_step(lb_solver* s, int64_t nsteps) {
                "step launch");
         s->cur ^= 1;
         ++s->steps;
+        if ((st = after_steps(s, 1)) != LB_OK) return st;
     }
     return LB_OK;
 }
@@ -442,6 +471,11 @@ lb_status lb_set_option(lb_solver* s, int32_t option, int32_t value) {
             s->steps_per_pass = p;
             return LB_OK;
         }
+        case LB_OPT_CHECK_INTERVAL:
+            if (value < 0) return fail(LB_ERR_INVALID_ARG, "the check interval must be >= 0");
+            s->check_interval = value;
+            s->since_check = 0;
+            return LB_OK;
         default:
             return fail(LB_ERR_INVALID_ARG, "unknown option");
     }
@@ -502,6 +536,7 @@ lb_status lb_set_state(lb_solver* s, const double* f_in, int64_t step) {
         LB_HIP(lbm::launch_wall_from_dense1(s->g, f_in, s->wall_now, s->stream), "set_state walls");
     s->cur = 0;
     s->steps = step;
+    s->since_check = 0;
     s->inited = true;
     return LB_OK;
 }

@@ -103,6 +103,9 @@ hipError_t launch_theta_from_velocity(int d, const Geo& g, double dx, double nu,
                                       double* work, double* theta, double* grad,
                                       hipStream_t st);
 hipError_t launch_check_theta(const double* theta, int64_t n, int* flag, hipStream_t st);
+// Sets *flag (atomic OR) if theta = sum_i f_i is not finite and positive at some node.
+hipError_t launch_check_state(int d, const Geo& g, const double* state, int* flag,
+                              hipStream_t st);
 
 // Adjoint kernels write one partial sum of the eps-gradient per block into
 // `partials`; launch_finalize then adds their sum (fixed order) to *g_eps.

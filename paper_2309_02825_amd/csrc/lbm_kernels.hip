@@ -1044,6 +1044,22 @@ __global__ void __launch_bounds__(256) k_layout_to_dense(const double* __restric
     for (int i = 0; i < Q; ++i) dense[(int64_t)i * g.V + k] = buf[slot<Q>(i, k)];
 }
 
+// Sets *flag when theta = sum_i f_i of some node of the state is not finite
+// and positive (a diverged or corrupted run: u = -2 nu grad theta / theta
+// needs theta > 0).
+template <int D>
+__global__ void __launch_bounds__(256) k_check_state(const double* __restrict__ src, int* flag,
+                                                     Geo g) {
+    constexpr int Q = Lat<D>::Q;
+    int c[4];
+    if (!thread_node<D>(g, c)) return;
+    const Nbr nb = make_nbr<D>(c, g);
+    double th = 0.0;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) th += src[slot<Q>(i, pull_index<D>(nb, i))];
+    if (!(th > 0.0) || !isfinite(th)) atomicOr(flag, 1);
+}
+
 __global__ void __launch_bounds__(256) k_check_theta(const double* __restrict__ th, int64_t n,
                                                      int* flag) {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -1817,6 +1833,11 @@ hipError_t launch_init(int d, const Geo& g, const Rates& r, const double* theta0
 hipError_t launch_macro(int d, const Geo& g, const Rates& r, const double* state, double* theta,
                         double* u, double* grad, hipStream_t st) {
     return LBM_LAUNCH(k_macro, state, theta, u, grad, g, r);
+}
+
+hipError_t launch_check_state(int d, const Geo& g, const double* state, int* flag,
+                              hipStream_t st) {
+    return LBM_LAUNCH(k_check_state, state, flag, g);
 }
 
 hipError_t launch_get_state(int d, const Geo& g, const double* state, double* dense,

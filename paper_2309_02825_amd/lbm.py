@@ -23,6 +23,7 @@ LB_ERR_OOM = -4
 LB_ERR_HIP = -5
 LB_ERR_STATE = -6
 LB_OPT_STEPS_PER_PASS = 1
+LB_OPT_CHECK_INTERVAL = 2
 LB_FLAG_BOUNDED = 1
 _NAMES = {0: "LB_OK", -1: "LB_ERR_INVALID_ARG", -2: "LB_ERR_UNSTABLE", -3: "LB_ERR_NONFINITE",
           -4: "LB_ERR_OOM", -5: "LB_ERR_HIP", -6: "LB_ERR_STATE"}

@@ -8,8 +8,12 @@ of shape ``(n_{d-1}, ..., n_0)`` and a vector field ``(d, n_{d-1}, ..., n_0)``.
 """
 from __future__ import annotations
 
+import hashlib
+import json
 import math
-from typing import List, Optional, Sequence
+import os
+import tempfile
+from typing import List, Optional, Sequence, Tuple
 
 import torch
 
@@ -126,6 +130,12 @@ class Solver:
         """D2Q9: the most time steps one pass over HBM advances (1, 2, 4 or 8;
         default 8).  Results are bitwise the same for every value."""
         L.lb_set_option(self.h, L.LB_OPT_STEPS_PER_PASS, int(n))
+
+    def set_check_interval(self, n: int):
+        """Failure detection: every n steps (0 = off) step() checks that theta
+        is finite and positive everywhere and raises LBError with
+        LB_ERR_NONFINITE otherwise (each check synchronises the stream)."""
+        L.lb_set_option(self.h, L.LB_OPT_CHECK_INTERVAL, int(n))
 
     def step_buffers(self, src: torch.Tensor, dst: torch.Tensor):
         src = _buffer(src, self.state_elems, self.device, "src")
@@ -321,6 +331,57 @@ def velocity(theta0: torch.Tensor, nu: torch.Tensor, grid, dx: float, dt: float,
 # batched form
 # ---------------------------------------------------------------------------
 
+def batch_signature(problems: Sequence, device_name: str, library_id: str) -> str:
+    """Key of a tuned tile choice: the instances (grid, dx, dt, nu, in
+    order), the GPU model and the build of the HIP library."""
+    items = [[list(map(int, p.grid)), repr(float(p.dx)), repr(float(p.dt)), repr(float(p.nu))]
+             for p in problems]
+    blob = json.dumps({"instances": items, "device": device_name, "library": library_id},
+                      sort_keys=True)
+    return hashlib.sha256(blob.encode()).hexdigest()
+
+
+def load_tuned(path: str, signature: str) -> Optional[Tuple[int, int]]:
+    """Tile (tx, ty) stored for ``signature`` in the JSON file at ``path``, or None."""
+    try:
+        with open(path) as fh:
+            entry = json.load(fh).get(signature)
+    except (OSError, ValueError, AttributeError):
+        return None
+    if not isinstance(entry, dict) or not isinstance(entry.get("tile"), list):
+        return None
+    tx, ty = entry["tile"]
+    return int(tx), int(ty)
+
+
+def store_tuned(path: str, signature: str, tile: Tuple[int, int], meta: dict) -> None:
+    """Add or replace the entry of ``signature`` (written to a temporary file
+    and renamed, so a reader never sees a partial file)."""
+    try:
+        with open(path) as fh:
+            table = json.load(fh)
+        if not isinstance(table, dict):
+            table = {}
+    except (OSError, ValueError):
+        table = {}
+    table[signature] = dict(meta, tile=[int(tile[0]), int(tile[1])])
+    d = os.path.dirname(os.path.abspath(path))
+    os.makedirs(d, exist_ok=True)
+    fd, tmp = tempfile.mkstemp(dir=d, prefix=".tune", suffix=".json")
+    with os.fdopen(fd, "w") as fh:
+        json.dump(table, fh, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def library_id() -> str:
+    """Content hash of the built HIP library (a rebuild invalidates tunings)."""
+    h = hashlib.sha256()
+    with open(L.LIBPATH, "rb") as fh:
+        for block in iter(lambda: fh.read(1 << 20), b""):
+            h.update(block)
+    return h.hexdigest()[:16]
+
+
 class BatchSolver:
     """Independent 2-D periodic instances of different sizes and viscosities
     advanced together: each launch runs one tile-table kernel over every
@@ -330,6 +391,7 @@ class BatchSolver:
     def __init__(self, problems: Sequence, device: Optional[torch.device] = None,
                  stream: Optional[torch.cuda.Stream] = None):
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.problems = list(problems)
         self.cfgs = [L.make_config(p.grid, p.dx, p.dt, p.nu) for p in problems]
         self.grids = [tuple(p.grid) for p in problems]
         total, self.offsets, self.elems = L.lb_batch_layout(self.cfgs)
@@ -377,8 +439,25 @@ class BatchSolver:
         (tx, ty) rectangles of 256 nodes."""
         L.lb_batch_set_tile(self.h, tx, ty)
 
-    def autotune(self, steps_per_trial: int = 3):
-        return L.lb_batch_autotune(self.h, steps_per_trial)
+    def autotune(self, steps_per_trial: int = 3, cache_file: Optional[str] = None):
+        """Time the tile candidates on the live pools (lb_batch_autotune) and
+        keep the fastest; returns (tx, ty).  With ``cache_file`` the choice is
+        looked up there first, keyed by batch_signature (instances, GPU model,
+        library build), and stored there after a fresh tuning."""
+        sig = None
+        if cache_file:
+            sig = batch_signature(self.problems, torch.cuda.get_device_name(self.device),
+                                  library_id())
+            tile = load_tuned(cache_file, sig)
+            if tile is not None:
+                self.set_tile(*tile)
+                return tile
+        tile = L.lb_batch_autotune(self.h, steps_per_trial)
+        if cache_file:
+            store_tuned(cache_file, sig, tile, {"instances": len(self.problems),
+                                                "device": torch.cuda.get_device_name(self.device),
+                                                "steps_per_trial": int(steps_per_trial)})
+        return tile
 
     def step(self, nsteps: int, graph: bool = True):
         L.lb_batch_step(self.h, nsteps, graph)

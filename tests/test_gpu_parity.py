@@ -450,6 +450,50 @@ def test_theta_check_rejects_nonpositive_and_nonfinite():
     s.close()
 
 
+@pytest.mark.parametrize("grid,spp", [((64, 48), 8), ((10, 9, 7), 2), ((300,), 1), ((5000,), 1)])
+def test_check_interval_detects_nonfinite_state(grid, spp):
+    """LB_OPT_CHECK_INTERVAL: a run with checks is bitwise the run without;
+    a state holding a NaN, an infinity or a non-positive theta (loaded as
+    ordinary values through lb_set_state) makes lb_step return
+    LB_ERR_NONFINITE at the first check."""
+    _say("check interval", grid, spp)
+    SV = _solver_mod()
+    from paper_2309_02825_amd import lbm as L
+    dx, dt, nu, th0, _ = _problem(grid, "random")
+    th0 = torch.from_numpy(th0).to(_dev())
+    ref = SV.Solver(grid, dx, dt, nu, device=_dev())
+    ref.set_steps_per_pass(spp)
+    ref.init(th0, None)
+    ref.step(37)
+    s = SV.Solver(grid, dx, dt, nu, device=_dev())
+    s.set_steps_per_pass(spp)
+    s.set_check_interval(5)
+    s.init(th0, None)
+    for n in (3, 1, 20, 13):
+        s.step(n)
+    assert s.steps == 37
+    assert torch.equal(s.get_state(), ref.get_state())
+    good = ref.get_state()
+    ref.close()
+    for bad in (float("nan"), float("inf"), "negative"):
+        f = good.clone()
+        if bad == "negative":
+            f = -f  # theta < 0 everywhere, and it stays so (the scheme is linear)
+        else:
+            f.view(s.q, -1)[3 % s.q, good[0].numel() // 2] = bad
+        s.set_state(f, 100)
+        with pytest.raises(L.LBError) as ei:
+            s.step(12)
+        assert ei.value.status == L.LB_ERR_NONFINITE, bad
+        assert 105 <= s.steps <= 112
+    # with the check off the same state steps without an error
+    s.set_check_interval(0)
+    s.set_state(f, 0)
+    s.step(12)
+    torch.cuda.synchronize()
+    s.close()
+
+
 def test_conservation_on_gpu():
     _say("conservation 2d 10k steps")
     grid = (96, 80)
@@ -1073,6 +1117,30 @@ def test_batch_beyond_4gib_instance():
     bs.close()
     del ths, us, th0s
     torch.cuda.empty_cache()
+
+
+def test_batch_autotune_cache(tmp_path):
+    """A tuned tile is stored and, for the same batch, read back instead of
+    tuned again (the stored entry decides the tile a new batch runs with)."""
+    _say("batch autotune cache")
+    SV = _solver_mod()
+    insts = W.batch_instances(count=6, seed=9, lmin=16, lmax=80)
+    path = str(tmp_path / "tune.json")
+    th = [torch.from_numpy(W.evaluate(p.modes, p.grid, p.dx)[0]) for p in insts]
+    a = SV.BatchSolver(insts, device=_dev())
+    a.init(th)
+    tile = a.autotune(1, cache_file=path)
+    a.close()
+    sig = SV.batch_signature(insts, torch.cuda.get_device_name(_dev()), SV.library_id())
+    assert SV.load_tuned(path, sig) == tuple(tile)
+    # plant a different (valid) choice: the next batch must take it untimed
+    SV.store_tuned(path, sig, (16, 16), {})
+    b = SV.BatchSolver(insts, device=_dev())
+    b.init(th)
+    assert b.autotune(1, cache_file=path) == (16, 16)
+    b.step(5, graph=False)
+    torch.cuda.synchronize()
+    b.close()
 
 
 def test_batch_full_size_against_exact_modes():

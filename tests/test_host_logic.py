@@ -122,3 +122,31 @@ def test_solver_buffer_checks_reject_bad_buffers():
         SV._buffer(torch.zeros(20, dtype=torch.float64)[::2], 10, cpu, "x")
     with pytest.raises(TypeError):
         SV._buffer([0.0] * 10, 10, cpu, "x")
+
+
+def test_autotune_cache_round_trip(tmp_path):
+    """The persisted tile choice of the batched form: keyed by the instances,
+    the GPU model and the library build; a changed instance, GPU or build
+    misses; entries of other batches survive a store; a damaged file reads
+    as empty."""
+    from paper_2309_02825_amd import solver as SV
+    from paper_2309_02825_amd import workloads as W
+    insts = W.batch_instances(count=5, seed=3)
+    path = str(tmp_path / "tune" / "batch.json")
+    sig = SV.batch_signature(insts, "gpu-a", "lib1")
+    assert SV.load_tuned(path, sig) is None
+    SV.store_tuned(path, sig, (-8, 128), {"instances": 5})
+    assert SV.load_tuned(path, sig) == (-8, 128)
+    other = W.batch_instances(count=5, seed=4)
+    sig2 = SV.batch_signature(other, "gpu-a", "lib1")
+    assert sig2 != sig and SV.load_tuned(path, sig2) is None
+    assert SV.batch_signature(insts, "gpu-b", "lib1") != sig
+    assert SV.batch_signature(insts, "gpu-a", "lib2") != sig
+    SV.store_tuned(path, sig2, (0, 0), {})
+    assert SV.load_tuned(path, sig) == (-8, 128) and SV.load_tuned(path, sig2) == (0, 0)
+    with open(path, "w") as fh:
+        fh.write("{not json")
+    assert SV.load_tuned(path, sig) is None
+    SV.store_tuned(path, sig, (-24, 32), {})
+    assert SV.load_tuned(path, sig) == (-24, 32)
+
