@@ -776,31 +776,27 @@ k_adjoint_steps_d2q9(const double* __restrict__ src, double* __restrict__ dst,
 // The 2-D scheme above one dimension up: a block of MS3_TX x MS3_TY threads
 // owns a tile of (MS3_TX - 2S) x (MS3_TY - 2S) output columns (x, y) plus an
 // S-wide halo, thread (tx, ty) owns one column in every stage, and the block
-// marches along z through a segment of planes.  The three populations with
-// e_x = e_y = 0 stay in their thread; the sixteen others go through LDS
-// already shifted by (e_x, e_y).  Planes are delayed in registers by e_z
-// (0, 1 or 2 iterations).  Register pressure limits S to 2 (about 250 VGPRs,
-// two waves per SIMD); each block uses 2 x 16 x 512 doubles of LDS.
+// marches along z through a segment of planes.  A row of the tile (fixed y)
+// is one wave, lane tx = column x: the ten populations with e_x != 0 are
+// pulled from lane tx - e_x by DPP lane shifts, as in the D2Q9 passes; the
+// ten with e_y != 0 (the xy edges after their x shift) then go through LDS
+// to row ty + e_y; the three with e_x = e_y = 0 stay in their thread.  Planes
+// are delayed in registers by e_z (0, 1 or 2 iterations).  Register pressure
+// limits S to 2 (217 VGPRs, two waves per SIMD, so one 512-thread block per
+// CU); each block uses 2 x 10 x 512 doubles of LDS.
 // ---------------------------------------------------------------------------
 __host__ __device__ constexpr int m3_ex(int i) { return Lat<3>::E[i][0]; }
 __host__ __device__ constexpr int m3_ey(int i) { return Lat<3>::E[i][1]; }
 __host__ __device__ constexpr int m3_ez(int i) { return Lat<3>::E[i][2]; }
-__host__ __device__ constexpr bool m3_mover(int i) { return m3_ex(i) != 0 || m3_ey(i) != 0; }
-// index of population i among the movers, and among those with its e_z
-__host__ __device__ constexpr int m3_xyslot(int i) {
-    int s = 0;
-    for (int j = 0; j < i; ++j) s += m3_mover(j);
-    return s;
-}
+// index of population i among those with its e_z
 __host__ __device__ constexpr int m3_zslot(int i) {
     int s = 0;
     for (int j = 0; j < i; ++j) s += m3_ez(j) == m3_ez(i);
     return s;
 }
-constexpr int M3_MOVERS = m3_xyslot(19);
 constexpr int M3_Z0 = 9, M3_ZP = 5;  // populations with e_z = 0 and with e_z = +1
-static_assert(M3_MOVERS == 16, "D3Q19 has 16 populations with e_x or e_y != 0");
 constexpr int M3_THREADS = MS3_TX * MS3_TY;
+static_assert(MS3_TX == 64, "a tile row of the D3Q19 pass is one wave (DPP lane shifts along x)");
 
 template <int S>
 struct Ms3State {
@@ -809,6 +805,17 @@ struct Ms3State {
     double u[2][S][M3_ZP];     // e_z = +1 populations of the planes of each parity
 };
 
+// y-movers (e_y != 0): the 10 populations exchanged through LDS
+__host__ __device__ constexpr bool m3_ymover(int i) { return m3_ey(i) != 0; }
+__host__ __device__ constexpr int m3_yslot(int i) {
+    int s = 0;
+    for (int j = 0; j < i; ++j) s += m3_ymover(j);
+    return s;
+}
+constexpr int M3_YMOVERS = m3_yslot(19);
+static_assert(M3_YMOVERS == 10, "D3Q19 has 10 populations with e_y != 0");
+
+// x shift by DPP (pull from lane tx - e_x), then y shift through LDS
 template <int S, int P>
 __device__ __forceinline__ void ms3_plane(Ms3State<S>& st, double* lds, int k,
                                           const double* __restrict__ src, double* __restrict__ dst,
@@ -820,26 +827,29 @@ __device__ __forceinline__ void ms3_plane(Ms3State<S>& st, double* lds, int k,
 #pragma unroll
     for (int i = 0; i < 19; ++i) f[i] = st.pre[i];
     {
-        // next plane (unused in the last iteration, as in ms_row)
         const int64_t base = (int64_t)wrapi(zs - S + k + 1, g.nz) * plane + col;
 #pragma unroll
         for (int i = 0; i < 19; ++i) st.pre[i] = src[slot<19>(i, base)];
     }
+    // pull along x (every lane takes part; the edge lanes receive zeros,
+    // which reach only halo columns, never a stored output)
 #pragma unroll
     for (int i = 0; i < 19; ++i)
-        if (m3_mover(i)) {
-            const int cx = tx + m3_ex(i), cy = ty + m3_ey(i);
-            if (cx >= 0 && cx < MS3_TX && cy >= 0 && cy < MS3_TY)
-                lds[m3_xyslot(i) * M3_THREADS + cy * MS3_TX + cx] = f[i];
+        if (m3_ex(i) != 0) f[i] = m3_ex(i) == 1 ? lane_shift<1>(f[i]) : lane_shift<-1>(f[i]);
+#pragma unroll
+    for (int i = 0; i < 19; ++i)
+        if (m3_ymover(i)) {
+            const int cy = ty + m3_ey(i);
+            if (cy >= 0 && cy < MS3_TY) lds[m3_yslot(i) * M3_THREADS + cy * MS3_TX + tx] = f[i];
         }
     __syncthreads();
 #pragma unroll
     for (int j = 1; j <= S; ++j) {
         double in[19];
-        const double* rd = lds + ((j - 1) & 1) * M3_MOVERS * M3_THREADS;
+        const double* rd = lds + ((j - 1) & 1) * M3_YMOVERS * M3_THREADS;
 #pragma unroll
         for (int i = 0; i < 19; ++i) {
-            const double v = m3_mover(i) ? rd[m3_xyslot(i) * M3_THREADS + tid] : f[i];
+            const double v = m3_ymover(i) ? rd[m3_yslot(i) * M3_THREADS + tid] : f[i];
             if (m3_ez(i) == -1) {
                 in[i] = v;
             } else if (m3_ez(i) == 0) {
@@ -850,17 +860,18 @@ __device__ __forceinline__ void ms3_plane(Ms3State<S>& st, double* lds, int k,
                 st.u[P][j - 1][m3_zslot(i)] = v;
             }
         }
-        if (k >= 2 * j && tx >= j && tx < MS3_TX - j && ty >= j && ty < MS3_TY - j) {
+        if (k >= 2 * j) {
             collide_d3q19(in, r);
             if (j < S) {
-                double* wr = lds + (j & 1) * M3_MOVERS * M3_THREADS;
+                double* wr = lds + (j & 1) * M3_YMOVERS * M3_THREADS;
 #pragma unroll
                 for (int i = 0; i < 19; ++i) {
-                    f[i] = in[i];
-                    if (m3_mover(i)) {
-                        const int cx = tx + m3_ex(i), cy = ty + m3_ey(i);
-                        if (cx >= 0 && cx < MS3_TX && cy >= 0 && cy < MS3_TY)
-                            wr[m3_xyslot(i) * M3_THREADS + cy * MS3_TX + cx] = in[i];
+                    double v = in[i];
+                    if (m3_ex(i) != 0) v = m3_ex(i) == 1 ? lane_shift<1>(v) : lane_shift<-1>(v);
+                    f[i] = v;
+                    if (m3_ymover(i)) {
+                        const int cy = ty + m3_ey(i);
+                        if (cy >= 0 && cy < MS3_TY) wr[m3_yslot(i) * M3_THREADS + cy * MS3_TX + tx] = v;
                     }
                 }
             } else if (tx >= S && tx < MS3_TX - S && ty >= S && ty < MS3_TY - S &&
@@ -880,7 +891,7 @@ template <int S>
 __global__ void __launch_bounds__(M3_THREADS) k_steps_d3q19(const double* __restrict__ src,
                                                             double* __restrict__ dst, Geo g,
                                                             Rates r, int lz, int ntx, int nty) {
-    __shared__ double lds[2 * M3_MOVERS * M3_THREADS];
+    __shared__ double lds[2 * M3_YMOVERS * M3_THREADS];
     const unsigned t = xcd_remap(blockIdx.x, gridDim.x);
     const unsigned ntile = (unsigned)ntx * (unsigned)nty;
     const int tile = (int)(t % ntile), seg = (int)(t / ntile);
