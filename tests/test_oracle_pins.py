@@ -210,6 +210,25 @@ def test_spectral_evaluator_matches_direct_oracle(d, grid, steps):
     assert np.max(np.abs(u - us) / scale[None]) < 1e-14
 
 
+@pytest.mark.parametrize("d,grid", [(1, (13,)), (2, (9, 7)), (3, (5, 6, 4))])
+def test_spectral_whole_field_matches_pointwise_evaluation(d, grid):
+    """The whole-field moment evaluation (one outer product of per-axis
+    phases per mode, used for full-size parity) equals the pointwise state
+    evaluation of the same exact discrete solution, and the direct oracle."""
+    rng = np.random.default_rng(40 + d)
+    modes = _random_modes(d, grid, 4, rng)
+    dx, nu = 0.05, 0.02
+    dt = 0.13 * dx * dx / nu
+    sol = S.ModeSolution(grid, dx, dt, nu, modes, 17)
+    th_f, u_f = sol.macro_field()
+    ths, us = sol.macro(S.all_points(grid))
+    assert max_rel(th_f, S.to_field(ths.astype(np.float64), grid)) < 1e-15
+    assert max_rel(u_f, S.to_field(us.astype(np.float64), grid)) < 1e-13
+    th0, g0 = W.evaluate(modes, grid, dx)
+    th, u, _ = O.solve(th0, g0, dx, dt, nu, 17)
+    assert max_rel(th_f, th) < 1e-13 and max_rel(u_f, u) < 1e-11
+
+
 @pytest.mark.parametrize("seed", range(24))
 def test_spectral_matches_direct_oracle_random_cases(seed):
     """Property form of the check above: lattice, grid (3..9 nodes per axis,
