@@ -14,10 +14,11 @@ RMSEs of 1e-10 .. 1e-14) differ from the printed ones by rounding: two FP64
 implementations of the scheme drift apart by about eps_mach sqrt(N) max|theta|
 after N steps (a random walk of per-step roundings), so every cell also
 accepts an absolute difference of 2 eps_mach sqrt(N) max|theta0|, but that
-floor never widens a cell's bound beyond 1e-3 relative (_bound): the oracle
-meets even the cells printed at 1e-13 .. 1e-14 (Table 4, eps = 0.10, t = 2)
-to 3e-4, so a 1 % error there still fails.  The finest levels run only with
-LBM_SLOW=1.
+floor never widens a cell's bound beyond FLOOR_CAP = 5e-3 relative (_bound).
+The oracle meets the cells printed at 1e-13 .. 1e-14 to within that: Table 4,
+eps = 0.10, t = 2 to 3e-4 at level 0 and 1.5e-3 at level 1; Table 3,
+eps = 0.20, level 2 (printed 5e-14 .. 2e-13) to 1.7e-3.  So a 1 % error in
+any of them fails.  The finest levels run only with LBM_SLOW=1.
 """
 import math
 import os
@@ -37,8 +38,9 @@ def _floor(nsteps, th0):
     return 2.0 * np.finfo(np.float64).eps * math.sqrt(max(nsteps, 1)) * float(np.max(np.abs(th0)))
 
 
-# the most the rounding floor may widen a cell's bound (relative)
-FLOOR_CAP = 1e-3
+# the most the rounding floor may widen a cell's bound (relative): above the
+# 1.7e-3 the FP64-floor cells of the finest levels differ by, below 1 %
+FLOOR_CAP = 5e-3
 
 
 def _bound(tol, printed, floor):
