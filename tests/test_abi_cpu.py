@@ -150,3 +150,32 @@ def test_binding_fails_loudly_without_library(monkeypatch):
         lbm.library()
     with pytest.raises(RuntimeError, match="no fallback"):
         lbm.lb_num_populations(2)
+
+
+def _build_c_client(out):
+    """Compile tests/c_client.c as strict C99 against include/lbm.h and link
+    it to the built library (the header must be plain C, the symbols must
+    resolve)."""
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc is not installed")
+    lib_dir = os.path.dirname(L.LIBPATH)
+    cmd = ["gcc", "-std=c99", "-Wall", "-Wextra", "-Werror", "-pedantic",
+           "-D__HIP_PLATFORM_AMD__", "-I", os.path.join(ROOT, "include"), "-isystem", "/opt/rocm/include",
+           "-o", out, os.path.join(ROOT, "tests", "c_client.c"),
+           "-L", lib_dir, "-llbm_hip", "-Wl,-rpath," + lib_dir,
+           "-L", "/opt/rocm/lib", "-lamdhip64", "-Wl,-rpath,/opt/rocm/lib", "-lm"]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    return out
+
+
+def test_c_client_compiles_as_c99_and_runs_host_calls(tmp_path):
+    """The ABI from a plain C program: parameters, sizes and validation need
+    no device."""
+    import subprocess
+    exe = _build_c_client(str(tmp_path / "c_client"))
+    r = subprocess.run([exe, "--no-gpu"], capture_output=True, text=True, timeout=60)
+    assert r.returncode == 0, r.stderr
+    assert r.stdout.strip() == "ok"

@@ -494,6 +494,20 @@ def test_check_interval_detects_nonfinite_state(grid, spp):
     s.close()
 
 
+def test_c_client_runs_on_gpu(tmp_path):
+    """The C ABI from a plain C99 program (tests/c_client.c): create, init
+    with the library's difference gradient and a theta check, 100 steps,
+    theta / u / grad theta; conservation and u = -2 nu grad(theta)/theta
+    checked on the host."""
+    import subprocess
+    from tests.test_abi_cpu import _build_c_client
+    _say("c client")
+    exe = _build_c_client(str(tmp_path / "c_client"))
+    r = subprocess.run([exe], capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stderr
+    assert r.stdout.strip() == "ok"
+
+
 def test_conservation_on_gpu():
     _say("conservation 2d 10k steps")
     grid = (96, 80)
