@@ -31,7 +31,13 @@ if ROOT not in sys.path:
 
 METRIC = "FP64 MLUPS + HBM GB/s (% roofline); batched and adjoint vs plain step"
 HBM_PEAK_GBS = 8000.0
+# one read and one write of a complete state: 2 q 8 bytes per node
 BYTES_PER_LU = {1: 48, 2: 144, 3: 304, 4: 528}
+# one read and one write of the populations of a post-collision state that
+# are independent (the twin edge populations of every axis pair are equal):
+# 2 x (1 + 2d + 2d(d-1)) x 8 bytes per node; what the passes inside one
+# lb_step call move
+BYTES_PER_NODE_PASS = {1: 48, 2: 112, 3: 208, 4: 336}
 # double-precision operations of one D2Q9 collision (collide_d2q9: 26 add/sub,
 # 6 mul, 3 fma counted twice)
 FLOPS_PER_LU_D2Q9 = 38
@@ -43,18 +49,25 @@ KERNEL_SOURCES = [os.path.join(ROOT, "paper_2309_02825_amd", "csrc", n)
                   for n in ("lbm_kernels.hip", "lbm_lattice.h", "lbm_kernels.h")]
 
 
-def pass_roofline(d: int, nodes: int, steps_per_launch: int, us_per_step: float) -> dict:
-    """Roofline of one launch of a pass kernel.  A pass reads the q
-    populations of every node once and writes them once, whatever the number
-    of time steps it advances: 2 q 8 bytes per node and pass are its
-    algorithmic bytes, so `frac` is a true fraction of the HBM peak.  The
-    per-update figure (2 q 8 bytes per lattice update, what a one-step pass
-    would move for the same updates) is kept as `lu_equivalent_gbs`."""
+def pass_roofline(d: int, nodes: int, steps_per_launch: int, us_per_step: float,
+                  reduced: bool = True) -> dict:
+    """Roofline of one launch of a pass kernel.  A pass reads the state of
+    every node once and writes it once, whatever the number of time steps it
+    advances.  Inside an lb_step call the state is post-collision, so only
+    its independent populations move: 2 x (7, 13, 21) x 8 bytes per node for
+    D2Q9, D3Q19, D4Q33 (`reduced`); those are the pass's algorithmic bytes,
+    and `frac` is a true fraction of the HBM peak.  The same time against a
+    complete state (2 q 8 bytes per node) is `complete_state_gbs`, and the
+    per-update figure (bytes per lattice update times the steps of a launch)
+    is `lu_equivalent_gbs`; neither is a fraction of the peak."""
     launch_s = us_per_step * steps_per_launch * 1e-6
-    pass_bytes = BYTES_PER_LU[d] * nodes
+    per_node = BYTES_PER_NODE_PASS[d] if reduced else BYTES_PER_LU[d]
+    pass_bytes = per_node * nodes
     gbs = pass_bytes / launch_s / 1e9
-    return {"bytes_per_launch": pass_bytes, "kernel_us_per_launch": round(launch_s * 1e6, 3),
+    return {"bytes_per_launch": pass_bytes, "bytes_per_node": per_node,
+            "kernel_us_per_launch": round(launch_s * 1e6, 3),
             "achieved_gbs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
+            "complete_state_gbs": round(BYTES_PER_LU[d] * nodes / launch_s / 1e9, 1),
             "lu_equivalent_gbs": round(gbs * steps_per_launch, 1)}
 
 
@@ -545,8 +558,10 @@ def main():
                      "lb_steps_per_launch": per_launch,
                      "kernel_us_per_launch": launch_us,
                      "algorithmic_bytes_per_launch": pr["bytes_per_launch"],
-                     "algorithmic_unit": f"node-pass: the {2 * {1: 3, 2: 9, 3: 19, 4: 33}[d]} "
-                                         f"populations of a node read and written once",
+                     "algorithmic_unit": f"node-pass: the {BYTES_PER_NODE_PASS[d] // 16} independent "
+                                         f"populations of a post-collision node read and written "
+                                         f"once ({BYTES_PER_NODE_PASS[d]} B)",
+                     "complete_state_gbs": pr["complete_state_gbs"],
                      "lu_equivalent_gbs": pr["lu_equivalent_gbs"],
                      "traffic_over_algorithmic": (round(traffic / pr["bytes_per_launch"], 4)
                                                   if traffic else None),

@@ -203,6 +203,7 @@ struct lb_solver {
     int steps_per_pass;  // LB_OPT_STEPS_PER_PASS: 1, 2, 4 or 8
     int64_t check_interval;  // LB_OPT_CHECK_INTERVAL: 0 (off) or steps between state checks
     int64_t since_check;     // steps lb_step has run since the last state check
+    bool twin_ok;            // the current state was written by a collision (twins equal)
     bool bounded;        // LB_FLAG_BOUNDED
     double* wall_now;    // bounded: theta at the two end nodes at the current time
     double* seg_partials;  // lb_adjoint_segment: one partials table per launch
@@ -288,6 +289,7 @@ lb_status lb_create(const lb_config* cfg, void* hip_stream, double* f_a, double*
     s->steps_per_pass = lbm::MAX_STEPS_PER_PASS;
     s->check_interval = 0;
     s->since_check = 0;
+    s->twin_ok = false;
     s->npartials = lbm::launch_shape(s->d, s->g).nblocks;
     s->partials = nullptr;
     s->flag = nullptr;
@@ -379,6 +381,7 @@ lb_status lb_init(lb_solver* s, const double* theta0, const double* grad_theta0,
     s->cur = 0;
     s->steps = 0;
     s->since_check = 0;
+    s->twin_ok = false;
     s->inited = true;
     return LB_OK;
 }
@@ -399,36 +402,57 @@ lb_status lb_step(lb_solver* s, int64_t nsteps) {
         s->steps += nsteps;
         return after_steps(s, nsteps);
     }
-    int64_t n = 0;
-    lb_status st = LB_OK;
-    if (s->d == 2) {
-        for (int pass = s->steps_per_pass; pass >= 2; pass /= 2) {
-            for (; n + pass <= nsteps; n += pass) {
-                LB_HIP(lbm::launch_steps(pass, s->g, s->r, s->buf[s->cur], s->buf[1 - s->cur],
-                                         s->stream),
-                       "multi-step launch");
-                s->cur ^= 1;
-                s->steps += pass;
-                if ((st = after_steps(s, pass)) != LB_OK) return st;
+    // Launch plan: on D2Q9 passes of 8, 4 and 2 steps (within the limit),
+    // on D3Q19 passes of 2, then single steps, as runs (steps per launch,
+    // launches).  A state written by a collision holds equal twin
+    // populations (twin<D>, lbm_lattice.h), so a launch reads only the
+    // independent ones unless the state came from lb_init or lb_set_state,
+    // and every launch but the last writes only those; the last launch, and
+    // any launch whose state is checked (LB_OPT_CHECK_INTERVAL), writes all
+    // q, so the state a call leaves (the one every other call sees) is
+    // complete.
+    std::vector<std::pair<int, int64_t>> runs;
+    {
+        int64_t n = 0;
+        if (s->d == 2) {
+            for (int pass = s->steps_per_pass; pass >= 2; pass /= 2) {
+                const int64_t k = (nsteps - n) / pass;
+                if (k > 0) runs.emplace_back(pass, k);
+                n += k * pass;
             }
+        } else if (s->d == 3 && s->steps_per_pass >= lbm::MAX_STEPS_PER_PASS_3D) {
+            const int pass = lbm::MAX_STEPS_PER_PASS_3D;
+            const int64_t k = (nsteps - n) / pass;
+            if (k > 0) runs.emplace_back(pass, k);
+            n += k * pass;
         }
-    } else if (s->d == 3 && s->steps_per_pass >= lbm::MAX_STEPS_PER_PASS_3D) {
-        const int pass = lbm::MAX_STEPS_PER_PASS_3D;
-        for (; n + pass <= nsteps; n += pass) {
-            LB_HIP(lbm::launch_steps3(pass, s->g, s->r, s->buf[s->cur], s->buf[1 - s->cur],
-                                      s->stream),
-                   "multi-step launch");
-            s->cur ^= 1;
-            s->steps += pass;
-            if ((st = after_steps(s, pass)) != LB_OK) return st;
-        }
+        if (n < nsteps) runs.emplace_back(1, nsteps - n);
     }
-    for (; n < nsteps; ++n) {
-        LB_HIP(lbm::launch_step(s->d, s->g, s->r, s->buf[s->cur], s->buf[1 - s->cur], s->stream),
-               "step launch");
-        s->cur ^= 1;
-        ++s->steps;
-        if ((st = after_steps(s, 1)) != LB_OK) return st;
+    lb_status st = LB_OK;
+    for (size_t ri = 0; ri < runs.size(); ++ri) {
+        const int steps = runs[ri].first;
+        for (int64_t t = 0; t < runs[ri].second; ++t) {
+            const bool last = ri + 1 == runs.size() && t + 1 == runs[ri].second;
+            const bool checked =
+                s->check_interval > 0 && s->since_check + steps >= s->check_interval;
+            const bool rin = s->twin_ok;
+            const bool wout = !last && !checked;
+            const double* src = s->buf[s->cur];
+            double* dst = s->buf[1 - s->cur];
+            if (steps == 1)
+                LB_HIP(lbm::launch_step(s->d, s->g, s->r, src, dst, s->stream, rin, wout),
+                       "step launch");
+            else if (s->d == 2)
+                LB_HIP(lbm::launch_steps(steps, s->g, s->r, src, dst, s->stream, rin, wout),
+                       "multi-step launch");
+            else
+                LB_HIP(lbm::launch_steps3(steps, s->g, s->r, src, dst, s->stream, rin, wout),
+                       "multi-step launch");
+            s->cur ^= 1;
+            s->steps += steps;
+            s->twin_ok = true;
+            if ((st = after_steps(s, steps)) != LB_OK) return st;
+        }
     }
     return LB_OK;
 }
@@ -537,6 +561,7 @@ lb_status lb_set_state(lb_solver* s, const double* f_in, int64_t step) {
     s->cur = 0;
     s->steps = step;
     s->since_check = 0;
+    s->twin_ok = false;
     s->inited = true;
     return LB_OK;
 }

@@ -43,8 +43,12 @@ struct Launch {
 };
 Launch launch_shape(int d, const Geo& g);
 
+// rin: src was written by a collision, so each twin population (twin<D>,
+// lbm_lattice.h) is read from the plane of the one it equals; wout: twins
+// are not stored, and dst may then only be read with rin.  Neither changes
+// the result.  The defaults read and write every population.
 hipError_t launch_step(int d, const Geo& g, const Rates& r, const double* src, double* dst,
-                       hipStream_t st);
+                       hipStream_t st, bool rin = false, bool wout = false);
 // nsteps (2, 4 or 8) D2Q9 steps in one pass over HBM (temporal blocking);
 // bitwise equal to nsteps launch_step calls.  A block of MS_THREADS threads
 // (one wave) produces a strip of strip_width(nsteps) columns.
@@ -52,7 +56,7 @@ constexpr int MS_THREADS = 64;
 constexpr int MAX_STEPS_PER_PASS = 8;
 __host__ __device__ constexpr int strip_width(int nsteps) { return MS_THREADS - 2 * nsteps; }
 hipError_t launch_steps(int nsteps, const Geo& g, const Rates& r, const double* src, double* dst,
-                        hipStream_t st);
+                        hipStream_t st, bool rin = false, bool wout = false);
 // The same passes keeping every intermediate state: step j of the pass
 // (1..nsteps) goes to out + (j - 1) stride; the buffers must not overlap src.
 hipError_t launch_steps_all(int nsteps, const Geo& g, const Rates& r, const double* src,
@@ -64,7 +68,7 @@ constexpr int MAX_STEPS_PER_PASS_3D = 2;
 __host__ __device__ constexpr int tile_width3(int nsteps) { return MS3_TX - 2 * nsteps; }
 __host__ __device__ constexpr int tile_height3(int nsteps) { return MS3_TY - 2 * nsteps; }
 hipError_t launch_steps3(int nsteps, const Geo& g, const Rates& r, const double* src, double* dst,
-                         hipStream_t st);
+                         hipStream_t st, bool rin = false, bool wout = false);
 // 1-D grids up to this many nodes run all their steps in one launch with the
 // state in LDS (3 populations x 8 B x 2048 = 48 KiB).
 constexpr int RESIDENT_MAX_1D = 2048;

@@ -125,7 +125,11 @@ __device__ __forceinline__ double block_sum(double v) {
 // ---------------------------------------------------------------------------
 // time step
 // ---------------------------------------------------------------------------
-template <int D>
+// RIN: src was written by a collision, so a twin population is read from
+// the plane of the population it equals (twin<D>); WOUT: the twins are not
+// stored (dst then holds a state that only a RIN read may use).  Both leave
+// the arithmetic, and so the result, bitwise unchanged.
+template <int D, bool RIN = false, bool WOUT = false>
 __global__ void __launch_bounds__(256) k_step(const double* __restrict__ src,
                                               double* __restrict__ dst, Geo g, Rates r) {
     constexpr int Q = Lat<D>::Q;
@@ -134,11 +138,12 @@ __global__ void __launch_bounds__(256) k_step(const double* __restrict__ src,
     const Nbr nb = make_nbr<D>(c, g);
     double f[Q];
 #pragma unroll
-    for (int i = 0; i < Q; ++i) f[i] = src[slot<Q>(i, pull_index<D>(nb, i))];
+    for (int i = 0; i < Q; ++i) f[i] = src[slot<Q>(RIN ? twin<D>(i) : i, pull_index<D>(nb, i))];
     collide<D>(f, r);
     const int k = node_index(g, c);
 #pragma unroll
-    for (int i = 0; i < Q; ++i) __builtin_nontemporal_store(f[i], dst + slot<Q>(i, k));
+    for (int i = 0; i < Q; ++i)
+        if (!WOUT || twin<D>(i) == i) __builtin_nontemporal_store(f[i], dst + slot<Q>(i, k));
 }
 
 // Small 1-D grids (n <= RESIDENT_MAX_1D): the whole state lives in LDS and
@@ -469,7 +474,8 @@ struct MsState {
 // also stores its rows of [ys, ye) to dst - (S - j) stride (the state after
 // j steps, for a caller that keeps every intermediate state).  NT: stage S
 // writes with non-temporal stores (otherwise through the caches).
-template <int S, int P, int ACTIVE, bool ALL, bool OFF32, bool NT = true>
+template <int S, int P, int ACTIVE, bool ALL, bool OFF32, bool NT = true, bool RIN = false,
+          bool WOUT = false>
 __device__ __forceinline__ void ms_row(MsState<S>& st, int k,
                                        const double* __restrict__ src, double* __restrict__ dst,
                                        int nx, int ny, int gx, int ys, int x0, const FoldedRates& r,
@@ -478,7 +484,7 @@ __device__ __forceinline__ void ms_row(MsState<S>& st, int k,
     const int lane = threadIdx.x;
     double f[9];
 #pragma unroll
-    for (int i = 0; i < 9; ++i) f[i] = st.pre[i];
+    for (int i = 0; i < 9; ++i) f[i] = st.pre[RIN ? twin<2>(i) : i];
     {
         // Prefetch the next input row.  In the last iteration the row is not
         // used (its address is wrapped, so in bounds); loading it anyway
@@ -489,7 +495,8 @@ __device__ __forceinline__ void ms_row(MsState<S>& st, int k,
         // stores; two waves per SIMD hide it.
         const MsAddr<OFF32> a(wrapi(ys - S + k + 1, ny) * nx + gx);
 #pragma unroll
-        for (int i = 0; i < 9; ++i) st.pre[i] = a.load(src, i);
+        for (int i = 0; i < 9; ++i)
+            if (!RIN || twin<2>(i) == i) st.pre[i] = a.load(src, i);
     }
 #pragma unroll
     for (int j = 1; j <= S; ++j) {
@@ -518,6 +525,7 @@ __device__ __forceinline__ void ms_row(MsState<S>& st, int k,
                 const MsAddr<OFF32> a(wrapi(ys - 2 * S + k, ny) * nx + x0 - S + lane);
 #pragma unroll
                 for (int i = 0; i < 9; ++i) {
+                    if (WOUT && twin<2>(i) != i) continue;
                     if constexpr (NT)
                         a.store(dst, i, in[i]);
                     else
@@ -540,21 +548,22 @@ __device__ __forceinline__ void ms_row(MsState<S>& st, int k,
     }
 }
 
-template <int S, int K, bool ALL, bool OFF32, bool NT = true>
+template <int S, int K, bool ALL, bool OFF32, bool NT = true, bool RIN = false, bool WOUT = false>
 __device__ __forceinline__ void ms_fill(MsState<S>& st, const double* __restrict__ src,
                                         double* __restrict__ dst, int nx, int ny, int gx, int ys,
                                         int x0, const FoldedRates& r, int nrows, int64_t stride) {
     if constexpr (K < 2 * S) {
-        ms_row<S, K & 1, K / 2, ALL, OFF32, NT>(st, K, src, dst, nx, ny, gx, ys, x0, r, nrows,
-                                                stride);
-        ms_fill<S, K + 1, ALL, OFF32, NT>(st, src, dst, nx, ny, gx, ys, x0, r, nrows, stride);
+        ms_row<S, K & 1, K / 2, ALL, OFF32, NT, RIN, WOUT>(st, K, src, dst, nx, ny, gx, ys, x0, r,
+                                                           nrows, stride);
+        ms_fill<S, K + 1, ALL, OFF32, NT, RIN, WOUT>(st, src, dst, nx, ny, gx, ys, x0, r, nrows,
+                                                     stride);
     }
 }
 
 // Advance rows [ys, ye) (ye > ys) of the columns [x0, x0 + 64 - 2S) of one
 // D2Q9 grid by S steps (reads rows ys-S .. ye-1+S and columns x0-S ..
 // x0+63-S, wrapped periodically).  All 64 lanes of the wave must be active.
-template <int S, bool ALL, bool OFF32, bool NT = true>
+template <int S, bool ALL, bool OFF32, bool NT = true, bool RIN = false, bool WOUT = false>
 __device__ __forceinline__ void ms_tile(const double* __restrict__ src, double* __restrict__ dst,
                                         int nx, int ny, const FoldedRates& r, int x0, int ys,
                                         int ye, int64_t stride = 0) {
@@ -564,24 +573,28 @@ __device__ __forceinline__ void ms_tile(const double* __restrict__ src, double* 
     {
         const MsAddr<OFF32> a(wrapi(ys - S, ny) * nx + gx);
 #pragma unroll
-        for (int i = 0; i < 9; ++i) st.pre[i] = a.load(src, i);
+        for (int i = 0; i < 9; ++i)
+            if (!RIN || twin<2>(i) == i) st.pre[i] = a.load(src, i);
     }
 #pragma unroll
     for (int j = 0; j < S; ++j)
 #pragma unroll
         for (int a = 0; a < 3; ++a) st.z[j][a] = st.u[0][j][a] = st.u[1][j][a] = 0.0;
     const int nrows = ye - ys;
-    ms_fill<S, 0, ALL, OFF32, NT>(st, src, dst, nx, ny, gx, ys, x0, r, nrows, stride);
+    ms_fill<S, 0, ALL, OFF32, NT, RIN, WOUT>(st, src, dst, nx, ny, gx, ys, x0, r, nrows, stride);
     for (int k = 2 * S; k <= kend; k += 2) {
-        ms_row<S, 0, S, ALL, OFF32, NT>(st, k, src, dst, nx, ny, gx, ys, x0, r, nrows, stride);
+        ms_row<S, 0, S, ALL, OFF32, NT, RIN, WOUT>(st, k, src, dst, nx, ny, gx, ys, x0, r, nrows,
+                                                   stride);
         if (k + 1 <= kend)
-            ms_row<S, 1, S, ALL, OFF32, NT>(st, k + 1, src, dst, nx, ny, gx, ys, x0, r, nrows,
-                                            stride);
+            ms_row<S, 1, S, ALL, OFF32, NT, RIN, WOUT>(st, k + 1, src, dst, nx, ny, gx, ys, x0, r,
+                                                       nrows, stride);
     }
 }
 
 // Two waves per SIMD: the register budget (256 per wave) holds S = 8.
-template <int S, bool OFF32>
+// RIN / WOUT: twin populations read from their twins' planes / not stored,
+// as for k_step.
+template <int S, bool OFF32, bool RIN, bool WOUT>
 __global__ void __launch_bounds__(MS_THREADS) __attribute__((amdgpu_waves_per_eu(2)))
 k_steps_d2q9(const double* __restrict__ src,
                                                            double* __restrict__ dst, Geo g,
@@ -590,13 +603,13 @@ k_steps_d2q9(const double* __restrict__ src,
     const int strip = (int)(t % (unsigned)nstrips);
     const int seg = (int)(t / (unsigned)nstrips);
     const int ys = seg * ly;
-    ms_tile<S, false, OFF32>(src, dst, g.nx, g.ny, folded(r), strip * strip_width(S), ys,
-                             min(ys + ly, g.ny), 0);
+    ms_tile<S, false, OFF32, true, RIN, WOUT>(src, dst, g.nx, g.ny, folded(r),
+                                              strip * strip_width(S), ys, min(ys + ly, g.ny), 0);
 }
 
 // The same pass with cached stores, for grids whose two states fit in the
 // Infinity Cache (the next pass then reads its input from there).
-template <int S, bool OFF32>
+template <int S, bool OFF32, bool RIN, bool WOUT>
 __global__ void __launch_bounds__(MS_THREADS) __attribute__((amdgpu_waves_per_eu(2)))
 k_steps_d2q9_cached(const double* __restrict__ src, double* __restrict__ dst, Geo g, Rates r,
                     int ly, int nstrips) {
@@ -604,8 +617,8 @@ k_steps_d2q9_cached(const double* __restrict__ src, double* __restrict__ dst, Ge
     const int strip = (int)(t % (unsigned)nstrips);
     const int seg = (int)(t / (unsigned)nstrips);
     const int ys = seg * ly;
-    ms_tile<S, false, OFF32, false>(src, dst, g.nx, g.ny, folded(r), strip * strip_width(S), ys,
-                                    min(ys + ly, g.ny), 0);
+    ms_tile<S, false, OFF32, false, RIN, WOUT>(src, dst, g.nx, g.ny, folded(r),
+                                               strip * strip_width(S), ys, min(ys + ly, g.ny), 0);
 }
 
 // The same pass writing the state after every one of its S steps: step j to
@@ -816,7 +829,7 @@ constexpr int M3_YMOVERS = m3_yslot(19);
 static_assert(M3_YMOVERS == 10, "D3Q19 has 10 populations with e_y != 0");
 
 // x shift by DPP (pull from lane tx - e_x), then y shift through LDS
-template <int S, int P>
+template <int S, int P, bool RIN, bool WOUT>
 __device__ __forceinline__ void ms3_plane(Ms3State<S>& st, double* lds, int k,
                                           const double* __restrict__ src, double* __restrict__ dst,
                                           const Geo& g, int col, int zs, int x0, int y0,
@@ -825,11 +838,12 @@ __device__ __forceinline__ void ms3_plane(Ms3State<S>& st, double* lds, int k,
     const int64_t plane = (int64_t)g.nx * g.ny;
     double f[19];
 #pragma unroll
-    for (int i = 0; i < 19; ++i) f[i] = st.pre[i];
+    for (int i = 0; i < 19; ++i) f[i] = st.pre[RIN ? twin<3>(i) : i];
     {
         const int64_t base = (int64_t)wrapi(zs - S + k + 1, g.nz) * plane + col;
 #pragma unroll
-        for (int i = 0; i < 19; ++i) st.pre[i] = src[slot<19>(i, base)];
+        for (int i = 0; i < 19; ++i)
+            if (!RIN || twin<3>(i) == i) st.pre[i] = src[slot<19>(i, base)];
     }
     // pull along x (every lane takes part; the edge lanes receive zeros,
     // which reach only halo columns, never a stored output)
@@ -879,7 +893,9 @@ __device__ __forceinline__ void ms3_plane(Ms3State<S>& st, double* lds, int k,
                 const int64_t kk = (int64_t)wrapi(zs - 2 * S + k, g.nz) * plane +
                                    (int64_t)(y0 - S + ty) * g.nx + (x0 - S + tx);
 #pragma unroll
-                for (int i = 0; i < 19; ++i) __builtin_nontemporal_store(in[i], dst + slot<19>(i, kk));
+                for (int i = 0; i < 19; ++i)
+                    if (!WOUT || twin<3>(i) == i)
+                        __builtin_nontemporal_store(in[i], dst + slot<19>(i, kk));
             }
         }
         if (j < S) __syncthreads();
@@ -887,7 +903,7 @@ __device__ __forceinline__ void ms3_plane(Ms3State<S>& st, double* lds, int k,
     if (S & 1) __syncthreads();
 }
 
-template <int S>
+template <int S, bool RIN, bool WOUT>
 __global__ void __launch_bounds__(M3_THREADS) k_steps_d3q19(const double* __restrict__ src,
                                                             double* __restrict__ dst, Geo g,
                                                             Rates r, int lz, int ntx, int nty) {
@@ -905,7 +921,8 @@ __global__ void __launch_bounds__(M3_THREADS) k_steps_d3q19(const double* __rest
     {
         const int64_t base = (int64_t)wrapi(zs - S, g.nz) * g.nx * g.ny + col;
 #pragma unroll
-        for (int i = 0; i < 19; ++i) st.pre[i] = src[slot<19>(i, base)];
+        for (int i = 0; i < 19; ++i)
+            if (!RIN || twin<3>(i) == i) st.pre[i] = src[slot<19>(i, base)];
     }
 #pragma unroll
     for (int j = 0; j < S; ++j) {
@@ -915,8 +932,9 @@ __global__ void __launch_bounds__(M3_THREADS) k_steps_d3q19(const double* __rest
         for (int a = 0; a < M3_ZP; ++a) st.u[0][j][a] = st.u[1][j][a] = 0.0;
     }
     for (int k = 0; k <= kend; k += 2) {
-        ms3_plane<S, 0>(st, lds, k, src, dst, g, col, zs, x0, y0, fr);
-        if (k + 1 <= kend) ms3_plane<S, 1>(st, lds, k + 1, src, dst, g, col, zs, x0, y0, fr);
+        ms3_plane<S, 0, RIN, WOUT>(st, lds, k, src, dst, g, col, zs, x0, y0, fr);
+        if (k + 1 <= kend)
+            ms3_plane<S, 1, RIN, WOUT>(st, lds, k + 1, src, dst, g, col, zs, x0, y0, fr);
     }
 }
 
@@ -1592,9 +1610,30 @@ Launch launch_shape(int d, const Geo& g) {
         return hipGetLastError();                                                 \
     })
 
+// (rin, wout) as template arguments of a kernel.
+template <typename F>
+hipError_t dispatch_io(bool rin, bool wout, F&& f) {
+    if (rin)
+        return wout ? f(std::true_type{}, std::true_type{}) : f(std::true_type{}, std::false_type{});
+    return wout ? f(std::false_type{}, std::true_type{}) : f(std::false_type{}, std::false_type{});
+}
+
 hipError_t launch_step(int d, const Geo& g, const Rates& r, const double* src, double* dst,
-                       hipStream_t st) {
-    return LBM_LAUNCH(k_step, src, dst, g, r);
+                       hipStream_t st, bool rin, bool wout) {
+    return dispatch(d, [&](auto dc) {
+        constexpr int DD = decltype(dc)::value;
+        const Launch L = launch_shape(DD, g);
+        if constexpr (DD == 1) {  // D1Q3 has no twins
+            hipLaunchKernelGGL((k_step<1>), L.grid, L.block, 0, st, src, dst, g, r);
+            return hipGetLastError();
+        } else {
+            return dispatch_io(rin, wout, [&](auto ri, auto wo) {
+                hipLaunchKernelGGL((k_step<DD, decltype(ri)::value, decltype(wo)::value>), L.grid,
+                                   L.block, 0, st, src, dst, g, r);
+                return hipGetLastError();
+            });
+        }
+    });
 }
 
 hipError_t launch_step_resident1(const Geo& g, const Rates& r, const double* src, double* dst,
@@ -1714,22 +1753,25 @@ static int steps_rows(const Geo& g, int nstrips, int min_rows) {
 
 template <int S>
 static hipError_t launch_steps_t(const Geo& g, const Rates& r, const double* src, double* dst,
-                                 hipStream_t st) {
+                                 hipStream_t st, bool rin, bool wout) {
     const int w = strip_width(S);
     const int nstrips = (g.nx + w - 1) / w;
     const int ly = steps_rows(g, nstrips, kMinRows);
     const int nseg = (g.ny + ly - 1) / ly;
     const dim3 grid((unsigned)((int64_t)nstrips * nseg));
-    if (d2q9_cached_stores(g))  // both states fit in 256 MB, so under 4 GiB
-        hipLaunchKernelGGL((k_steps_d2q9_cached<S, true>), grid, dim3(MS_THREADS), 0, st, src, dst,
-                           g, r, ly, nstrips);
-    else if (ms_off32(g))
-        hipLaunchKernelGGL((k_steps_d2q9<S, true>), grid, dim3(MS_THREADS), 0, st, src, dst, g, r,
-                           ly, nstrips);
-    else
-        hipLaunchKernelGGL((k_steps_d2q9<S, false>), grid, dim3(MS_THREADS), 0, st, src, dst, g, r,
-                           ly, nstrips);
-    return hipGetLastError();
+    return dispatch_io(rin, wout, [&](auto ri, auto wo) {
+        constexpr bool RI = decltype(ri)::value, WO = decltype(wo)::value;
+        if (d2q9_cached_stores(g))  // both states fit in 256 MB, so under 4 GiB
+            hipLaunchKernelGGL((k_steps_d2q9_cached<S, true, RI, WO>), grid, dim3(MS_THREADS), 0,
+                               st, src, dst, g, r, ly, nstrips);
+        else if (ms_off32(g))
+            hipLaunchKernelGGL((k_steps_d2q9<S, true, RI, WO>), grid, dim3(MS_THREADS), 0, st, src,
+                               dst, g, r, ly, nstrips);
+        else
+            hipLaunchKernelGGL((k_steps_d2q9<S, false, RI, WO>), grid, dim3(MS_THREADS), 0, st,
+                               src, dst, g, r, ly, nstrips);
+        return hipGetLastError();
+    });
 }
 
 // Planes per segment of a D3Q19 pass: 64, fewer (at least 16) when the grid
@@ -1737,7 +1779,7 @@ static hipError_t launch_steps_t(const Geo& g, const Rates& r, const double* src
 // segments.
 template <int S>
 static hipError_t launch_steps3_t(const Geo& g, const Rates& r, const double* src, double* dst,
-                                  hipStream_t st) {
+                                  hipStream_t st, bool rin, bool wout) {
     const int ntx = (g.nx + tile_width3(S) - 1) / tile_width3(S);
     const int nty = (g.ny + tile_height3(S) - 1) / tile_height3(S);
     int64_t lz = ((int64_t)g.nz * ntx * nty + 1279) / 1280;
@@ -1750,16 +1792,19 @@ static hipError_t launch_steps3_t(const Geo& g, const Rates& r, const double* sr
     const int64_t nseg = (g.nz + lz - 1) / lz;  // every segment non-empty
     const int64_t nb = (int64_t)ntx * nty * nseg;
     if (nb > (int64_t)UINT32_MAX) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_steps_d3q19<S>, dim3((unsigned)nb), dim3(M3_THREADS), 0, st, src, dst, g,
-                       r, (int)lz, ntx, nty);
-    return hipGetLastError();
+    return dispatch_io(rin, wout, [&](auto ri, auto wo) {
+        hipLaunchKernelGGL((k_steps_d3q19<S, decltype(ri)::value, decltype(wo)::value>),
+                           dim3((unsigned)nb), dim3(M3_THREADS), 0, st, src, dst, g, r, (int)lz,
+                           ntx, nty);
+        return hipGetLastError();
+    });
 }
 
 hipError_t launch_steps3(int nsteps, const Geo& g, const Rates& r, const double* src, double* dst,
-                         hipStream_t st) {
+                         hipStream_t st, bool rin, bool wout) {
     if (g.nw != 1) return hipErrorInvalidValue;
     switch (nsteps) {
-        case 2: return launch_steps3_t<2>(g, r, src, dst, st);
+        case 2: return launch_steps3_t<2>(g, r, src, dst, st, rin, wout);
         default: return hipErrorInvalidValue;
     }
 }
@@ -1827,11 +1872,11 @@ hipError_t launch_adjoint_steps(int nsteps, const Geo& g, const Rates& r, const 
 }
 
 hipError_t launch_steps(int nsteps, const Geo& g, const Rates& r, const double* src, double* dst,
-                        hipStream_t st) {
+                        hipStream_t st, bool rin, bool wout) {
     switch (nsteps) {
-        case 2: return launch_steps_t<2>(g, r, src, dst, st);
-        case 4: return launch_steps_t<4>(g, r, src, dst, st);
-        case 8: return launch_steps_t<8>(g, r, src, dst, st);
+        case 2: return launch_steps_t<2>(g, r, src, dst, st, rin, wout);
+        case 4: return launch_steps_t<4>(g, r, src, dst, st, rin, wout);
+        case 8: return launch_steps_t<8>(g, r, src, dst, st, rin, wout);
         default: return hipErrorInvalidValue;
     }
 }

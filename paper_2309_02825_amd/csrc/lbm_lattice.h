@@ -30,6 +30,20 @@
 
 namespace lbm {
 
+// Twin populations.  Theorem 2 relaxes the third-order moments
+// sum e_a e_b^2 f and sum e_a^2 e_b f to their equilibrium 0 at rate 1, so
+// after every collision the two edge populations of a pair (a, b) with
+// opposite velocities are equal: f(-,-) = f(+,+) and f(+,-) = f(-,+) (the
+// difference and the sum of those two moments give them).  The collisions
+// below produce them as the same rounded value, so a state written by a
+// collision holds only 1 + 2d + 2 d(d-1) independent populations per node
+// (7 of 9 for D2Q9, 13 of 19 for D3Q19, 21 of 33 for D4Q33).  twin(i) is the
+// population whose storage plane holds the value of i in such a state: the
+// (+,+) or (-,+) edge of the pair for its (-,-) or (+,-) edge, i itself
+// otherwise.
+template <int D>
+__host__ __device__ constexpr int twin(int i);
+
 // Relaxation rates and weights of Theorem 2 plus the derived constants the
 // kernels use.  Filled on the host (lbm_params.cpp).
 struct Rates {
@@ -98,6 +112,38 @@ template <> struct Lat<4> {
         {0, 1, 0, 1},   {0, -1, 0, 1},  {0, -1, 0, -1}, {0, 1, 0, -1},
         {0, 0, 1, 1},   {0, 0, -1, 1},  {0, 0, -1, -1}, {0, 0, 1, -1}};
 };
+
+// Edge populations come in groups of four per axis pair, (+,+) (-,+) (-,-)
+// (+,-), after the rest and the 2d axis velocities.
+template <int D>
+__host__ __device__ constexpr int twin(int i) {
+    return (i >= 1 + 2 * D && ((i - (1 + 2 * D)) & 3) >= 2) ? i - 2 : i;
+}
+template <int D>
+__host__ __device__ constexpr bool twins_are_opposite() {
+    for (int i = 0; i < Lat<D>::Q; ++i) {
+        const int t = twin<D>(i);
+        if (t == i) continue;
+        for (int a = 0; a < 4; ++a)
+            if (Lat<D>::E[i][a] != -Lat<D>::E[t][a]) return false;
+        if ((Lat<D>::E[i][0] != 0) + (Lat<D>::E[i][1] != 0) + (Lat<D>::E[i][2] != 0) +
+                (Lat<D>::E[i][3] != 0) != 2)
+            return false;
+    }
+    return true;
+}
+static_assert(twins_are_opposite<2>() && twins_are_opposite<3>() && twins_are_opposite<4>(),
+              "a twin is the opposite edge velocity of its pair");
+// Number of distinct populations of a post-collision state.
+template <int D>
+__host__ __device__ constexpr int num_independent() {
+    int n = 0;
+    for (int i = 0; i < Lat<D>::Q; ++i) n += twin<D>(i) == i;
+    return n;
+}
+static_assert(num_independent<2>() == 7 && num_independent<3>() == 13 &&
+                  num_independent<4>() == 21 && num_independent<1>() == 3,
+              "independent populations after a collision");
 
 // Number of axis pairs as an array extent (at least 1).
 template <int D> struct NPairs {

@@ -420,6 +420,39 @@ def test_multi_step_passes_equal_single_steps_3d(grid, steps):
     assert np.array_equal(outs[0], outs[1])
 
 
+@pytest.mark.parametrize("grid,calls", [((130, 67), (19, 10)), ((4096, 40), (8, 17)),
+                                         ((37, 29, 23), (7, 4)), ((64, 9, 40), (2, 3)),
+                                         ((6, 5, 4, 7), (5, 3)), ((3, 3, 3, 3), (1, 2))])
+def test_reduced_state_passes_equal_complete_steps(grid, calls):
+    """Inside one lb_step call the launches read and write only the
+    independent populations of a post-collision state (the twin edge
+    populations are equal); the states lb_step leaves, after a first call
+    from lb_init and a second from a post-collision state, are bitwise those
+    of lb_step_buffers single steps, which read and write every population."""
+    _say("reduced-state passes", grid, calls)
+    SV = _solver_mod()
+    dx, dt, nu, th0, _ = _problem(grid, "random")
+    th0 = torch.from_numpy(th0).to(_dev())
+    s = SV.Solver(grid, dx, dt, nu, device=_dev())
+    s.init(th0, None)
+    ref = SV.Solver(grid, dx, dt, nu, device=_dev())
+    ref.init(th0, None)
+    cur = 0  # reference state in ref.bufs[cur]; ref's own current buffer is bufs[0]
+    for n in calls:
+        s.step(n)
+        for _ in range(n):
+            ref.step_buffers(ref.bufs[cur], ref.bufs[1 - cur])
+            cur ^= 1
+        if cur == 1:
+            ref.bufs[0].copy_(ref.bufs[1])
+            cur = 0
+        got, want = s.get_state(), ref.get_state()
+        torch.cuda.synchronize()
+        assert torch.equal(got, want), (grid, n)
+    s.close()
+    ref.close()
+
+
 def test_run_to_run_bitwise_determinism():
     _say("determinism")
     grid = (257, 129)
