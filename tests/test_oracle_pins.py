@@ -465,6 +465,33 @@ def test_grad_theta_negative_control_post_collision():
     assert e[1] > 0.5 * e[0] and e[1] > 1.0
 
 
+@pytest.mark.parametrize("d", [2, 3, 4])
+@pytest.mark.parametrize("eps", [0.02, 0.08, 0.13, 0.2])
+def test_post_collision_twin_populations_are_equal(d, eps):
+    """Theorem 2 relaxes the third-order moments sum e_a e_b^2 f and
+    sum e_a^2 e_b f to their equilibrium 0 at rate 1, so after a collision
+    the opposite edge populations of every axis pair are equal:
+    f(-e) = f(e) for e = (+,+) and (-,+).  The rows of the oracle's
+    collision matrix C for the two velocities of such a pair coincide (to
+    the rounding of its numerical M^-1), for every distribution; the other
+    rows are all distinct (away from eps = 1/6, where every rate is 1 and C
+    maps any distribution to its equilibrium).  The GPU passes store one of
+    each pair."""
+    L = O.lattice(d, eps)
+    C, _ = O.collision_matrix(d, eps)
+    q = L.q
+    e = L.e
+    twins = 0
+    for i in range(q):
+        for k in range(i + 1, q):
+            same = np.abs(C[i] - C[k]).max() < 1e-14 * np.abs(C).max()
+            is_edge = np.abs(e[i]).sum() == 2
+            opposite = np.array_equal(e[i], -e[k])
+            assert same == (is_edge and opposite), (i, k, e[i], e[k])
+            twins += same
+    assert twins == {2: 2, 3: 6, 4: 12}[d]
+
+
 @pytest.mark.parametrize("d,shape", [(1, (13,)), (2, (9, 7)), (3, (5, 6, 4)), (4, (3, 4, 3, 5))])
 def test_grad_theta_cole_hopf_identity(d, shape):
     """Sec. II: u = -2 nu grad(theta)/theta.  With grad theta from the
