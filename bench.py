@@ -301,34 +301,42 @@ def form_batched(torch, SV, W, dev):
     bs.close()
     mlups = nodes * 1000 / (ms / 1e3) / 1e6
     # launches of the graph: passes of S steps in a mode (-S, rows) or
-    # (-16-S, rows), the remainder as single steps; each launch reads and
-    # writes every instance's state once (144 B per node)
+    # (-16-S, rows), the remainder as single steps; the timed call starts
+    # from a post-collision pool, so each launch reads and writes the 7
+    # independent populations of every node (112 B) and the last one also
+    # writes the two twins (16 B)
     S = (-tile[0] - 16 if tile[0] < -16 else -tile[0]) if tile[0] < 0 else 1
     launches = 1000 // S + 1000 % S
-    pass_bytes = 144 * nodes
-    gbs = launches * pass_bytes / (ms / 1e3) / 1e9
+    pass_bytes = BYTES_PER_NODE_PASS[2] * nodes
+    graph_bytes = launches * pass_bytes + 16 * nodes
+    gbs = graph_bytes / (ms / 1e3) / 1e9
     return {"instances": len(insts), "total_nodes": nodes, "lb_steps": 1000,
             "launch": "one hipGraph of tile-table kernels (S steps per launch for tile "
                       "(-S, rows))", "tile": list(tile), "lb_steps_per_launch": S,
             "launches": launches, "graph_ms": round(ms, 3), "wall_s": round(wall, 4),
             "mlups": round(mlups, 1), "bytes_per_launch": pass_bytes,
+            "graph_algorithmic_bytes": graph_bytes,
             "kernel_us_per_launch": round(ms * 1e3 / launches, 2),
             "achieved_gbs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
+            "complete_state_gbs": round(launches * BYTES_PER_LU[2] * nodes / (ms / 1e3) / 1e9, 1),
             "lu_equivalent_gbs": round(mlups * 144 / 1e3, 1)}
 
 
 def adjoint_backward_bytes(V: int, starts, nsteps: int, spp: int = D2_STEPS_PER_PASS,
                            max_reverse: int = 4) -> int:
-    """Algorithmic HBM bytes of the D2Q9 backward sweep (one node's 9
-    populations are 72 B), following the launch plan of lb_adjoint_segment:
-    a recomputation pass of S steps reads its input state once and writes
-    all S states; a reverse pass of S steps reads and writes lambda once and
-    reads the S states it needs; single steps move three states.  The seed
-    (lb_macro_adjoint: state and g_u read, lambda written) and the adjoint of
-    the initialisation (lambda read, theta0 read, g_theta0 written) are
-    included."""
-    st = 72 * V
-    total = st + 16 * V + st
+    """Algorithmic HBM bytes of the D2Q9 backward sweep, following the launch
+    plan of lb_adjoint_segment.  A checkpoint and lambda are complete (9
+    populations, 72 B per node); the recomputed states are post-collision
+    and move only their 7 independent populations (56 B).  A recomputation
+    pass of S steps reads its input once (the checkpoint for the first pass
+    of a segment) and writes all S states; a reverse pass of S steps reads
+    and writes lambda once and reads the S states it needs; single steps read
+    one state and write one, single adjoint steps read one state and lambda
+    and write lambda.  The seed (lb_macro_adjoint: state and g_u read,
+    lambda written) and the adjoint of the initialisation (lambda read,
+    theta0 read, g_theta0 written) are included."""
+    full, red = 72 * V, 56 * V
+    total = full + 16 * V + full
     ends = list(starts[1:]) + [nsteps]
     for b, e in zip(starts, ends):
         m = e - b
@@ -336,10 +344,12 @@ def adjoint_backward_bytes(V: int, starts, nsteps: int, spp: int = D2_STEPS_PER_
         p = spp
         while p >= 2:
             while j + p <= m:
-                total += st * (1 + p)
+                total += (full if j == 1 else red) + red * p
                 j += p
             p //= 2
-        total += 2 * st * max(m - j, 0)
+        while j < m:
+            total += (full if j == 1 else red) + red
+            j += 1
         left = m - 1
         plan = []
         p = min(spp, max_reverse)
@@ -349,9 +359,11 @@ def adjoint_backward_bytes(V: int, starts, nsteps: int, spp: int = D2_STEPS_PER_
                 left -= p
             p //= 2
         plan.append(1)
-        for p in plan:
-            total += 3 * st if p == 1 else st * (2 + p)
-    total += st + 2 * 8 * V
+        for k, p in enumerate(plan):
+            # the last launch of the plan is the single step at the checkpoint
+            f_bytes = full if k == len(plan) - 1 else red * p
+            total += 2 * full + f_bytes
+    total += full + 2 * 8 * V
     return total
 
 

@@ -156,7 +156,18 @@ lb_status lb_theta_from_velocity(lb_solver* s, const double* u0, double* theta0,
  * moment space, then stream), alternating the two buffers.  How the steps are
  * grouped into launches (passes of several steps, see LB_OPT_STEPS_PER_PASS;
  * on 1-D grids of up to 2048 nodes the whole run in one launch) never changes
- * the result: it is bitwise that of single steps. */
+ * the result: it is bitwise that of single steps.
+ * The relaxation rates of Theorem 2 send the third-order moments to their
+ * equilibrium (zero) at rate 1, so after every collision the two opposite
+ * edge populations of each pair of axes are equal (f for (-1,-1) equals f for
+ * (+1,+1), f for (+1,-1) equals f for (-1,+1)).  Launches inside one call
+ * (D2Q9, D3Q19, D4Q33) therefore store only the other populations and read
+ * each such twin from its partner's plane; the last launch of the call, and a
+ * launch that ends with a check (LB_OPT_CHECK_INTERVAL), store all of them, so
+ * the current state between calls is always complete.  The first launch of a
+ * call reads twins from their partners too unless the state came from lb_init
+ * or lb_set_state: a caller that changes the current buffer in place must go
+ * through lb_set_state. */
 lb_status lb_step(lb_solver* s, int64_t nsteps);
 
 /* LB_FLAG_BOUNDED solvers: advance nsteps >= 0 time steps on the interval.
@@ -268,7 +279,10 @@ lb_status lb_adjoint_step(lb_solver* s, const double* state_n, const double* lam
  * storage layout; the call recomputes f^{n0+1} .. f^{n0+m-1} into `work`
  * (m - 1 consecutive state buffers of lb_state_bytes each; may be NULL when
  * m = 1), bitwise as single steps would (on D2Q9 by multi-step passes that
- * store every step, up to LB_OPT_STEPS_PER_PASS steps each), then applies
+ * store every step, up to LB_OPT_STEPS_PER_PASS steps each) except that the
+ * twin populations (lb_step) are not stored: they equal their partners and
+ * are read from there, so work is scratch whose twin planes keep whatever
+ * they held before.  It then applies
  * the adjoint steps for n = n0+m-1 down to n0.  lambda holds dL/df^{n0+m}
  * on entry and dL/df^{n0} on return; lambda_tmp is a second state buffer
  * used as the ping-pong partner.  lambda on return is bitwise that of m
@@ -373,16 +387,21 @@ lb_status lb_batch_autotune(lb_batch* b, int32_t steps_per_trial, int32_t* best_
                             int32_t* best_ty);
 
 /* Advance every instance nsteps.  With use_graph != 0 the nsteps launches
- * are captured once into a hipGraph (cached per nsteps and starting pool, up
- * to 16 graphs; capturing a 17th first waits for the batch's stream and
- * clears the cache) and replayed with a single hipGraphLaunch. */
+ * are captured once into a hipGraph (cached per nsteps, starting pool and
+ * whether that pool came from lb_batch_init, up to 16 graphs; capturing a 17th
+ * first waits for the batch's stream and clears the cache) and replayed with a
+ * single hipGraphLaunch.  Launches store twin populations as in lb_step: only
+ * the last launch of a call stores all of them, and the first reads them from
+ * their partners unless the pool came from lb_batch_init. */
 lb_status lb_batch_step(lb_batch* b, int64_t nsteps, int32_t use_graph);
 
 /* theta (packed V_b per instance) and u (packed 2 x V_b per instance, at
  * 2*node_offset_b); either may be NULL. */
 lb_status lb_batch_macro(lb_batch* b, double* theta, double* u);
 
-/* Current pool (pool_a or pool_b) and steps taken. */
+/* Current pool (pool_a or pool_b) and steps taken.  The pool is complete
+ * between calls; it is for reading (a changed pool is taken up by
+ * lb_batch_init only). */
 double* lb_batch_current(const lb_batch* b);
 /* Waits for the batch's stream, then frees the cached graphs and tile tables
  * (the pools stay the caller's).  NULL is accepted. */

@@ -9,6 +9,7 @@
 #include <mutex>
 #include <new>
 #include <string>
+#include <tuple>
 #include <utility>
 #include <vector>
 
@@ -658,14 +659,18 @@ static lb_status run_segment(lb_solver* s, const SegmentPlan& plan, const double
     const int64_t se = elements_of(&s->cfg);
     // forward recomputation of the segment's states f^{n0+1} .. f^{n0+m-1}
     // (bitwise single steps): on D2Q9 by multi-step passes that store the
-    // state after each of their steps, the rest one step at a time
+    // state after each of their steps, the rest one step at a time.  Every
+    // state in work comes from a collision, so its twin populations are not
+    // stored and are read from their partners' planes; the checkpoint may be
+    // any state and is read whole.
     const double* prev = ckpt;
     int64_t j = 1;  // next state to produce
     if (s->d == 2) {
         for (int pass = s->steps_per_pass; pass >= 2; pass /= 2) {
             for (; j + pass <= m; j += pass) {
                 double* out = work + (j - 1) * se;
-                LB_HIP(lbm::launch_steps_all(pass, s->g, s->r, prev, out, se, s->stream),
+                LB_HIP(lbm::launch_steps_all(pass, s->g, s->r, prev, out, se, s->stream,
+                                             prev != ckpt, true),
                        "multi-step launch");
                 prev = out + (int64_t)(pass - 1) * se;
             }
@@ -673,7 +678,8 @@ static lb_status run_segment(lb_solver* s, const SegmentPlan& plan, const double
     }
     for (; j < m; ++j) {
         double* nxt = work + (j - 1) * se;
-        LB_HIP(lbm::launch_step(s->d, s->g, s->r, prev, nxt, s->stream), "step launch");
+        LB_HIP(lbm::launch_step(s->d, s->g, s->r, prev, nxt, s->stream, prev != ckpt, true),
+               "step launch");
         prev = nxt;
     }
     double* lin = lambda;
@@ -688,11 +694,11 @@ static lb_status run_segment(lb_solver* s, const SegmentPlan& plan, const double
             const int steps = plan.reverse[(size_t)t];
             if (steps == 1)
                 LB_HIP(lbm::launch_adjoint_step(2, s->g, s->r, ftop, lin, lout, tables + t * T, T,
-                                                s->stream),
+                                                s->stream, N != 1),
                        "adjoint_step launch");
-            else
+            else  // reads f^{n0+N-1} .. f^{n0+N-steps}, all in work (N > steps)
                 LB_HIP(lbm::launch_adjoint_steps(steps, s->g, s->r, lin, lout, ftop, se,
-                                                 tables + t * T, T, s->stream),
+                                                 tables + t * T, T, s->stream, true),
                        "adjoint multi-step launch");
             std::swap(lin, lout);
             N -= steps;
@@ -703,7 +709,7 @@ static lb_status run_segment(lb_solver* s, const SegmentPlan& plan, const double
         for (j = m - 1; j >= 0; --j) {
             const double* fn = j == 0 ? ckpt : work + (j - 1) * se;
             LB_HIP(lbm::launch_adjoint_step(s->d, s->g, s->r, fn, lin, lout, tables + j * T, T,
-                                            s->stream),
+                                            s->stream, j != 0),
                    "adjoint_step launch");
             std::swap(lin, lout);
         }
@@ -797,6 +803,7 @@ struct lb_batch {
     int cur;
     int64_t steps;
     bool inited;
+    bool twin_ok;  // pool[cur] was written by a collision (twins equal their partners)
     BatchInst* d_insts;
     BatchTile* d_tiles;
     int64_t ntiles;
@@ -804,7 +811,8 @@ struct lb_batch {
     int64_t nlin;
     int tx, ty;
     bool off32;  // every instance's state is under 4 GiB
-    std::map<std::pair<int64_t, int>, hipGraphExec_t> graphs;
+    // graphs keyed by (step count, starting pool, twin_ok)
+    std::map<std::tuple<int64_t, int, bool>, hipGraphExec_t> graphs;
 };
 
 // Multi-step tile modes: tx = -S (two-wave LDS strips of
@@ -824,7 +832,7 @@ static void drop_graphs(lb_batch* b) {
     b->graphs.clear();
 }
 
-// Graphs kept per batch (one per step count and starting pool); a new one
+// Graphs kept per batch (one per step count, starting pool and twin_ok); a new one
 // beyond this clears the cache once the work already enqueued has finished.
 constexpr size_t kMaxCachedGraphs = 16;
 
@@ -930,6 +938,7 @@ lb_status lb_batch_create(const lb_config* cfgs, int32_t count, void* hip_stream
     b->cur = 0;
     b->steps = 0;
     b->inited = false;
+    b->twin_ok = false;
     b->d_insts = nullptr;
     b->d_tiles = nullptr;
     b->ntiles = 0;
@@ -981,6 +990,7 @@ lb_status lb_batch_init(lb_batch* b, const double* theta0, const double* grad) {
     b->cur = 0;
     b->steps = 0;
     b->inited = true;
+    b->twin_ok = false;
     return LB_OK;
 }
 
@@ -1008,28 +1018,43 @@ static int64_t batch_launches(const lb_batch* b, int64_t nsteps) {
 }
 
 // Enqueue nsteps steps starting from pool[cur]; *cur_out receives the pool
-// that then holds the state.
+// that then holds the state.  As in lb_step, the first launch reads twins
+// from their partners' planes when the state came from a collision
+// (b->twin_ok), every later launch does, and only the last launch stores the
+// twins, so that the pool a call leaves holds a complete state.
 static lb_status batch_launch_plain(lb_batch* b, int64_t nsteps, hipStream_t st, int cur,
                                     int* cur_out) {
+    const int64_t total = batch_launches(b, nsteps);
+    int64_t launch = 0;
+    auto io = [&](bool* rin, bool* wout) {
+        *rin = launch > 0 || b->twin_ok;
+        *wout = launch + 1 < total;
+        ++launch;
+    };
+    bool rin, wout;
     if (mode_multi_step(b->tx)) {
         const int S = mode_steps(b->tx);
         int64_t n = 0;
         for (; n + S <= nsteps; n += S) {
+            io(&rin, &wout);
             LB_HIP(lbm::launch_batch_steps(S, b->d_insts, b->d_tiles, b->ntiles, b->pool[cur],
-                                           b->pool[1 - cur], b->off32, mode_one_wave(b->tx), st),
+                                           b->pool[1 - cur], b->off32, mode_one_wave(b->tx), st,
+                                           rin, wout),
                    "batch multi-step launch");
             cur ^= 1;
         }
         for (; n < nsteps; ++n) {
+            io(&rin, &wout);
             LB_HIP(lbm::launch_batch_step(b->d_insts, b->d_lin, b->nlin, 0, 0, b->pool[cur],
-                                          b->pool[1 - cur], st),
+                                          b->pool[1 - cur], st, rin, wout),
                    "batch step launch");
             cur ^= 1;
         }
     } else {
         for (int64_t n = 0; n < nsteps; ++n) {
+            io(&rin, &wout);
             LB_HIP(lbm::launch_batch_step(b->d_insts, b->d_tiles, b->ntiles, b->tx, b->ty,
-                                          b->pool[cur], b->pool[1 - cur], st),
+                                          b->pool[cur], b->pool[1 - cur], st, rin, wout),
                    "batch step launch");
             cur ^= 1;
         }
@@ -1048,7 +1073,7 @@ lb_status lb_batch_step(lb_batch* b, int64_t nsteps, int32_t use_graph) {
         lb_status st = batch_launch_plain(b, nsteps, b->stream, b->cur, &next);
         if (st != LB_OK) return st;
     } else {
-        auto key = std::make_pair(nsteps, b->cur);
+        auto key = std::make_tuple(nsteps, b->cur, b->twin_ok);
         auto it = b->graphs.find(key);
         if (it == b->graphs.end()) {
             if (b->graphs.size() >= kMaxCachedGraphs) {
@@ -1077,6 +1102,7 @@ lb_status lb_batch_step(lb_batch* b, int64_t nsteps, int32_t use_graph) {
     }
     b->cur = next;
     b->steps += nsteps;
+    b->twin_ok = true;
     return LB_OK;
 }
 
@@ -1101,18 +1127,21 @@ lb_status lb_batch_autotune(lb_batch* b, int32_t steps_per_trial, int32_t* best_
         st = build_tiles(b, c[0], c[1]);
         if (st != LB_OK) break;
         // Trials always launch pool[cur] -> pool[1-cur]: the current state
-        // is untouched and the other pool is scratch.  Times are per step.
+        // is untouched and the other pool is scratch, written without its
+        // twins as by the passes inside a step call.  Times are per step.
         const int per_launch = mode_multi_step(c[0]) ? mode_steps(c[0]) : 1;
         auto trial = [&](int reps) -> lb_status {
             for (int r = 0; r < reps; ++r) {
                 if (mode_multi_step(c[0]))
                     LB_HIP(lbm::launch_batch_steps(per_launch, b->d_insts, b->d_tiles, b->ntiles,
                                                    b->pool[b->cur], b->pool[1 - b->cur], b->off32,
-                                                   mode_one_wave(c[0]), b->stream),
+                                                   mode_one_wave(c[0]), b->stream, b->twin_ok,
+                                                   true),
                            "batch multi-step launch");
                 else
                     LB_HIP(lbm::launch_batch_step(b->d_insts, b->d_tiles, b->ntiles, b->tx, b->ty,
-                                                  b->pool[b->cur], b->pool[1 - b->cur], b->stream),
+                                                  b->pool[b->cur], b->pool[1 - b->cur], b->stream,
+                                                  b->twin_ok, true),
                            "batch step launch");
             }
             return LB_OK;

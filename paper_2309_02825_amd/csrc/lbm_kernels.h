@@ -60,7 +60,8 @@ hipError_t launch_steps(int nsteps, const Geo& g, const Rates& r, const double* 
 // The same passes keeping every intermediate state: step j of the pass
 // (1..nsteps) goes to out + (j - 1) stride; the buffers must not overlap src.
 hipError_t launch_steps_all(int nsteps, const Geo& g, const Rates& r, const double* src,
-                            double* out, int64_t stride, hipStream_t st);
+                            double* out, int64_t stride, hipStream_t st, bool rin = false,
+                            bool wout = false);
 // nsteps (2) D3Q19 steps in one pass; a block of MS3_TX x MS3_TY threads
 // produces a tile of tile_width3 x tile_height3 columns and marches along z.
 constexpr int MS3_TX = 64, MS3_TY = 8;
@@ -117,9 +118,11 @@ hipError_t launch_macro_adjoint(int d, const Geo& g, const Rates& r, const doubl
                                 const double* g_theta, const double* g_u, double* lambda,
                                 double* partials, hipStream_t st);
 // partials: a table of ntab >= launch_shape(d, g).nblocks entries, all written.
+// rin: state was written by a collision (twins read from their partners'
+// planes, as for launch_step).
 hipError_t launch_adjoint_step(int d, const Geo& g, const Rates& r, const double* state,
                                const double* lam_in, double* lam_out, double* partials,
-                               int64_t ntab, hipStream_t st);
+                               int64_t ntab, hipStream_t st, bool rin = false);
 hipError_t launch_init_adjoint(int d, const Geo& g, const Rates& r, const double* theta0,
                                const double* grad, const double* lambda0, double* g_theta0,
                                double* g_grad, double* partials, hipStream_t st);
@@ -134,7 +137,7 @@ constexpr int MAX_ADJOINT_STEPS_PER_PASS = 4;
 int64_t adjoint_steps_table(const Geo& g);
 hipError_t launch_adjoint_steps(int nsteps, const Geo& g, const Rates& r, const double* lam_in,
                                 double* lam_out, const double* ftop, int64_t stride,
-                                double* partials, int64_t ntab, hipStream_t st);
+                                double* partials, int64_t ntab, hipStream_t st, bool rin = false);
 // m tables of n partials (table j at partials + j n) added to *g_eps table
 // by table, j = m-1 first: bitwise m launch_finalize calls in that order.
 // sums: m doubles of scratch.
@@ -152,8 +155,10 @@ struct BatchTile {
     int x0, y0;         // tile origin
     int pad;            // multi-step tiles: end row of the segment
 };
+// rin / wout as for launch_step.
 hipError_t launch_batch_step(const BatchInst* insts, const BatchTile* tiles, int64_t ntiles,
-                             int tx, int ty, const double* src, double* dst, hipStream_t st);
+                             int tx, int ty, const double* src, double* dst, hipStream_t st,
+                             bool rin = false, bool wout = false);
 // nsteps (2, 4 or 8) steps per pass; tiles (inst, x0, y0, y1) cover strips of
 // batch_strip_width(nsteps) columns (blocks of LW_THREADS threads).
 constexpr int LW_THREADS = 128;
@@ -164,6 +169,6 @@ __host__ __device__ constexpr int batch_strip_width(int nsteps) { return LW_THRE
 // batch_strip_width(nsteps) columns run by the two-wave LDS routine.
 hipError_t launch_batch_steps(int nsteps, const BatchInst* insts, const BatchTile* tiles,
                               int64_t ntiles, const double* src, double* dst, bool off32,
-                              bool one_wave, hipStream_t st);
+                              bool one_wave, hipStream_t st, bool rin = false, bool wout = false);
 
 }  // namespace lbm

@@ -541,7 +541,8 @@ __device__ __forceinline__ void ms_row(MsState<S>& st, int k,
                     const MsAddr<OFF32> a((ys + rr) * nx + x0 - S + lane);
                     double* out = dst - (int64_t)(S - j) * stride;
 #pragma unroll
-                    for (int i = 0; i < 9; ++i) a.store(out, i, in[i]);
+                    for (int i = 0; i < 9; ++i)
+                        if (!WOUT || twin<2>(i) == i) a.store(out, i, in[i]);
                 }
             }
         }
@@ -623,7 +624,8 @@ k_steps_d2q9_cached(const double* __restrict__ src, double* __restrict__ dst, Ge
 
 // The same pass writing the state after every one of its S steps: step j to
 // out + (j - 1) stride (the adjoint's recomputation of a checkpoint segment).
-template <int S, bool OFF32>
+// RIN / WOUT as for k_step (WOUT applies to every state written).
+template <int S, bool OFF32, bool RIN, bool WOUT>
 __global__ void __launch_bounds__(MS_THREADS) __attribute__((amdgpu_waves_per_eu(2)))
 k_steps_d2q9_all(const double* __restrict__ src, double* __restrict__ out, int64_t stride, Geo g,
                  Rates r, int ly, int nstrips) {
@@ -631,8 +633,9 @@ k_steps_d2q9_all(const double* __restrict__ src, double* __restrict__ out, int64
     const int strip = (int)(t % (unsigned)nstrips);
     const int seg = (int)(t / (unsigned)nstrips);
     const int ys = seg * ly;
-    ms_tile<S, true, OFF32>(src, out + (int64_t)(S - 1) * stride, g.nx, g.ny, folded(r),
-                     strip * strip_width(S), ys, min(ys + ly, g.ny), stride);
+    ms_tile<S, true, OFF32, true, RIN, WOUT>(src, out + (int64_t)(S - 1) * stride, g.nx, g.ny,
+                                             folded(r), strip * strip_width(S), ys,
+                                             min(ys + ly, g.ny), stride);
 }
 
 // ---------------------------------------------------------------------------
@@ -646,7 +649,9 @@ k_steps_d2q9_all(const double* __restrict__ src, double* __restrict__ out, int64
 // right).  Stage j produces lambda^{N-j} from lambda^{N-j+1}; at the nodes the
 // wave owns it also adds the eps part <mu, (dC/deps) f^{N-j}> (through the
 // dual moments of mu, eps_part_d2q9), with f^{N-j}
-// pulled from its state buffer at ftop - (j - 1) stride (ftop = f^{N-1}).
+// pulled from its state buffer at ftop - (j - 1) stride (ftop = f^{N-1});
+// RIN: those states were written by a collision and twin populations are
+// read from their partners' planes (as in k_step).
 // Each lane sums the eps parts of its nodes over all stages and rows in a
 // fixed order; the wave's sum goes to partials[block], and the blocks from
 // nblocks to ntab - 1 write zeros, so the table always holds ntab entries.
@@ -661,15 +666,17 @@ struct AsState : MsState<S> {
 };
 
 // f^{N-j} pulled at node (x, y): population i from (x - e_i, y - e_i).
+template <bool RIN>
 __device__ __forceinline__ void as_load_f(double (&fn)[9], const double* __restrict__ fs, int x,
                                           int y, int nx, int ny) {
     const int rows[3] = {wrapi(y + 1, ny) * nx, y * nx, wrapi(y - 1, ny) * nx};
     const int cols[3] = {x == nx - 1 ? 0 : x + 1, x, x == 0 ? nx - 1 : x - 1};
 #pragma unroll
-    for (int i = 0; i < 9; ++i) fn[i] = fs[slot<9>(i, rows[ms_ey(i) + 1] + cols[ms_ex(i) + 1])];
+    for (int i = 0; i < 9; ++i)
+        fn[i] = fs[slot<9>(RIN ? twin<2>(i) : i, rows[ms_ey(i) + 1] + cols[ms_ex(i) + 1])];
 }
 
-template <int S, int P, int ACTIVE>
+template <int S, int P, int ACTIVE, bool RIN>
 __device__ __forceinline__ void as_row(AsState<S>& st, double& ge, int k,
                                        const double* __restrict__ src, double* __restrict__ dst,
                                        const double* __restrict__ ftop, int64_t stride, int nx,
@@ -723,22 +730,23 @@ __device__ __forceinline__ void as_row(AsState<S>& st, double& ge, int k,
     for (int j = 1; j <= S; ++j) {
         const int rr = k + 1 - S - j;
         if (own && rr >= 0 && rr < nrows)
-            as_load_f(st.fp[j - 1], ftop - (int64_t)(j - 1) * stride, x, ys + rr, nx, ny);
+            as_load_f<RIN>(st.fp[j - 1], ftop - (int64_t)(j - 1) * stride, x, ys + rr, nx, ny);
     }
 }
 
-template <int S, int K>
+template <int S, int K, bool RIN>
 __device__ __forceinline__ void as_fill(AsState<S>& st, double& ge,
                                         const double* __restrict__ src, double* __restrict__ dst,
                                         const double* __restrict__ ftop, int64_t stride, int nx,
                                         int ny, int gx, int ys, int x0, int nrows, const Rates& r) {
     if constexpr (K < 2 * S) {
-        as_row<S, K & 1, K / 2>(st, ge, K, src, dst, ftop, stride, nx, ny, gx, ys, x0, nrows, r);
-        as_fill<S, K + 1>(st, ge, src, dst, ftop, stride, nx, ny, gx, ys, x0, nrows, r);
+        as_row<S, K & 1, K / 2, RIN>(st, ge, K, src, dst, ftop, stride, nx, ny, gx, ys, x0, nrows,
+                                     r);
+        as_fill<S, K + 1, RIN>(st, ge, src, dst, ftop, stride, nx, ny, gx, ys, x0, nrows, r);
     }
 }
 
-template <int S>
+template <int S, bool RIN>
 __global__ void __launch_bounds__(MS_THREADS) __attribute__((amdgpu_waves_per_eu(2)))
 k_adjoint_steps_d2q9(const double* __restrict__ src, double* __restrict__ dst,
                      const double* __restrict__ ftop, int64_t stride,
@@ -768,11 +776,12 @@ k_adjoint_steps_d2q9(const double* __restrict__ src, double* __restrict__ dst,
         for (int i = 0; i < 9; ++i) st.fp[j][i] = 0.0;
     }
     double ge = 0.0;
-    as_fill<S, 0>(st, ge, src, dst, ftop, stride, nx, ny, gx, ys, x0, nrows, r);
+    as_fill<S, 0, RIN>(st, ge, src, dst, ftop, stride, nx, ny, gx, ys, x0, nrows, r);
     for (int k = 2 * S; k <= kend; k += 2) {
-        as_row<S, 0, S>(st, ge, k, src, dst, ftop, stride, nx, ny, gx, ys, x0, nrows, r);
+        as_row<S, 0, S, RIN>(st, ge, k, src, dst, ftop, stride, nx, ny, gx, ys, x0, nrows, r);
         if (k + 1 <= kend)
-            as_row<S, 1, S>(st, ge, k + 1, src, dst, ftop, stride, nx, ny, gx, ys, x0, nrows, r);
+            as_row<S, 1, S, RIN>(st, ge, k + 1, src, dst, ftop, stride, nx, ny, gx, ys, x0, nrows,
+                                 r);
     }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) ge += __shfl_xor(ge, o, 64);
@@ -1149,7 +1158,8 @@ __global__ void __launch_bounds__(256) k_macro_adjoint(const double* __restrict_
 
 // lam_out(x) = C^T mu(x), mu_i(x) = lam_in_i(x + e_i); eps part <mu, C' f^n(x)>.
 // One partial per block; blocks past the grid up to ntab - 1 are written zero.
-template <int D>
+// RIN: the state was written by a collision (twins read as in k_step).
+template <int D, bool RIN = false>
 __global__ void __launch_bounds__(256) k_adjoint_step(const double* __restrict__ state,
                                                       const double* __restrict__ lin,
                                                       double* __restrict__ lout,
@@ -1164,7 +1174,7 @@ __global__ void __launch_bounds__(256) k_adjoint_step(const double* __restrict__
         double f[Q], mu[Q];
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
-            f[i] = state[slot<Q>(i, pull_index<D>(nb, i))];
+            f[i] = state[slot<Q>(RIN ? twin<D>(i) : i, pull_index<D>(nb, i))];
             mu[i] = lin[slot<Q>(i, push_index<D>(nb, i))];
         }
         double df[Q];
@@ -1380,6 +1390,7 @@ __global__ void __launch_bounds__(256) k_theta_from_potential(const double* __re
 // One block per tile.  tx > 0: a tx x (256/tx) rectangle of one instance at
 // (x0, y0); tx == 0: 256 consecutive node indices of one instance starting at
 // x0, crossing row ends, so no lane idles except at the instance's last tile.
+template <bool RIN, bool WOUT>
 __global__ void __launch_bounds__(256) k_batch_step(const BatchInst* __restrict__ insts,
                                                     const BatchTile* __restrict__ tiles, int tx,
                                                     int log2tx, const double* __restrict__ src,
@@ -1411,12 +1422,13 @@ __global__ void __launch_bounds__(256) k_batch_step(const BatchInst* __restrict_
     double* d = dst + in.offset;
     double f[Q];
 #pragma unroll
-    for (int i = 0; i < Q; ++i) f[i] = s[slot<Q>(i, pull_index<2>(nb, i))];
+    for (int i = 0; i < Q; ++i) f[i] = s[slot<Q>(RIN ? twin<2>(i) : i, pull_index<2>(nb, i))];
     const Rates r = in.r;
     collide<2>(f, r);
     const int k = y * g.nx + x;
 #pragma unroll
-    for (int i = 0; i < Q; ++i) __builtin_nontemporal_store(f[i], d + slot<Q>(i, k));
+    for (int i = 0; i < Q; ++i)
+        if (!WOUT || twin<2>(i) == i) __builtin_nontemporal_store(f[i], d + slot<Q>(i, k));
 }
 
 // ---------------------------------------------------------------------------
@@ -1455,7 +1467,7 @@ struct LwState {
 };
 
 // One iteration k of the march; P = k & 1.
-template <int S, int P, bool OFF32>
+template <int S, int P, bool OFF32, bool RIN, bool WOUT>
 __device__ __forceinline__ void lw_row(LwState<S>& st, double (&lds)[2][6][LW_THREADS], int k,
                                        int kend, const double* __restrict__ src,
                                        double* __restrict__ dst, int nx, int ny, int gx, int ys,
@@ -1464,13 +1476,14 @@ __device__ __forceinline__ void lw_row(LwState<S>& st, double (&lds)[2][6][LW_TH
     const int tid = threadIdx.x;
     double f[9];
 #pragma unroll
-    for (int i = 0; i < 9; ++i) f[i] = st.pre[i];
+    for (int i = 0; i < 9; ++i) f[i] = st.pre[RIN ? twin<2>(i) : i];
     // (an unconditional prefetch as in ms_row raised this kernel to 260
     // VGPRs, one wave per SIMD, and cost 20 % on the batch)
     if (k < kend) {
         const MsAddr<OFF32> a(wrapi(ys - S + k + 1, ny) * nx + gx);
 #pragma unroll
-        for (int i = 0; i < 9; ++i) st.pre[i] = a.load(src, i);
+        for (int i = 0; i < 9; ++i)
+            if (!RIN || twin<2>(i) == i) st.pre[i] = a.load(src, i);
     }
 #pragma unroll
     for (int i = 0; i < 9; ++i)
@@ -1512,7 +1525,8 @@ __device__ __forceinline__ void lw_row(LwState<S>& st, double (&lds)[2][6][LW_TH
             } else if (tid >= S && tid < S + W && x0 - S + tid < nx) {
                 const MsAddr<OFF32> a(wrapi(ys - 2 * S + k, ny) * nx + x0 - S + tid);
 #pragma unroll
-                for (int i = 0; i < 9; ++i) a.store(dst, i, in[i]);
+                for (int i = 0; i < 9; ++i)
+                    if (!WOUT || twin<2>(i) == i) a.store(dst, i, in[i]);
             }
         }
         if (j < S) __syncthreads();
@@ -1524,7 +1538,7 @@ __device__ __forceinline__ void lw_row(LwState<S>& st, double (&lds)[2][6][LW_TH
 // Advance rows [ys, ye) of the columns [x0, x0 + LW_THREADS - 2S) of one
 // D2Q9 grid by S steps (reads rows ys-S .. ye-1+S and columns x0-S ..
 // x0+LW_THREADS-S-1, wrapped periodically).
-template <int S, bool OFF32>
+template <int S, bool OFF32, bool RIN, bool WOUT>
 __device__ __forceinline__ void lw_tile(const double* __restrict__ src, double* __restrict__ dst,
                                         int nx, int ny, const FoldedRates& r, int x0, int ys, int ye,
                                         double (&lds)[2][6][LW_THREADS]) {
@@ -1534,16 +1548,17 @@ __device__ __forceinline__ void lw_tile(const double* __restrict__ src, double* 
     {
         const MsAddr<OFF32> a(wrapi(ys - S, ny) * nx + gx);
 #pragma unroll
-        for (int i = 0; i < 9; ++i) st.pre[i] = a.load(src, i);
+        for (int i = 0; i < 9; ++i)
+            if (!RIN || twin<2>(i) == i) st.pre[i] = a.load(src, i);
     }
 #pragma unroll
     for (int j = 0; j < S; ++j)
 #pragma unroll
         for (int a = 0; a < 3; ++a) st.z[j][a] = st.u[0][j][a] = st.u[1][j][a] = 0.0;
     for (int k = 0; k <= kend; k += 2) {
-        lw_row<S, 0, OFF32>(st, lds, k, kend, src, dst, nx, ny, gx, ys, x0, r);
+        lw_row<S, 0, OFF32, RIN, WOUT>(st, lds, k, kend, src, dst, nx, ny, gx, ys, x0, r);
         if (k + 1 <= kend)
-            lw_row<S, 1, OFF32>(st, lds, k + 1, kend, src, dst, nx, ny, gx, ys, x0, r);
+            lw_row<S, 1, OFF32, RIN, WOUT>(st, lds, k + 1, kend, src, dst, nx, ny, gx, ys, x0, r);
     }
 }
 
@@ -1551,7 +1566,8 @@ __device__ __forceinline__ void lw_tile(const double* __restrict__ src, double* 
 // Batched S-step pass: tile (inst, x0, y0, y1) = rows [y0, y1) of the strip
 // at x0 (batch_strip_width(S) columns) of one instance.  OFF32: every
 // instance's state is under 4 GiB (MsAddr<true> from the instance's start).
-template <int S, bool OFF32>
+// RIN / WOUT as for k_step.
+template <int S, bool OFF32, bool RIN, bool WOUT>
 __global__ void __launch_bounds__(LW_THREADS) k_batch_steps(const BatchInst* __restrict__ insts,
                                                             const BatchTile* __restrict__ tiles,
                                                             const double* __restrict__ src,
@@ -1559,20 +1575,20 @@ __global__ void __launch_bounds__(LW_THREADS) k_batch_steps(const BatchInst* __r
     __shared__ double lds[2][6][LW_THREADS];
     const BatchTile t = tiles[xcd_remap(blockIdx.x, gridDim.x)];
     const BatchInst& in = insts[t.inst];
-    lw_tile<S, OFF32>(src + in.offset, dst + in.offset, in.nx, in.ny, folded(in.r), t.x0, t.y0,
-                      t.pad, lds);
+    lw_tile<S, OFF32, RIN, WOUT>(src + in.offset, dst + in.offset, in.nx, in.ny, folded(in.r),
+                                 t.x0, t.y0, t.pad, lds);
 }
 
 // The same pass with the one-wave march of k_steps_d2q9: tile (inst, x0,
 // y0, y1) = rows [y0, y1) of the strip at x0 (strip_width(S) columns).
-template <int S, bool OFF32>
+template <int S, bool OFF32, bool RIN, bool WOUT>
 __global__ void __launch_bounds__(MS_THREADS) __attribute__((amdgpu_waves_per_eu(2)))
 k_batch_steps_w(const BatchInst* __restrict__ insts, const BatchTile* __restrict__ tiles,
                 const double* __restrict__ src, double* __restrict__ dst) {
     const BatchTile t = tiles[xcd_remap(blockIdx.x, gridDim.x)];
     const BatchInst& in = insts[t.inst];
-    ms_tile<S, false, OFF32>(src + in.offset, dst + in.offset, in.nx, in.ny, folded(in.r), t.x0,
-                             t.y0, t.pad, 0);
+    ms_tile<S, false, OFF32, true, RIN, WOUT>(src + in.offset, dst + in.offset, in.nx, in.ny,
+                                              folded(in.r), t.x0, t.y0, t.pad, 0);
 }
 
 template <typename F>
@@ -1811,26 +1827,30 @@ hipError_t launch_steps3(int nsteps, const Geo& g, const Rates& r, const double*
 
 template <int S>
 static hipError_t launch_steps_all_t(const Geo& g, const Rates& r, const double* src, double* out,
-                                     int64_t stride, hipStream_t st) {
+                                     int64_t stride, hipStream_t st, bool rin, bool wout) {
     const int w = strip_width(S);
     const int nstrips = (g.nx + w - 1) / w;
     const int ly = steps_rows(g, nstrips, kMinRowsSegment);
-    const int nseg = (g.ny + ly - 1) / ly;
-    if (ms_off32(g))
-        hipLaunchKernelGGL((k_steps_d2q9_all<S, true>), dim3((unsigned)((int64_t)nstrips * nseg)),
-                           dim3(MS_THREADS), 0, st, src, out, stride, g, r, ly, nstrips);
-    else
-        hipLaunchKernelGGL((k_steps_d2q9_all<S, false>), dim3((unsigned)((int64_t)nstrips * nseg)),
-                           dim3(MS_THREADS), 0, st, src, out, stride, g, r, ly, nstrips);
-    return hipGetLastError();
+    const dim3 grid((unsigned)((int64_t)nstrips * ((g.ny + ly - 1) / ly)));
+    const bool off32 = ms_off32(g);
+    return dispatch_io(rin, wout, [&](auto ri, auto wo) {
+        constexpr bool RI = decltype(ri)::value, WO = decltype(wo)::value;
+        if (off32)
+            hipLaunchKernelGGL((k_steps_d2q9_all<S, true, RI, WO>), grid, dim3(MS_THREADS), 0, st,
+                               src, out, stride, g, r, ly, nstrips);
+        else
+            hipLaunchKernelGGL((k_steps_d2q9_all<S, false, RI, WO>), grid, dim3(MS_THREADS), 0, st,
+                               src, out, stride, g, r, ly, nstrips);
+        return hipGetLastError();
+    });
 }
 
 hipError_t launch_steps_all(int nsteps, const Geo& g, const Rates& r, const double* src,
-                            double* out, int64_t stride, hipStream_t st) {
+                            double* out, int64_t stride, hipStream_t st, bool rin, bool wout) {
     switch (nsteps) {
-        case 2: return launch_steps_all_t<2>(g, r, src, out, stride, st);
-        case 4: return launch_steps_all_t<4>(g, r, src, out, stride, st);
-        case 8: return launch_steps_all_t<8>(g, r, src, out, stride, st);
+        case 2: return launch_steps_all_t<2>(g, r, src, out, stride, st, rin, wout);
+        case 4: return launch_steps_all_t<4>(g, r, src, out, stride, st, rin, wout);
+        case 8: return launch_steps_all_t<8>(g, r, src, out, stride, st, rin, wout);
         default: return hipErrorInvalidValue;
     }
 }
@@ -1850,23 +1870,34 @@ int64_t adjoint_steps_table(const Geo& g) {
 template <int S>
 static hipError_t launch_adjoint_steps_t(const Geo& g, const Rates& r, const double* lam_in,
                                          double* lam_out, const double* ftop, int64_t stride,
-                                         double* partials, int64_t ntab, hipStream_t st) {
+                                         double* partials, int64_t ntab, hipStream_t st,
+                                         bool rin) {
     const int w = strip_width(S);
     const int nstrips = (g.nx + w - 1) / w;
     const int ly = steps_rows(g, nstrips, kMinRowsSegment);
     const int64_t nb = (int64_t)nstrips * ((g.ny + ly - 1) / ly);
     if (nb > ntab || ntab > (int64_t)INT32_MAX) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_adjoint_steps_d2q9<S>, dim3((unsigned)nb), dim3(MS_THREADS), 0, st,
-                       lam_in, lam_out, ftop, stride, partials, (int)ntab, g, r, ly, nstrips);
+    if (rin)
+        hipLaunchKernelGGL((k_adjoint_steps_d2q9<S, true>), dim3((unsigned)nb), dim3(MS_THREADS),
+                           0, st, lam_in, lam_out, ftop, stride, partials, (int)ntab, g, r, ly,
+                           nstrips);
+    else
+        hipLaunchKernelGGL((k_adjoint_steps_d2q9<S, false>), dim3((unsigned)nb), dim3(MS_THREADS),
+                           0, st, lam_in, lam_out, ftop, stride, partials, (int)ntab, g, r, ly,
+                           nstrips);
     return hipGetLastError();
 }
 
 hipError_t launch_adjoint_steps(int nsteps, const Geo& g, const Rates& r, const double* lam_in,
                                 double* lam_out, const double* ftop, int64_t stride,
-                                double* partials, int64_t ntab, hipStream_t st) {
+                                double* partials, int64_t ntab, hipStream_t st, bool rin) {
     switch (nsteps) {
-        case 2: return launch_adjoint_steps_t<2>(g, r, lam_in, lam_out, ftop, stride, partials, ntab, st);
-        case 4: return launch_adjoint_steps_t<4>(g, r, lam_in, lam_out, ftop, stride, partials, ntab, st);
+        case 2:
+            return launch_adjoint_steps_t<2>(g, r, lam_in, lam_out, ftop, stride, partials, ntab,
+                                             st, rin);
+        case 4:
+            return launch_adjoint_steps_t<4>(g, r, lam_in, lam_out, ftop, stride, partials, ntab,
+                                             st, rin);
         default: return hipErrorInvalidValue;
     }
 }
@@ -1958,9 +1989,20 @@ hipError_t launch_macro_adjoint(int d, const Geo& g, const Rates& r, const doubl
 
 hipError_t launch_adjoint_step(int d, const Geo& g, const Rates& r, const double* state,
                                const double* lam_in, double* lam_out, double* partials,
-                               int64_t ntab, hipStream_t st) {
+                               int64_t ntab, hipStream_t st, bool rin) {
     if (ntab < launch_shape(d, g).nblocks) return hipErrorInvalidValue;
-    return LBM_LAUNCH(k_adjoint_step, state, lam_in, lam_out, partials, ntab, g, r);
+    return dispatch(d, [&](auto dc) {
+        constexpr int DD = decltype(dc)::value;
+        const Launch L = launch_shape(DD, g);
+        constexpr bool HAS_TWINS = DD > 1;  // D1Q3 has none
+        if (HAS_TWINS && rin)
+            hipLaunchKernelGGL((k_adjoint_step<DD, HAS_TWINS>), L.grid, L.block, 0, st, state,
+                               lam_in, lam_out, partials, ntab, g, r);
+        else
+            hipLaunchKernelGGL((k_adjoint_step<DD, false>), L.grid, L.block, 0, st, state, lam_in,
+                               lam_out, partials, ntab, g, r);
+        return hipGetLastError();
+    });
 }
 
 hipError_t launch_init_adjoint(int d, const Geo& g, const Rates& r, const double* theta0,
@@ -1985,25 +2027,21 @@ hipError_t launch_finalize_tables(const double* partials, int64_t n, int64_t m, 
     return hipGetLastError();
 }
 
-template <bool OFF32>
+template <bool OFF32, bool RIN, bool WOUT>
 static hipError_t launch_batch_steps_t(int nsteps, const BatchInst* insts, const BatchTile* tiles,
                                        int64_t ntiles, const double* src, double* dst,
                                        bool one_wave, hipStream_t st) {
-    if (one_wave) {
-        const dim3 grid((unsigned)ntiles), block(MS_THREADS);
-        switch (nsteps) {
-            case 2: hipLaunchKernelGGL((k_batch_steps_w<2, OFF32>), grid, block, 0, st, insts, tiles, src, dst); break;
-            case 4: hipLaunchKernelGGL((k_batch_steps_w<4, OFF32>), grid, block, 0, st, insts, tiles, src, dst); break;
-            case 8: hipLaunchKernelGGL((k_batch_steps_w<8, OFF32>), grid, block, 0, st, insts, tiles, src, dst); break;
-            default: return hipErrorInvalidValue;
-        }
-        return hipGetLastError();
-    }
-    const dim3 grid((unsigned)ntiles), block(LW_THREADS);
-    switch (nsteps) {
-        case 2: hipLaunchKernelGGL((k_batch_steps<2, OFF32>), grid, block, 0, st, insts, tiles, src, dst); break;
-        case 4: hipLaunchKernelGGL((k_batch_steps<4, OFF32>), grid, block, 0, st, insts, tiles, src, dst); break;
-        case 8: hipLaunchKernelGGL((k_batch_steps<8, OFF32>), grid, block, 0, st, insts, tiles, src, dst); break;
+    const dim3 grid((unsigned)ntiles), block(one_wave ? MS_THREADS : LW_THREADS);
+    switch (nsteps * (one_wave ? -1 : 1)) {
+#define LBM_BATCH_CASE(S)                                                                      \
+    case S: hipLaunchKernelGGL((k_batch_steps<S, OFF32, RIN, WOUT>), grid, block, 0, st, insts, \
+                               tiles, src, dst); break;                                        \
+    case -S: hipLaunchKernelGGL((k_batch_steps_w<S, OFF32, RIN, WOUT>), grid, block, 0, st,    \
+                                insts, tiles, src, dst); break;
+        LBM_BATCH_CASE(2)
+        LBM_BATCH_CASE(4)
+        LBM_BATCH_CASE(8)
+#undef LBM_BATCH_CASE
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -2011,22 +2049,30 @@ static hipError_t launch_batch_steps_t(int nsteps, const BatchInst* insts, const
 
 hipError_t launch_batch_steps(int nsteps, const BatchInst* insts, const BatchTile* tiles,
                               int64_t ntiles, const double* src, double* dst, bool off32,
-                              bool one_wave, hipStream_t st) {
+                              bool one_wave, hipStream_t st, bool rin, bool wout) {
     if (ntiles <= 0) return hipSuccess;
-    return off32 ? launch_batch_steps_t<true>(nsteps, insts, tiles, ntiles, src, dst, one_wave, st)
-                 : launch_batch_steps_t<false>(nsteps, insts, tiles, ntiles, src, dst, one_wave,
-                                               st);
+    return dispatch_io(rin, wout, [&](auto ri, auto wo) {
+        constexpr bool RI = decltype(ri)::value, WO = decltype(wo)::value;
+        return off32 ? launch_batch_steps_t<true, RI, WO>(nsteps, insts, tiles, ntiles, src, dst,
+                                                          one_wave, st)
+                     : launch_batch_steps_t<false, RI, WO>(nsteps, insts, tiles, ntiles, src, dst,
+                                                           one_wave, st);
+    });
 }
 
 hipError_t launch_batch_step(const BatchInst* insts, const BatchTile* tiles, int64_t ntiles,
-                             int tx, int ty, const double* src, double* dst, hipStream_t st) {
+                             int tx, int ty, const double* src, double* dst, hipStream_t st,
+                             bool rin, bool wout) {
     (void)ty;
     int log2tx = 0;
     while (tx > 0 && (1 << log2tx) < tx) ++log2tx;
     if (ntiles <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_batch_step, dim3((unsigned)ntiles), dim3(256), 0, st, insts, tiles, tx,
-                       log2tx, src, dst);
-    return hipGetLastError();
+    return dispatch_io(rin, wout, [&](auto ri, auto wo) {
+        hipLaunchKernelGGL((k_batch_step<decltype(ri)::value, decltype(wo)::value>),
+                           dim3((unsigned)ntiles), dim3(256), 0, st, insts, tiles, tx, log2tx, src,
+                           dst);
+        return hipGetLastError();
+    });
 }
 
 }  // namespace lbm
