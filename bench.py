@@ -78,11 +78,15 @@ def log(*a):
 def d2_kernel(steps: int, nodes: int) -> str:
     """Name of the D2Q9 pass kernel as the trace shows it: the variant with
     cached stores runs when both state buffers fit in the 256 MB Infinity
-    Cache, the one with 32-bit offsets when a state buffer is under 4 GiB."""
+    Cache, the one with 32-bit offsets when a state buffer is under 4 GiB.
+    The launches between the first and the last of an lb_step call read and
+    write only the independent populations (the last two template
+    arguments)."""
     state_bytes = 9 * ((nodes + 4095) // 4096) * 4096 * 8
     if 2 * state_bytes <= 256 << 20:
-        return f"k_steps_d2q9_cached<{steps}, true>"
-    return f"k_steps_d2q9<{steps}, {'true' if state_bytes <= 0xFFFFFFFF else 'false'}>"
+        return f"k_steps_d2q9_cached<{steps}, true, true, true>"
+    return (f"k_steps_d2q9<{steps}, {'true' if state_bytes <= 0xFFFFFFFF else 'false'}, "
+            "true, true>")
 
 
 def kernel_source_hash() -> str:
@@ -285,7 +289,7 @@ def form_batched(torch, SV, W, dev):
         gr.append(g)
     bs.init(th, gr)
     del th, gr
-    tile = bs.autotune(3)
+    tile = bs.autotune(6)
     bs.step(1000, graph=True)        # capture + warm
     stream = torch.cuda.current_stream()
     timer = Timer(torch, stream)
@@ -544,7 +548,7 @@ def main():
     # what the roofline fraction is taken against
     per_launch = {2: D2_STEPS_PER_PASS, 3: D3_STEPS_PER_PASS}.get(d, 1)
     kernel = {2: d2_kernel(D2_STEPS_PER_PASS, V),
-              3: f"k_steps_d3q19<{D3_STEPS_PER_PASS}>"}.get(d, f"k_step<{d}>")
+              3: f"k_steps_d3q19<{D3_STEPS_PER_PASS}, true, true>"}.get(d, f"k_step<{d}, true, true>")
     pr = pass_roofline(d, V, per_launch, kms * 1e3)
     launch_us = pr["kernel_us_per_launch"]
     log(f"{mlups:.1f} MLUPS, kernel {launch_us:.2f} us per launch of {per_launch} steps, "
@@ -602,7 +606,7 @@ def main():
                 ms = kernel_only(torch, SV, W, wl, 400, dev, steps_per_pass=spp)
                 ml = V / (ms / 1e3) / 1e6
                 sweep[f"steps_per_pass_{spp}"] = {
-                    "kernel": "k_step<2>" if spp == 1 else d2_kernel(spp, V),
+                    "kernel": "k_step<2, true, true>" if spp == 1 else d2_kernel(spp, V),
                     "kernel_us_per_step": round(ms * 1e3, 2), "mlups": round(ml, 1),
                     "lb_steps_timed": 400, **pass_roofline(2, V, spp, ms * 1e3)}
             forms[wl.name + "_steps_per_pass"] = sweep
@@ -618,8 +622,8 @@ def main():
             spl = {2: D2_STEPS_PER_PASS, 3: D3_STEPS_PER_PASS}.get(w2.d, 1)
             forms[name] = {"lattice": {2: "D2Q9", 3: "D3Q19", 4: "D4Q33"}[w2.d],
                            "kernel": {2: d2_kernel(D2_STEPS_PER_PASS, w2.nodes),
-                                      3: f"k_steps_d3q19<{D3_STEPS_PER_PASS}>"}.get(
-                                          w2.d, f"k_step<{w2.d}>"),
+                                      3: f"k_steps_d3q19<{D3_STEPS_PER_PASS}, true, true>"}.get(
+                                          w2.d, f"k_step<{w2.d}, true, true>"),
                            "lb_steps_per_launch": spl,
                            "kernel_us_per_step": round(ms * 1e3, 2),
                            "mlups": round(ml, 1), "lb_steps_timed": n,
@@ -633,7 +637,7 @@ def main():
                 ms1 = kernel_only(torch, SV, W, w2, n, dev, steps_per_pass=1)
                 ml1 = w2.nodes / (ms1 / 1e3) / 1e6
                 forms[name]["single_step"] = {
-                    "kernel": "k_step<3>", "kernel_us_per_step": round(ms1 * 1e3, 2),
+                    "kernel": "k_step<3, true, true>", "kernel_us_per_step": round(ms1 * 1e3, 2),
                     "mlups": round(ml1, 1), **pass_roofline(3, w2.nodes, 1, ms1 * 1e3)}
             log(name, forms[name])
         if want("heat1d"):

@@ -381,8 +381,9 @@ lb_status lb_batch_set_tile(lb_batch* b, int32_t tx, int32_t ty);
 
 /* Time candidate tile shapes, one-step and multi-step, per step on the real
  * pools (the current state is left as it was; the other pool is used as
- * scratch) and keep the fastest; best_tx/best_ty receive the choice (may be
- * NULL). */
+ * scratch and holds no meaningful values afterwards) and keep the fastest;
+ * best_tx/best_ty receive the choice (may be NULL).  The trials time the
+ * launches that a step call runs between its first and its last. */
 lb_status lb_batch_autotune(lb_batch* b, int32_t steps_per_trial, int32_t* best_tx,
                             int32_t* best_ty);
 

@@ -1127,21 +1127,22 @@ lb_status lb_batch_autotune(lb_batch* b, int32_t steps_per_trial, int32_t* best_
         st = build_tiles(b, c[0], c[1]);
         if (st != LB_OK) break;
         // Trials always launch pool[cur] -> pool[1-cur]: the current state
-        // is untouched and the other pool is scratch, written without its
-        // twins as by the passes inside a step call.  Times are per step.
+        // is untouched and the other pool is scratch.  They time the launches
+        // a step call runs between its first and its last (twins read from
+        // their partners' planes and not stored), whatever pool[cur] holds:
+        // what lands in the scratch pool is never read.  Times are per step.
         const int per_launch = mode_multi_step(c[0]) ? mode_steps(c[0]) : 1;
         auto trial = [&](int reps) -> lb_status {
             for (int r = 0; r < reps; ++r) {
                 if (mode_multi_step(c[0]))
                     LB_HIP(lbm::launch_batch_steps(per_launch, b->d_insts, b->d_tiles, b->ntiles,
                                                    b->pool[b->cur], b->pool[1 - b->cur], b->off32,
-                                                   mode_one_wave(c[0]), b->stream, b->twin_ok,
-                                                   true),
+                                                   mode_one_wave(c[0]), b->stream, true, true),
                            "batch multi-step launch");
                 else
                     LB_HIP(lbm::launch_batch_step(b->d_insts, b->d_tiles, b->ntiles, b->tx, b->ty,
                                                   b->pool[b->cur], b->pool[1 - b->cur], b->stream,
-                                                  b->twin_ok, true),
+                                                  true, true),
                            "batch step launch");
             }
             return LB_OK;

@@ -87,13 +87,15 @@ def test_adjoint_and_heat_recipes():
 
 def test_bench_names_the_pass_variant():
     import bench
-    # a 4096^2 state (1.2 GB) takes 32-bit offsets, 8192 x 7400 (4.37 GB) does not
-    assert bench.d2_kernel(8, 4096 * 4096) == "k_steps_d2q9<8, true>"
-    assert bench.d2_kernel(8, 8192 * 7400) == "k_steps_d2q9<8, false>"
+    # a 4096^2 state (1.2 GB) takes 32-bit offsets, 8192 x 7400 (4.37 GB) does
+    # not; the launches inside a step call read and write the independent
+    # populations only (the last two template arguments)
+    assert bench.d2_kernel(8, 4096 * 4096) == "k_steps_d2q9<8, true, true, true>"
+    assert bench.d2_kernel(8, 8192 * 7400) == "k_steps_d2q9<8, false, true, true>"
     # both 1024^2 states (151 MB) fit in the 256 MB Infinity Cache, 1448^2 (302 MB) do not
-    assert bench.d2_kernel(4, 1024 * 1024) == "k_steps_d2q9_cached<4, true>"
-    assert bench.d2_kernel(8, 1280 * 1280) == "k_steps_d2q9_cached<8, true>"
-    assert bench.d2_kernel(8, 1448 * 1448) == "k_steps_d2q9<8, true>"
+    assert bench.d2_kernel(4, 1024 * 1024) == "k_steps_d2q9_cached<4, true, true, true>"
+    assert bench.d2_kernel(8, 1280 * 1280) == "k_steps_d2q9_cached<8, true, true, true>"
+    assert bench.d2_kernel(8, 1448 * 1448) == "k_steps_d2q9<8, true, true, true>"
 
 
 def test_bench_refuses_more_than_one_gpu():
