@@ -167,7 +167,8 @@ lb_status lb_theta_from_velocity(lb_solver* s, const double* u0, double* theta0,
  * the current state between calls is always complete.  The first launch of a
  * call reads twins from their partners too unless the state came from lb_init
  * or lb_set_state: a caller that changes the current buffer in place must go
- * through lb_set_state. */
+ * through lb_set_state.  After an LB_ERR_HIP return (a launch that failed)
+ * the current state is unspecified and must be set again. */
 lb_status lb_step(lb_solver* s, int64_t nsteps);
 
 /* LB_FLAG_BOUNDED solvers: advance nsteps >= 0 time steps on the interval.
