@@ -453,6 +453,51 @@ def test_reduced_state_passes_equal_complete_steps(grid, calls):
     ref.close()
 
 
+@pytest.mark.parametrize("seed", range(4))
+def test_reduced_state_random_call_sequences(seed):
+    """Random sequences of lb_step calls of random lengths, interleaved with
+    state round trips through lb_get_state / lb_set_state (which make the
+    next launch read every population), pass-limit changes, check intervals
+    and lb_macro reads, on a seeded random D2Q9, D3Q19 or D4Q33 grid: after
+    every call the state is bitwise that of lb_step_buffers single steps."""
+    rng = np.random.default_rng(1200 + seed)
+    d = (2, 3, 4, 2)[seed]
+    grid = {2: (int(rng.integers(20, 150)), int(rng.integers(10, 90))),
+            3: (int(rng.integers(8, 70)), int(rng.integers(5, 20)), int(rng.integers(5, 20))),
+            4: tuple(int(v) for v in rng.integers(3, 7, size=4))}[d]
+    _say("reduced-state call sequence", seed, grid)
+    SV = _solver_mod()
+    dx, dt, nu, th0, _ = _problem(grid, "random")
+    th0 = torch.from_numpy(th0).to(_dev())
+    s = SV.Solver(grid, dx, dt, nu, device=_dev())
+    s.init(th0, None)
+    ref = SV.Solver(grid, dx, dt, nu, device=_dev())
+    ref.init(th0, None)
+    cur = 0
+    for op in rng.integers(0, 5, size=14):
+        if op <= 1:
+            n = int(rng.integers(1, 26))
+            s.step(n)
+            for _ in range(n):
+                ref.step_buffers(ref.bufs[cur], ref.bufs[1 - cur])
+                cur ^= 1
+        elif op == 2:
+            s.set_state(s.get_state(), s.steps)
+        elif op == 3:
+            s.set_steps_per_pass(int(rng.choice([1, 2, 4, 8])))
+            s.set_check_interval(int(rng.choice([0, 3, 7])))
+        else:
+            s.macro()
+        if cur == 1:
+            ref.bufs[0].copy_(ref.bufs[1])
+            cur = 0
+        got, want = s.get_state(), ref.get_state()
+        torch.cuda.synchronize()
+        assert torch.equal(got, want), (grid, int(op))
+    s.close()
+    ref.close()
+
+
 def test_run_to_run_bitwise_determinism():
     _say("determinism")
     grid = (257, 129)
@@ -1124,6 +1169,30 @@ def test_batch_graphs_keyed_on_init_state():
                                     24, want_f=False)
                 assert np.array_equal(ths[b].cpu().numpy(), th), (tx, b)
                 assert np.array_equal(us[b].cpu().numpy(), u), (tx, b)
+    bs.close()
+
+
+def test_batch_autotune_between_steps():
+    """lb_batch_autotune times its candidates on the live pools (reading the
+    current pool as a post-collision state, writing the other one): run
+    between step calls, after a first call from lb_batch_init and before the
+    next, it leaves every instance bitwise on its single-instance run."""
+    _say("batch autotune between steps")
+    SV = _solver_mod()
+    insts = W.batch_instances(count=4, seed=13, lmin=40, lmax=130, nsteps=8)
+    th0s = [torch.from_numpy(W.evaluate(p.modes, p.grid, p.dx)[0]) for p in insts]
+    bs = SV.BatchSolver(insts, device=_dev())
+    bs.init(th0s, None)
+    bs.autotune(1)
+    bs.step(5, graph=False)
+    bs.autotune(1)
+    bs.step(11, graph=True)
+    ths, us = bs.macro()
+    torch.cuda.synchronize()
+    for b, p in enumerate(insts):
+        th, u, _ = _gpu_run(p.grid, p.dx, p.dt, p.nu, th0s[b].numpy(), None, 16, want_f=False)
+        assert np.array_equal(ths[b].cpu().numpy(), th), b
+        assert np.array_equal(us[b].cpu().numpy(), u), b
     bs.close()
 
 
