@@ -1112,8 +1112,8 @@ lb_status lb_batch_autotune(lb_batch* b, int32_t steps_per_trial, int32_t* best_
     if (!b->inited) return fail(LB_ERR_STATE, "autotune needs an initialised batch");
     if (steps_per_trial < 1) steps_per_trial = 1;
     // one-wave strips (-24, rows) favour short segments: on 512 ragged
-    // instances 219 GLUPS at 32 rows, 203 at 64-192, against 239 for the
-    // two-wave (-8, 128)
+    // instances 280 GLUPS at 32 rows, 263-264 at 64-192, against 261-263
+    // for the two-wave (-8, 128) and (-8, 192)
     static const int cand[][2] = {{0, 0},   {256, 1}, {64, 4},   {16, 16},  {-2, 64},
                                   {-4, 64},  {-8, 32}, {-8, 64},  {-8, 128}, {-8, 192},
                                   {-8, 256}, {-24, 16}, {-24, 32}};

@@ -804,7 +804,8 @@ k_adjoint_steps_d2q9(const double* __restrict__ src, double* __restrict__ dst,
 // ten with e_y != 0 (the xy edges after their x shift) then go through LDS
 // to row ty + e_y; the three with e_x = e_y = 0 stay in their thread.  Planes
 // are delayed in registers by e_z (0, 1 or 2 iterations).  Register pressure
-// limits S to 2 (217 VGPRs, two waves per SIMD, so one 512-thread block per
+// limits S to 2 (194 VGPRs when only the 13 independent populations are
+// loaded, 217 otherwise; two waves per SIMD, so one 512-thread block per
 // CU); each block uses 2 x 10 x 512 doubles of LDS.
 // ---------------------------------------------------------------------------
 __host__ __device__ constexpr int m3_ex(int i) { return Lat<3>::E[i][0]; }
