@@ -838,18 +838,63 @@ __host__ __device__ constexpr int m3_yslot(int i) {
 constexpr int M3_YMOVERS = m3_yslot(19);
 static_assert(M3_YMOVERS == 10, "D3Q19 has 10 populations with e_y != 0");
 
-// x shift by DPP (pull from lane tx - e_x), then y shift through LDS
-template <int S, int P, bool RIN, bool WOUT>
+// Whether plane i of a post-collision state (population i, or its twin)
+// holds a population with e_y = ey.
+__host__ __device__ constexpr bool m3_plane_holds(int i, int ey) {
+    for (int p = 0; p < 19; ++p)
+        if (twin<3>(p) == i && m3_ey(p) == ey) return true;
+    return false;
+}
+__host__ __device__ constexpr int m3_planes_holding(int ey) {
+    int n = 0;
+    for (int i = 0; i < 19; ++i) n += twin<3>(i) == i && m3_plane_holds(i, ey);
+    return n;
+}
+static_assert(m3_planes_holding(1) == 5 && m3_planes_holding(-1) == 5,
+              "an edge row of the tile passes on 5 of the 13 independent planes");
+
+// With only the 13 independent populations, one input plane (z-plane zp) of
+// the column col through a buffer resource over that z-plane's chunks
+// (32-bit offsets).  The first tile row passes on only its populations with
+// e_y = +1 and the last only those with e_y = -1; the planes they do not
+// need get an out-of-range offset, so the hardware drops those loads (no
+// memory access, the register reads 0) and every wave still issues the same
+// instructions: the two edge rows fetch 5 of the 13 planes.
+__device__ __forceinline__ void m3_load_plane(double (&pre)[19], const double* src,
+                                              int64_t plane, int zp, int col, int ty) {
+    const int64_t n0 = (int64_t)zp * plane;
+    const int64_t c0 = n0 >> 12, c1 = (n0 + plane - 1) >> 12;
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<double*>(src) + c0 * 19 * 4096, (short)0,
+        (int)((c1 - c0 + 1) * 19 * 4096 * 8), 0x00020000);
+    const int64_t kk = n0 + col;
+    const unsigned base = (unsigned)((((kk >> 12) - c0) * 19 * 4096 + (kk & 4095)) * 8);
+#pragma unroll
+    for (int i = 0; i < 19; ++i)
+        if (twin<3>(i) == i) {
+            const bool need = (ty != 0 || m3_plane_holds(i, 1)) &&
+                              (ty != MS3_TY - 1 || m3_plane_holds(i, -1));
+            const unsigned off = need ? base + (unsigned)(i * 4096 * 8) : 0x80000000u;
+            pre[i] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, 0));
+        }
+}
+
+// x shift by DPP (pull from lane tx - e_x), then y shift through LDS.  BUF:
+// the input planes come through m3_load_plane (RIN only).
+template <int S, int P, bool RIN, bool WOUT, bool BUF = false>
 __device__ __forceinline__ void ms3_plane(Ms3State<S>& st, double* lds, int k,
                                           const double* __restrict__ src, double* __restrict__ dst,
                                           const Geo& g, int col, int zs, int x0, int y0,
                                           const FoldedRates& r) {
+    static_assert(!BUF || RIN, "buffer loads serve the reduced state only");
     const int tid = threadIdx.x, tx = tid % MS3_TX, ty = tid / MS3_TX;
     const int64_t plane = (int64_t)g.nx * g.ny;
     double f[19];
 #pragma unroll
     for (int i = 0; i < 19; ++i) f[i] = st.pre[RIN ? twin<3>(i) : i];
-    {
+    if constexpr (BUF) {
+        m3_load_plane(st.pre, src, plane, wrapi(zs - S + k + 1, g.nz), col, ty);
+    } else {
         const int64_t base = (int64_t)wrapi(zs - S + k + 1, g.nz) * plane + col;
 #pragma unroll
         for (int i = 0; i < 19; ++i)
@@ -913,7 +958,7 @@ __device__ __forceinline__ void ms3_plane(Ms3State<S>& st, double* lds, int k,
     if (S & 1) __syncthreads();
 }
 
-template <int S, bool RIN, bool WOUT>
+template <int S, bool RIN, bool WOUT, bool BUF>
 __global__ void __launch_bounds__(M3_THREADS) k_steps_d3q19(const double* __restrict__ src,
                                                             double* __restrict__ dst, Geo g,
                                                             Rates r, int lz, int ntx, int nty) {
@@ -942,9 +987,9 @@ __global__ void __launch_bounds__(M3_THREADS) k_steps_d3q19(const double* __rest
         for (int a = 0; a < M3_ZP; ++a) st.u[0][j][a] = st.u[1][j][a] = 0.0;
     }
     for (int k = 0; k <= kend; k += 2) {
-        ms3_plane<S, 0, RIN, WOUT>(st, lds, k, src, dst, g, col, zs, x0, y0, fr);
+        ms3_plane<S, 0, RIN, WOUT, BUF>(st, lds, k, src, dst, g, col, zs, x0, y0, fr);
         if (k + 1 <= kend)
-            ms3_plane<S, 1, RIN, WOUT>(st, lds, k + 1, src, dst, g, col, zs, x0, y0, fr);
+            ms3_plane<S, 1, RIN, WOUT, BUF>(st, lds, k + 1, src, dst, g, col, zs, x0, y0, fr);
     }
 }
 
@@ -1809,10 +1854,18 @@ static hipError_t launch_steps3_t(const Geo& g, const Rates& r, const double* sr
     const int64_t nseg = (g.nz + lz - 1) / lz;  // every segment non-empty
     const int64_t nb = (int64_t)ntx * nty * nseg;
     if (nb > (int64_t)UINT32_MAX) return hipErrorInvalidValue;
+    // buffer loads need the chunks of one z-plane under 2 GiB (planes up to
+    // about 14 M nodes)
+    const int64_t plane = (int64_t)g.nx * g.ny;
+    const bool buf = (plane / 4096 + 2) * 19 * 4096 * 8 < ((int64_t)1 << 31);
     return dispatch_io(rin, wout, [&](auto ri, auto wo) {
-        hipLaunchKernelGGL((k_steps_d3q19<S, decltype(ri)::value, decltype(wo)::value>),
-                           dim3((unsigned)nb), dim3(M3_THREADS), 0, st, src, dst, g, r, (int)lz,
-                           ntx, nty);
+        constexpr bool RI = decltype(ri)::value, WO = decltype(wo)::value;
+        if (RI && buf)
+            hipLaunchKernelGGL((k_steps_d3q19<S, RI, WO, RI>), dim3((unsigned)nb),
+                               dim3(M3_THREADS), 0, st, src, dst, g, r, (int)lz, ntx, nty);
+        else
+            hipLaunchKernelGGL((k_steps_d3q19<S, RI, WO, false>), dim3((unsigned)nb),
+                               dim3(M3_THREADS), 0, st, src, dst, g, r, (int)lz, ntx, nty);
         return hipGetLastError();
     });
 }
