@@ -548,7 +548,7 @@ def main():
     # what the roofline fraction is taken against
     per_launch = {2: D2_STEPS_PER_PASS, 3: D3_STEPS_PER_PASS}.get(d, 1)
     kernel = {2: d2_kernel(D2_STEPS_PER_PASS, V),
-              3: f"k_steps_d3q19<{D3_STEPS_PER_PASS}, true, true>"}.get(d, f"k_step<{d}, true, true>")
+              3: f"k_steps_d3q19<{D3_STEPS_PER_PASS}, true, true, true>"}.get(d, f"k_step<{d}, true, true>")
     pr = pass_roofline(d, V, per_launch, kms * 1e3)
     launch_us = pr["kernel_us_per_launch"]
     log(f"{mlups:.1f} MLUPS, kernel {launch_us:.2f} us per launch of {per_launch} steps, "
@@ -622,7 +622,7 @@ def main():
             spl = {2: D2_STEPS_PER_PASS, 3: D3_STEPS_PER_PASS}.get(w2.d, 1)
             forms[name] = {"lattice": {2: "D2Q9", 3: "D3Q19", 4: "D4Q33"}[w2.d],
                            "kernel": {2: d2_kernel(D2_STEPS_PER_PASS, w2.nodes),
-                                      3: f"k_steps_d3q19<{D3_STEPS_PER_PASS}, true, true>"}.get(
+                                      3: f"k_steps_d3q19<{D3_STEPS_PER_PASS}, true, true, true>"}.get(
                                           w2.d, f"k_step<{w2.d}, true, true>"),
                            "lb_steps_per_launch": spl,
                            "kernel_us_per_step": round(ms * 1e3, 2),
