@@ -100,8 +100,19 @@ __device__ __forceinline__ bool thread_node(const Geo& g, int (&c)[4]) {
         c[1] = (int)((rest % gridDim.y) * BY + threadIdx.y);
         if constexpr (D >= 3) {
             const unsigned zw = rest / gridDim.y;  // grid.z runs over n_z * n_w
-            c[2] = (int)(zw % (unsigned)g.nz);
-            c[3] = (int)(zw / (unsigned)g.nz);
+            if (D == 4 && (g.nz & 7) == 0 && (g.nw & 7) == 0) {
+                // (z, w) planes in 8 x 8 patches, so that the blocks running
+                // at the same time (about 64 planes of 64 x 64 nodes) hold
+                // both the z and the w neighbours of most of their nodes in
+                // L2: a twin is pulled from its partner's plane at the node
+                // the partner's own pull does not read (64^4: +6 %)
+                const unsigned p = zw >> 6, q = zw & 63, npz = (unsigned)g.nz >> 3;
+                c[2] = (int)((p % npz) * 8 + (q & 7));
+                c[3] = (int)((p / npz) * 8 + (q >> 3));
+            } else {
+                c[2] = (int)(zw % (unsigned)g.nz);
+                c[3] = (int)(zw / (unsigned)g.nz);
+            }
         }
     }
     return c[0] < g.nx && c[1] < g.ny;

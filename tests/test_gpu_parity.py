@@ -106,6 +106,7 @@ CASES = [
     ("4d_ragged_6x5x4x7", (6, 5, 4, 7), 9, "random"),
     ("4d_cos_9x5x6x5", (9, 5, 6, 5), 5, "cos"),
     ("4d_ex4_level0", (20, 20, 20, 20), 40, "ex4"),
+    ("4d_patches_7x5x16x8", (7, 5, 16, 8), 6, "random"),
 ]
 
 
@@ -664,6 +665,11 @@ def test_full_size_2d(n):
 def test_full_size_3d(n):
     _say("full-size 3d", n, "2000 steps")
     _full_size_case(W.heat_3d(n), 2000)
+
+
+def test_full_size_4d():
+    _say("full-size 4d", 64, "200 steps")
+    _full_size_case(W.heat_4d(64, 200), 200)
 
 
 # ---------------------------------------------------------------------------
