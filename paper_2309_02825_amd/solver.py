@@ -147,6 +147,10 @@ class Solver:
         return L.lb_steps_taken(self.h)
 
     def current(self) -> torch.Tensor:
+        """The buffer that holds the current state (all q populations, in the
+        storage layout).  It is for reading, e.g. as a checkpoint: the next
+        step call reads the twin populations from their partners' planes, so
+        a state changed in place must go through set_state."""
         ptr = L.lb_current_state(self.h)
         return self.bufs[0] if ptr == self.bufs[0].data_ptr() else self.bufs[1]
 
