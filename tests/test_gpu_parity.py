@@ -401,6 +401,43 @@ def test_multi_step_passes_beyond_4gib_state():
     torch.cuda.empty_cache()
 
 
+def test_d3q19_passes_beyond_the_buffer_load_plane_limit():
+    """D3Q19 passes load their planes through a buffer resource per z-plane
+    while one z-plane's chunks stay under 2 GiB (about 14 M nodes); a
+    3800 x 3800 x 3 grid (14.4 M nodes per plane) takes the other path, and
+    its passes from a post-collision state are bitwise lb_step_buffers single
+    steps, which read and write every population."""
+    grid = (3800, 3800, 3)
+    plane = grid[0] * grid[1]
+    assert (plane // 4096 + 2) * 19 * 4096 * 8 >= 2 ** 31
+    _say("d3q19 past the buffer-load plane limit", grid, 6)
+    SV = _solver_mod()
+    dx, nu = 1.0 / grid[0], 0.01
+    dt = 0.1 * dx * dx / nu
+    gen = torch.Generator(device=_dev()).manual_seed(8)
+    th0 = 2.0 + 0.5 * torch.rand(tuple(reversed(grid)), dtype=torch.float64, device=_dev(),
+                                 generator=gen)
+    s = SV.Solver(grid, dx, dt, nu, device=_dev())
+    s.init(th0, None)
+    s.step(6)
+    got = s.get_state()
+    s.close()
+    ref = SV.Solver(grid, dx, dt, nu, device=_dev())
+    ref.init(th0, None)
+    cur = 0
+    for _ in range(6):
+        ref.step_buffers(ref.bufs[cur], ref.bufs[1 - cur])
+        cur ^= 1
+    # six steps leave the reference state in bufs[0], its current buffer
+    assert cur == 0
+    want = ref.get_state()
+    ref.close()
+    torch.cuda.synchronize()
+    assert torch.equal(got, want)
+    del got, want, th0
+    torch.cuda.empty_cache()
+
+
 @pytest.mark.parametrize("grid,steps", [((37, 29, 23), 5), ((5, 3, 2), 4), ((1, 1, 1), 3),
                                          ((64, 9, 40), 8), ((130, 7, 11), 7), ((61, 5, 70), 6)])
 def test_multi_step_passes_equal_single_steps_3d(grid, steps):
