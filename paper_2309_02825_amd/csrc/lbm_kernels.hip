@@ -484,9 +484,11 @@ struct MsState {
 // (pipeline fill), stage S stores only when ACTIVE == S.  ALL: stage j < S
 // also stores its rows of [ys, ye) to dst - (S - j) stride (the state after
 // j steps, for a caller that keeps every intermediate state).  NT: stage S
-// writes with non-temporal stores (otherwise through the caches).
+// writes with non-temporal stores (otherwise through the caches).  UP: the
+// march runs from row ye - 1 + S up to ys - S, so the roles of e_y = +1 and
+// e_y = -1 in the row delays swap (same arithmetic per node).
 template <int S, int P, int ACTIVE, bool ALL, bool OFF32, bool NT = true, bool RIN = false,
-          bool WOUT = false>
+          bool WOUT = false, bool UP = false>
 __device__ __forceinline__ void ms_row(MsState<S>& st, int k,
                                        const double* __restrict__ src, double* __restrict__ dst,
                                        int nx, int ny, int gx, int ys, int x0, const FoldedRates& r,
@@ -504,7 +506,8 @@ __device__ __forceinline__ void ms_row(MsState<S>& st, int k,
         // widened by a missing load (512^2: 90 -> 106 GLUPS).  The masked
         // stores of stage S still make that wait cover the previous row's
         // stores; two waves per SIMD hide it.
-        const MsAddr<OFF32> a(wrapi(ys - S + k + 1, ny) * nx + gx);
+        const int row = UP ? ys + nrows - 1 + S - (k + 1) : ys - S + k + 1;
+        const MsAddr<OFF32> a(wrapi(row, ny) * nx + gx);
 #pragma unroll
         for (int i = 0; i < 9; ++i)
             if (!RIN || twin<2>(i) == i) st.pre[i] = a.load(src, i);
@@ -512,15 +515,17 @@ __device__ __forceinline__ void ms_row(MsState<S>& st, int k,
 #pragma unroll
     for (int j = 1; j <= S; ++j) {
         // inputs of stage j: stage j-1 rows of iterations k (e_y = -1), k-1
-        // (e_y = 0) and k-2 (e_y = +1), pulled from lane t - e_x
+        // (e_y = 0) and k-2 (e_y = +1), pulled from lane t - e_x (marching
+        // up, e_y = +1 and -1 trade places)
         double in[9];
 #pragma unroll
         for (int i = 0; i < 9; ++i) {
             const double v = ms_ex(i) == 0 ? f[i]
                                            : (ms_ex(i) == 1 ? lane_shift<1>(f[i]) : lane_shift<-1>(f[i]));
-            if (ms_ey(i) == -1) {
+            const int ey = UP ? -ms_ey(i) : ms_ey(i);
+            if (ey == -1) {
                 in[i] = v;
-            } else if (ms_ey(i) == 0) {
+            } else if (ey == 0) {
                 in[i] = st.z[j - 1][ms_yslot(i)];
                 st.z[j - 1][ms_yslot(i)] = v;
             } else {
@@ -533,7 +538,8 @@ __device__ __forceinline__ void ms_row(MsState<S>& st, int k,
 #pragma unroll
             for (int i = 0; i < 9; ++i) f[i] = in[i];
             if (j == S && ACTIVE == S && lane >= S && lane < S + W && x0 - S + lane < nx) {
-                const MsAddr<OFF32> a(wrapi(ys - 2 * S + k, ny) * nx + x0 - S + lane);
+                const int row = UP ? ys + nrows - 1 + 2 * S - k : ys - 2 * S + k;
+                const MsAddr<OFF32> a(wrapi(row, ny) * nx + x0 - S + lane);
 #pragma unroll
                 for (int i = 0; i < 9; ++i) {
                     if (WOUT && twin<2>(i) != i) continue;
@@ -549,7 +555,7 @@ __device__ __forceinline__ void ms_row(MsState<S>& st, int k,
                 // side per stage)
                 const int rr = k - S - j;
                 if (rr >= 0 && rr < nrows && lane >= S && lane < S + W && x0 - S + lane < nx) {
-                    const MsAddr<OFF32> a((ys + rr) * nx + x0 - S + lane);
+                    const MsAddr<OFF32> a((UP ? ys + nrows - 1 - rr : ys + rr) * nx + x0 - S + lane);
                     double* out = dst - (int64_t)(S - j) * stride;
 #pragma unroll
                     for (int i = 0; i < 9; ++i)
@@ -560,22 +566,25 @@ __device__ __forceinline__ void ms_row(MsState<S>& st, int k,
     }
 }
 
-template <int S, int K, bool ALL, bool OFF32, bool NT = true, bool RIN = false, bool WOUT = false>
+template <int S, int K, bool ALL, bool OFF32, bool NT = true, bool RIN = false, bool WOUT = false,
+          bool UP = false>
 __device__ __forceinline__ void ms_fill(MsState<S>& st, const double* __restrict__ src,
                                         double* __restrict__ dst, int nx, int ny, int gx, int ys,
                                         int x0, const FoldedRates& r, int nrows, int64_t stride) {
     if constexpr (K < 2 * S) {
-        ms_row<S, K & 1, K / 2, ALL, OFF32, NT, RIN, WOUT>(st, K, src, dst, nx, ny, gx, ys, x0, r,
-                                                           nrows, stride);
-        ms_fill<S, K + 1, ALL, OFF32, NT, RIN, WOUT>(st, src, dst, nx, ny, gx, ys, x0, r, nrows,
-                                                     stride);
+        ms_row<S, K & 1, K / 2, ALL, OFF32, NT, RIN, WOUT, UP>(st, K, src, dst, nx, ny, gx, ys, x0,
+                                                               r, nrows, stride);
+        ms_fill<S, K + 1, ALL, OFF32, NT, RIN, WOUT, UP>(st, src, dst, nx, ny, gx, ys, x0, r, nrows,
+                                                         stride);
     }
 }
 
 // Advance rows [ys, ye) (ye > ys) of the columns [x0, x0 + 64 - 2S) of one
 // D2Q9 grid by S steps (reads rows ys-S .. ye-1+S and columns x0-S ..
-// x0+63-S, wrapped periodically).  All 64 lanes of the wave must be active.
-template <int S, bool ALL, bool OFF32, bool NT = true, bool RIN = false, bool WOUT = false>
+// x0+63-S, wrapped periodically), marching down the rows or, with UP, up.
+// All 64 lanes of the wave must be active.
+template <int S, bool ALL, bool OFF32, bool NT = true, bool RIN = false, bool WOUT = false,
+          bool UP = false>
 __device__ __forceinline__ void ms_tile(const double* __restrict__ src, double* __restrict__ dst,
                                         int nx, int ny, const FoldedRates& r, int x0, int ys,
                                         int ye, int64_t stride = 0) {
@@ -583,7 +592,7 @@ __device__ __forceinline__ void ms_tile(const double* __restrict__ src, double* 
     const int kend = ye - ys + 2 * S - 1;  // >= 2S
     MsState<S> st;
     {
-        const MsAddr<OFF32> a(wrapi(ys - S, ny) * nx + gx);
+        const MsAddr<OFF32> a(wrapi(UP ? ye - 1 + S : ys - S, ny) * nx + gx);
 #pragma unroll
         for (int i = 0; i < 9; ++i)
             if (!RIN || twin<2>(i) == i) st.pre[i] = a.load(src, i);
@@ -593,19 +602,23 @@ __device__ __forceinline__ void ms_tile(const double* __restrict__ src, double* 
 #pragma unroll
         for (int a = 0; a < 3; ++a) st.z[j][a] = st.u[0][j][a] = st.u[1][j][a] = 0.0;
     const int nrows = ye - ys;
-    ms_fill<S, 0, ALL, OFF32, NT, RIN, WOUT>(st, src, dst, nx, ny, gx, ys, x0, r, nrows, stride);
+    ms_fill<S, 0, ALL, OFF32, NT, RIN, WOUT, UP>(st, src, dst, nx, ny, gx, ys, x0, r, nrows,
+                                                 stride);
     for (int k = 2 * S; k <= kend; k += 2) {
-        ms_row<S, 0, S, ALL, OFF32, NT, RIN, WOUT>(st, k, src, dst, nx, ny, gx, ys, x0, r, nrows,
-                                                   stride);
-        if (k + 1 <= kend)
-            ms_row<S, 1, S, ALL, OFF32, NT, RIN, WOUT>(st, k + 1, src, dst, nx, ny, gx, ys, x0, r,
+        ms_row<S, 0, S, ALL, OFF32, NT, RIN, WOUT, UP>(st, k, src, dst, nx, ny, gx, ys, x0, r,
                                                        nrows, stride);
+        if (k + 1 <= kend)
+            ms_row<S, 1, S, ALL, OFF32, NT, RIN, WOUT, UP>(st, k + 1, src, dst, nx, ny, gx, ys, x0,
+                                                           r, nrows, stride);
     }
 }
 
 // Two waves per SIMD: the register budget (256 per wave) holds S = 8.
 // RIN / WOUT: twin populations read from their twins' planes / not stored,
-// as for k_step.
+// as for k_step.  Odd row segments march up: two neighbouring segments then
+// read the halo rows they share at the same time (both at their ends, or
+// both at their starts), so the second read finds them in the caches
+// (1024^2 +6 %, 512^2 +4 %, 4096^2 within 0.5 %).
 template <int S, bool OFF32, bool RIN, bool WOUT>
 __global__ void __launch_bounds__(MS_THREADS) __attribute__((amdgpu_waves_per_eu(2)))
 k_steps_d2q9(const double* __restrict__ src,
@@ -615,8 +628,14 @@ k_steps_d2q9(const double* __restrict__ src,
     const int strip = (int)(t % (unsigned)nstrips);
     const int seg = (int)(t / (unsigned)nstrips);
     const int ys = seg * ly;
-    ms_tile<S, false, OFF32, true, RIN, WOUT>(src, dst, g.nx, g.ny, folded(r),
-                                              strip * strip_width(S), ys, min(ys + ly, g.ny), 0);
+    if (seg & 1)
+        ms_tile<S, false, OFF32, true, RIN, WOUT, true>(src, dst, g.nx, g.ny, folded(r),
+                                                        strip * strip_width(S), ys,
+                                                        min(ys + ly, g.ny), 0);
+    else
+        ms_tile<S, false, OFF32, true, RIN, WOUT>(src, dst, g.nx, g.ny, folded(r),
+                                                  strip * strip_width(S), ys, min(ys + ly, g.ny),
+                                                  0);
 }
 
 // The same pass with cached stores, for grids whose two states fit in the
@@ -629,8 +648,14 @@ k_steps_d2q9_cached(const double* __restrict__ src, double* __restrict__ dst, Ge
     const int strip = (int)(t % (unsigned)nstrips);
     const int seg = (int)(t / (unsigned)nstrips);
     const int ys = seg * ly;
-    ms_tile<S, false, OFF32, false, RIN, WOUT>(src, dst, g.nx, g.ny, folded(r),
-                                               strip * strip_width(S), ys, min(ys + ly, g.ny), 0);
+    if (seg & 1)
+        ms_tile<S, false, OFF32, false, RIN, WOUT, true>(src, dst, g.nx, g.ny, folded(r),
+                                                         strip * strip_width(S), ys,
+                                                         min(ys + ly, g.ny), 0);
+    else
+        ms_tile<S, false, OFF32, false, RIN, WOUT>(src, dst, g.nx, g.ny, folded(r),
+                                                   strip * strip_width(S), ys,
+                                                   min(ys + ly, g.ny), 0);
 }
 
 // The same pass writing the state after every one of its S steps: step j to
