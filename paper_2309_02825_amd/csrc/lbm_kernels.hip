@@ -96,8 +96,8 @@ __device__ __forceinline__ bool thread_node(const Geo& g, int (&c)[4]) {
         c[0] = (int)(tx * B1 + threadIdx.x);
         c[1] = 0;
     } else {
-        c[0] = (int)(tx * BX + threadIdx.x);
-        c[1] = (int)((rest % gridDim.y) * BY + threadIdx.y);
+        c[0] = (int)(tx * blockDim.x + threadIdx.x);
+        c[1] = (int)((rest % gridDim.y) * blockDim.y + threadIdx.y);
         if constexpr (D >= 3) {
             const unsigned zw = rest / gridDim.y;  // grid.z runs over n_z * n_w
             if (D == 4 && (g.nz & 7) == 0 && (g.nw & 7) == 0) {
@@ -1692,8 +1692,14 @@ Launch launch_shape(int d, const Geo& g) {
         L.block = dim3(B1, 1, 1);
         L.grid = dim3((unsigned)((g.nx + B1 - 1) / B1), 1, 1);
     } else {
-        L.block = dim3(BX, BY, 1);
-        L.grid = dim3((unsigned)((g.nx + BX - 1) / BX), (unsigned)((g.ny + BY - 1) / BY),
+        // 256 threads: a whole row segment of 256 nodes, or for rows of at
+        // most 128 (64) nodes 2 (4) rows of 128 (64), so that short rows do
+        // not leave most of a block idle (64^4: one row of 64 per block left
+        // three of its four waves without a node)
+        const int bx = g.nx > 128 ? BX : (g.nx > 64 ? 128 : 64);
+        const int by = BX * BY / bx;
+        L.block = dim3(bx, by, 1);
+        L.grid = dim3((unsigned)((g.nx + bx - 1) / bx), (unsigned)((g.ny + by - 1) / by),
                       (unsigned)(d >= 3 ? g.nz * g.nw : 1));
     }
     L.nblocks = (int64_t)L.grid.x * L.grid.y * L.grid.z;
