@@ -38,9 +38,9 @@ BYTES_PER_LU = {1: 48, 2: 144, 3: 304, 4: 528}
 # 2 x (1 + 2d + 2d(d-1)) x 8 bytes per node; what the passes inside one
 # lb_step call move
 BYTES_PER_NODE_PASS = {1: 48, 2: 112, 3: 208, 4: 336}
-# double-precision operations of one D2Q9 collision (collide_d2q9: 26 add/sub,
-# 6 mul, 3 fma counted twice)
-FLOPS_PER_LU_D2Q9 = 38
+# double-precision operations of one D2Q9 collision (collide_d2q9: 19 add/sub,
+# 2 mul, 10 fma counted twice)
+FLOPS_PER_LU_D2Q9 = 41
 FP64_PEAK_TFLOPS = 78.6
 D2_STEPS_PER_PASS = 8
 D3_STEPS_PER_PASS = 2
