@@ -687,7 +687,12 @@ k_steps_d2q9_all(const double* __restrict__ src, double* __restrict__ out, int64
 // dual moments of mu, eps_part_d2q9), with f^{N-j}
 // pulled from its state buffer at ftop - (j - 1) stride (ftop = f^{N-1});
 // RIN: those states were written by a collision and twin populations are
-// read from their partners' planes (as in k_step).
+// read from their partners' planes (as in k_step).  The partner planes of the
+// twins (those of the (+,+) and (-,+) edges) serve two rows of the pull each
+// (row y - 1 for the edge itself, row y + 1 for its twin), so each of their
+// rows is loaded once at the lane's own column, kept two rows in a per-wave
+// LDS delay and pulled along x by a DPP lane shift (as_load_f_tw, as_edges):
+// every plane row of the recomputed states is read once per pass.
 // Each lane sums the eps parts of its nodes over all stages and rows in a
 // fixed order; the wave's sum goes to partials[block], and the blocks from
 // nblocks to ntab - 1 write zeros, so the table always holds ntab entries.
@@ -712,11 +717,50 @@ __device__ __forceinline__ void as_load_f(double (&fn)[9], const double* __restr
         fn[i] = fs[slot<9>(RIN ? twin<2>(i) : i, rows[ms_ey(i) + 1] + cols[ms_ex(i) + 1])];
 }
 
+// RIN: the per-wave LDS delay of the two partner planes for stage j holds,
+// per row parity, the raw rows (own column of each lane) of planes 5 and 6:
+// tw[((j - 1) * 2 + parity) * 128 + plane * 64 + lane].  Each lane reads
+// and writes only its own entries.
+constexpr int AS_TW = 128;  // doubles per stage and parity
+// f^{N-j} for row y (RIN): populations 0-4 pulled as in as_load_f (own
+// lanes); fn[7], fn[8] the raw rows y + 1 of planes 5 and 6 (every lane).
+// as_edges completes the pull when the row is used.
+__device__ __forceinline__ void as_load_f_tw(double (&fn)[9], const double* __restrict__ fs,
+                                             int x, int gx, int y, int nx, int ny, bool own) {
+    if (own) {
+        const int rows[3] = {wrapi(y + 1, ny) * nx, y * nx, wrapi(y - 1, ny) * nx};
+        const int cols[3] = {x == nx - 1 ? 0 : x + 1, x, x == 0 ? nx - 1 : x - 1};
+#pragma unroll
+        for (int i = 0; i < 5; ++i) fn[i] = fs[slot<9>(i, rows[ms_ey(i) + 1] + cols[ms_ex(i) + 1])];
+    }
+    const int yp = wrapi(y + 1, ny) * nx + gx;
+    fn[7] = fs[slot<9>(5, yp)];
+    fn[8] = fs[slot<9>(6, yp)];
+}
+// Row y of stage j: take the raw rows y - 1 of planes 5 and 6 from the LDS
+// delay (stored two rows earlier, or at the start of the segment), store the
+// raw rows y + 1 in their place for row y + 2, and pull the four edge
+// populations along x: population i of plane 5 or 6 from the lane at
+// x - e_x (e = (1,1), (-1,1) from row y - 1; (-1,-1), (1,-1) from row y + 1).
+__device__ __forceinline__ void as_edges(double (&fn)[9], double* tw) {
+    const double m5 = tw[threadIdx.x], m6 = tw[64 + threadIdx.x];
+    tw[threadIdx.x] = fn[7];
+    tw[64 + threadIdx.x] = fn[8];
+    fn[5] = lane_shift<1>(m5);
+    fn[6] = lane_shift<-1>(m6);
+    fn[7] = lane_shift<-1>(fn[7]);
+    fn[8] = lane_shift<1>(fn[8]);
+}
+static_assert(ms_ex(5) == 1 && ms_ey(5) == 1 && ms_ex(6) == -1 && ms_ey(6) == 1 &&
+                  twin<2>(7) == 5 && twin<2>(8) == 6,
+              "the edge planes 5 and 6 carry the (+,+) and (-,+) edges and their twins");
+
 template <int S, int P, int ACTIVE, bool RIN>
 __device__ __forceinline__ void as_row(AsState<S>& st, double& ge, int k,
                                        const double* __restrict__ src, double* __restrict__ dst,
                                        const double* __restrict__ ftop, int64_t stride, int nx,
-                                       int ny, int gx, int ys, int x0, int nrows, const Rates& r) {
+                                       int ny, int gx, int ys, int x0, int nrows, const Rates& r,
+                                       double* tw) {
     constexpr int W = MS_THREADS - 2 * S;
     const int lane = threadIdx.x;
     const int x = x0 - S + lane;
@@ -749,7 +793,10 @@ __device__ __forceinline__ void as_row(AsState<S>& st, double& ge, int k,
         }
         if (j <= ACTIVE) {
             const int rr = k - S - j;  // owned row ys + rr of this stage
-            if (own && rr >= 0 && rr < nrows) ge += eps_part_d2q9(in, st.fp[j - 1], r);
+            if (rr >= 0 && rr < nrows) {
+                if constexpr (RIN) as_edges(st.fp[j - 1], tw + ((j - 1) * 2 + (rr & 1)) * AS_TW);
+                if (own) ge += eps_part_d2q9(in, st.fp[j - 1], r);
+            }
             double lam[9];
             collide_adjoint<2>(in, r, lam);
 #pragma unroll
@@ -765,8 +812,14 @@ __device__ __forceinline__ void as_row(AsState<S>& st, double& ge, int k,
 #pragma unroll
     for (int j = 1; j <= S; ++j) {
         const int rr = k + 1 - S - j;
-        if (own && rr >= 0 && rr < nrows)
-            as_load_f<RIN>(st.fp[j - 1], ftop - (int64_t)(j - 1) * stride, x, ys + rr, nx, ny);
+        if constexpr (RIN) {
+            if (rr >= 0 && rr < nrows)
+                as_load_f_tw(st.fp[j - 1], ftop - (int64_t)(j - 1) * stride, x, gx, ys + rr, nx,
+                             ny, own);
+        } else {
+            if (own && rr >= 0 && rr < nrows)
+                as_load_f<RIN>(st.fp[j - 1], ftop - (int64_t)(j - 1) * stride, x, ys + rr, nx, ny);
+        }
     }
 }
 
@@ -774,11 +827,12 @@ template <int S, int K, bool RIN>
 __device__ __forceinline__ void as_fill(AsState<S>& st, double& ge,
                                         const double* __restrict__ src, double* __restrict__ dst,
                                         const double* __restrict__ ftop, int64_t stride, int nx,
-                                        int ny, int gx, int ys, int x0, int nrows, const Rates& r) {
+                                        int ny, int gx, int ys, int x0, int nrows, const Rates& r,
+                                        double* tw) {
     if constexpr (K < 2 * S) {
         as_row<S, K & 1, K / 2, RIN>(st, ge, K, src, dst, ftop, stride, nx, ny, gx, ys, x0, nrows,
-                                     r);
-        as_fill<S, K + 1, RIN>(st, ge, src, dst, ftop, stride, nx, ny, gx, ys, x0, nrows, r);
+                                     r, tw);
+        as_fill<S, K + 1, RIN>(st, ge, src, dst, ftop, stride, nx, ny, gx, ys, x0, nrows, r, tw);
     }
 }
 
@@ -811,13 +865,29 @@ k_adjoint_steps_d2q9(const double* __restrict__ src, double* __restrict__ dst,
 #pragma unroll
         for (int i = 0; i < 9; ++i) st.fp[j][i] = 0.0;
     }
+    // RIN: the LDS delay of the partner planes starts with the raw rows
+    // ys - 1 (parity 0) and ys (parity 1) of every stage's state; each lane
+    // reads back only what it wrote, so no barrier is needed
+    __shared__ double tw[RIN ? S * 2 * AS_TW : 1];
+    if constexpr (RIN) {
+#pragma unroll
+        for (int j = 0; j < S; ++j) {
+            const double* fs = ftop - (int64_t)j * stride;
+#pragma unroll
+            for (int p = 0; p < 2; ++p) {
+                const int row = wrapi(ys - 1 + p, ny) * nx + gx;
+                tw[(j * 2 + p) * AS_TW + threadIdx.x] = fs[slot<9>(5, row)];
+                tw[(j * 2 + p) * AS_TW + 64 + threadIdx.x] = fs[slot<9>(6, row)];
+            }
+        }
+    }
     double ge = 0.0;
-    as_fill<S, 0, RIN>(st, ge, src, dst, ftop, stride, nx, ny, gx, ys, x0, nrows, r);
+    as_fill<S, 0, RIN>(st, ge, src, dst, ftop, stride, nx, ny, gx, ys, x0, nrows, r, tw);
     for (int k = 2 * S; k <= kend; k += 2) {
-        as_row<S, 0, S, RIN>(st, ge, k, src, dst, ftop, stride, nx, ny, gx, ys, x0, nrows, r);
+        as_row<S, 0, S, RIN>(st, ge, k, src, dst, ftop, stride, nx, ny, gx, ys, x0, nrows, r, tw);
         if (k + 1 <= kend)
             as_row<S, 1, S, RIN>(st, ge, k + 1, src, dst, ftop, stride, nx, ny, gx, ys, x0, nrows,
-                                 r);
+                                 r, tw);
     }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) ge += __shfl_xor(ge, o, 64);
