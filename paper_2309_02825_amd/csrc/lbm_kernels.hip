@@ -604,13 +604,20 @@ __device__ __forceinline__ void ms_tile(const double* __restrict__ src, double* 
     const int nrows = ye - ys;
     ms_fill<S, 0, ALL, OFF32, NT, RIN, WOUT, UP>(st, src, dst, nx, ny, gx, ys, x0, r, nrows,
                                                  stride);
-    for (int k = 2 * S; k <= kend; k += 2) {
+    // whole row pairs in the loop and a last odd row after it: the loop then
+    // has a single path back to its head, and the compiler keeps the row
+    // delays in place instead of copying them at the join (bitwise the same;
+    // 4096^2 +3 %)
+    int k = 2 * S;
+    for (; k + 1 <= kend; k += 2) {
         ms_row<S, 0, S, ALL, OFF32, NT, RIN, WOUT, UP>(st, k, src, dst, nx, ny, gx, ys, x0, r,
                                                        nrows, stride);
-        if (k + 1 <= kend)
-            ms_row<S, 1, S, ALL, OFF32, NT, RIN, WOUT, UP>(st, k + 1, src, dst, nx, ny, gx, ys, x0,
-                                                           r, nrows, stride);
+        ms_row<S, 1, S, ALL, OFF32, NT, RIN, WOUT, UP>(st, k + 1, src, dst, nx, ny, gx, ys, x0, r,
+                                                       nrows, stride);
     }
+    if (k <= kend)
+        ms_row<S, 0, S, ALL, OFF32, NT, RIN, WOUT, UP>(st, k, src, dst, nx, ny, gx, ys, x0, r,
+                                                       nrows, stride);
 }
 
 // Two waves per SIMD: the register budget (256 per wave) holds S = 8.
@@ -883,12 +890,15 @@ k_adjoint_steps_d2q9(const double* __restrict__ src, double* __restrict__ dst,
     }
     double ge = 0.0;
     as_fill<S, 0, RIN>(st, ge, src, dst, ftop, stride, nx, ny, gx, ys, x0, nrows, r, tw);
-    for (int k = 2 * S; k <= kend; k += 2) {
+    // row pairs in the loop, a last odd row after it (as in ms_tile)
+    int k = 2 * S;
+    for (; k + 1 <= kend; k += 2) {
         as_row<S, 0, S, RIN>(st, ge, k, src, dst, ftop, stride, nx, ny, gx, ys, x0, nrows, r, tw);
-        if (k + 1 <= kend)
-            as_row<S, 1, S, RIN>(st, ge, k + 1, src, dst, ftop, stride, nx, ny, gx, ys, x0, nrows,
-                                 r, tw);
+        as_row<S, 1, S, RIN>(st, ge, k + 1, src, dst, ftop, stride, nx, ny, gx, ys, x0, nrows, r,
+                             tw);
     }
+    if (k <= kend)
+        as_row<S, 0, S, RIN>(st, ge, k, src, dst, ftop, stride, nx, ny, gx, ys, x0, nrows, r, tw);
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) ge += __shfl_xor(ge, o, 64);
     if (threadIdx.x == 0) {
@@ -1092,11 +1102,13 @@ __global__ void __launch_bounds__(M3_THREADS) k_steps_d3q19(const double* __rest
 #pragma unroll
         for (int a = 0; a < M3_ZP; ++a) st.u[0][j][a] = st.u[1][j][a] = 0.0;
     }
-    for (int k = 0; k <= kend; k += 2) {
+    // plane pairs in the loop, a last odd plane after it (as in ms_tile)
+    int k = 0;
+    for (; k + 1 <= kend; k += 2) {
         ms3_plane<S, 0, RIN, WOUT, BUF>(st, lds, k, src, dst, g, col, zs, x0, y0, fr);
-        if (k + 1 <= kend)
-            ms3_plane<S, 1, RIN, WOUT, BUF>(st, lds, k + 1, src, dst, g, col, zs, x0, y0, fr);
+        ms3_plane<S, 1, RIN, WOUT, BUF>(st, lds, k + 1, src, dst, g, col, zs, x0, y0, fr);
     }
+    if (k <= kend) ms3_plane<S, 0, RIN, WOUT, BUF>(st, lds, k, src, dst, g, col, zs, x0, y0, fr);
 }
 
 // ---------------------------------------------------------------------------
@@ -1707,11 +1719,13 @@ __device__ __forceinline__ void lw_tile(const double* __restrict__ src, double* 
     for (int j = 0; j < S; ++j)
 #pragma unroll
         for (int a = 0; a < 3; ++a) st.z[j][a] = st.u[0][j][a] = st.u[1][j][a] = 0.0;
-    for (int k = 0; k <= kend; k += 2) {
+    // row pairs in the loop, a last odd row after it (as in ms_tile)
+    int k = 0;
+    for (; k + 1 <= kend; k += 2) {
         lw_row<S, 0, OFF32, RIN, WOUT>(st, lds, k, kend, src, dst, nx, ny, gx, ys, x0, r);
-        if (k + 1 <= kend)
-            lw_row<S, 1, OFF32, RIN, WOUT>(st, lds, k + 1, kend, src, dst, nx, ny, gx, ys, x0, r);
+        lw_row<S, 1, OFF32, RIN, WOUT>(st, lds, k + 1, kend, src, dst, nx, ny, gx, ys, x0, r);
     }
+    if (k <= kend) lw_row<S, 0, OFF32, RIN, WOUT>(st, lds, k, kend, src, dst, nx, ny, gx, ys, x0, r);
 }
 
 
