@@ -920,7 +920,7 @@ k_adjoint_steps_d2q9(const double* __restrict__ src, double* __restrict__ dst,
 // ten with e_y != 0 (the xy edges after their x shift) then go through LDS
 // to row ty + e_y; the three with e_x = e_y = 0 stay in their thread.  Planes
 // are delayed in registers by e_z (0, 1 or 2 iterations).  Register pressure
-// limits S to 2 (194 VGPRs when only the 13 independent populations are
+// limits S to 2 (190 VGPRs when only the 13 independent populations are
 // loaded, 217 otherwise; two waves per SIMD, so one 512-thread block per
 // CU); each block uses 2 x 10 x 512 doubles of LDS.
 // ---------------------------------------------------------------------------
@@ -1003,7 +1003,11 @@ __device__ __forceinline__ void ms3_plane(Ms3State<S>& st, double* lds, int k,
                                           const Geo& g, int col, int zs, int x0, int y0,
                                           const FoldedRates& r) {
     static_assert(!BUF || RIN, "buffer loads serve the reduced state only");
-    const int tid = threadIdx.x, tx = tid % MS3_TX, ty = tid / MS3_TX;
+    // a tile row is one wave: ty is uniform across it, and saying so lets the
+    // per-row choices (edge-row loads, y exchange) compile to scalar selects
+    // and branches instead of lane-masked ones
+    const int tid = threadIdx.x, tx = tid % MS3_TX;
+    const int ty = __builtin_amdgcn_readfirstlane(tid / MS3_TX);
     const int64_t plane = (int64_t)g.nx * g.ny;
     double f[19];
 #pragma unroll
@@ -1084,7 +1088,8 @@ __global__ void __launch_bounds__(M3_THREADS) k_steps_d3q19(const double* __rest
     const int tile = (int)(t % ntile), seg = (int)(t / ntile);
     const int x0 = (tile % ntx) * tile_width3(S), y0 = (tile / ntx) * tile_height3(S);
     const int zs = seg * lz, ze = min(zs + lz, g.nz);
-    const int tx = threadIdx.x % MS3_TX, ty = threadIdx.x / MS3_TX;
+    const int tx = threadIdx.x % MS3_TX;
+    const int ty = __builtin_amdgcn_readfirstlane((int)threadIdx.x / MS3_TX);
     const int col = wrapi(y0 - S + ty, g.ny) * g.nx + wrapi(x0 - S + tx, g.nx);
     const int kend = ze - zs + 2 * S - 1;
     const FoldedRates fr = folded(r);
