@@ -800,12 +800,14 @@ __device__ __forceinline__ void as_row(AsState<S>& st, double& ge, int k,
         }
         if (j <= ACTIVE) {
             const int rr = k - S - j;  // owned row ys + rr of this stage
+            // the dual moments of mu serve the eps part and C^T mu
+            const Dual2 du = dual_d2q9(in);
             if (rr >= 0 && rr < nrows) {
                 if constexpr (RIN) as_edges(st.fp[j - 1], tw + ((j - 1) * 2 + (rr & 1)) * AS_TW);
-                if (own) ge += eps_part_d2q9(in, st.fp[j - 1], r);
+                if (own) ge += eps_part_d2q9(du, st.fp[j - 1], r);
             }
             double lam[9];
-            collide_adjoint<2>(in, r, lam);
+            collide_adjoint_d2q9(du, r, lam);  // as collide_adjoint<2>
 #pragma unroll
             for (int i = 0; i < 9; ++i) f[i] = lam[i];
             if (j == S && ACTIVE == S && own) {

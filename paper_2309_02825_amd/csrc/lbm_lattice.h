@@ -384,23 +384,63 @@ __device__ __forceinline__ void collide_deps(const double (&f)[Lat<D>::Q], const
 // -ds1 j_a, -ds21 (P_a - theta/3), -ds22 P_xy and 4 dw_d theta on the
 // c_x^2 c_y^2 row (zero elsewhere), so the product is sum over rows of
 // nu_row m'_row.  Equal to sum_i mu_i df_i of collide_deps up to rounding.
-__device__ __forceinline__ double eps_part_d2q9(const double (&mu)[9], const double (&f)[9],
+// Dual moments nu = M^-T mu of a D2Q9 mu (those of collide_adjoint below),
+// shared by the eps part and the folded adjoint collision.  The products by
+// 1/2 and 1/4 are exact, so the fused forms round as the plain ones would.
+struct Dual2 {
+    double rest, nax, nay, naax, naay, nab, naabb;
+};
+__device__ __forceinline__ Dual2 dual_d2q9(const double (&mu)[9]) {
+    const double sx = mu[1] + mu[3], sy = mu[2] + mu[4];
+    const double se = mu[5] + mu[7], sd = mu[6] + mu[8];
+    Dual2 d;
+    d.rest = mu[0];
+    d.nax = 0.5 * (mu[1] - mu[3]);
+    d.nay = 0.5 * (mu[2] - mu[4]);
+    d.naax = fma(0.5, sx, -mu[0]);
+    d.naay = fma(0.5, sy, -mu[0]);
+    d.nab = 0.25 * (se - sd);
+    d.naabb = fma(0.25, se + sd, fma(-0.5, sx + sy, mu[0]));
+    return d;
+}
+
+__device__ __forceinline__ double eps_part_d2q9(const Dual2& d, const double (&f)[9],
                                                 const Rates& r) {
     const double xp = f[1] + f[5] + f[8], xm = f[3] + f[6] + f[7];
     const double yp = f[2] + f[5] + f[6], ym = f[4] + f[7] + f[8];
     const double jx = xp - xm, Px = xp + xm, jy = yp - ym, Py = yp + ym;
     const double th = f[0] + (f[2] + f[4]) + Px;
     const double Pxy = (f[5] + f[7]) - (f[6] + f[8]);
-    const double sx = mu[1] + mu[3], sy = mu[2] + mu[4];
-    const double se = (mu[5] + mu[7]), sd = (mu[6] + mu[8]);
-    const double nax = 0.5 * (mu[1] - mu[3]), nay = 0.5 * (mu[2] - mu[4]);
-    const double naax = 0.5 * sx - mu[0], naay = 0.5 * sy - mu[0];
-    const double nab = 0.25 * (se - sd);
-    const double naabb = (mu[0] - 0.5 * (sx + sy)) + 0.25 * (se + sd);
     const double th3 = th * (1.0 / 3.0);
-    return (-r.ds1) * (nax * jx + nay * jy) +
-           (-r.ds21) * (naax * (Px - th3) + naay * (Py - th3)) + (-r.ds22) * (nab * Pxy) +
-           (4.0 * r.dwd) * (naabb * th);
+    return (-r.ds1) * (d.nax * jx + d.nay * jy) +
+           (-r.ds21) * (d.naax * (Px - th3) + d.naay * (Py - th3)) + (-r.ds22) * (d.nab * Pxy) +
+           (4.0 * r.dwd) * (d.naabb * th);
+}
+
+// lam = C^T mu for D2Q9 from the dual moments, with the algebra of
+// collide_adjoint below folded: with t_a = (1 - s1) nu_a, tt_a =
+// (1 - s21) nu_aa and n0 = nu_0 + (s21/3)(nu_xx + nu_yy) + 4 w_d nu_xxyy,
+// lam_rest = n0, lam_{+-a} = (n0 + tt_a) +- t_a and the four edges are
+// (c +- (1 - s22) nu_xy) +- (t_x +- t_y) with c = n0 + tt_x + tt_y
+// (signs e_x e_y, e_x and e_y).  24 operations against about 60.
+__device__ __forceinline__ void collide_adjoint_d2q9(const Dual2& d, const Rates& r,
+                                                     double (&lam)[9]) {
+    const double ttx = r.one_m_s21 * d.naax, tty = r.one_m_s21 * d.naay;
+    const double n0 = fma(r.R4wd, d.naabb, fma(r.s21 * (1.0 / 3.0), d.naax + d.naay, d.rest));
+    const double bx = n0 + ttx, by = n0 + tty;
+    const double tx = r.one_m_s1 * d.nax, ty = r.one_m_s1 * d.nay;
+    const double c = bx + tty;
+    const double cp = fma(r.one_m_s22, d.nab, c), cm = fma(-r.one_m_s22, d.nab, c);
+    const double p = tx + ty, m = tx - ty;
+    lam[0] = n0;
+    lam[1] = bx + tx;
+    lam[3] = bx - tx;
+    lam[2] = by + ty;
+    lam[4] = by - ty;
+    lam[5] = cp + p;
+    lam[7] = cp - p;
+    lam[6] = cm - m;
+    lam[8] = cm + m;
 }
 
 // lam = C^T mu.  With C = M^-1 C_m M and C_m = I - S + S (M w) e_0^T,
@@ -416,6 +456,10 @@ __device__ __forceinline__ double eps_part_d2q9(const double (&mu)[9], const dou
 template <int D>
 __device__ __forceinline__ void collide_adjoint(const double (&mu)[Lat<D>::Q], const Rates& r,
                                                 double (&lam)[Lat<D>::Q]) {
+    if constexpr (D == 2) {
+        collide_adjoint_d2q9(dual_d2q9(mu), r, lam);
+        return;
+    }
     constexpr int Q = Lat<D>::Q;
     double na[D], naa[D], nab[NPairs<D>::value], naabb[NPairs<D>::value];
     const double rest = mu[0];
