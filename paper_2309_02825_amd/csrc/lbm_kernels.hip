@@ -433,6 +433,7 @@ __device__ __forceinline__ GChar* wave_base(const double* p) {
     return (GChar*)(((unsigned long long)hi << 32) | lo);
 }
 template <bool OFF32> struct MsAddr;
+typedef unsigned int MsU2 __attribute__((__vector_size__(8)));  // a double as buffer data
 template <> struct MsAddr<true> {
     unsigned off;
     __device__ __forceinline__ explicit MsAddr(int k)
@@ -557,9 +558,25 @@ __device__ __forceinline__ void ms_row(MsState<S>& st, int k,
                 if (rr >= 0 && rr < nrows && lane >= S && lane < S + W && x0 - S + lane < nx) {
                     const MsAddr<OFF32> a((UP ? ys + nrows - 1 - rr : ys + rr) * nx + x0 - S + lane);
                     double* out = dst - (int64_t)(S - j) * stride;
+                    if constexpr (OFF32) {
+                        // a buffer descriptor per state and the plane as a
+                        // scalar offset shared by all S states: a 64-bit
+                        // base per plane and state would exceed the scalar
+                        // registers (they spill into VGPR lanes)
+                        const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+                            out, (short)0, (int)(unsigned)((uint64_t)9 * CHUNK * 8 *
+                                                          (uint64_t)((nx * ny + CHUNK - 1) >> 12)),
+                            0x00020000);
 #pragma unroll
-                    for (int i = 0; i < 9; ++i)
-                        if (!WOUT || twin<2>(i) == i) a.store(out, i, in[i]);
+                        for (int i = 0; i < 9; ++i)
+                            if (!WOUT || twin<2>(i) == i)
+                                __builtin_amdgcn_raw_buffer_store_b64(
+                                    __builtin_bit_cast(MsU2, in[i]), rs, a.off, i * CHUNK * 8, 2);
+                    } else {
+#pragma unroll
+                        for (int i = 0; i < 9; ++i)
+                            if (!WOUT || twin<2>(i) == i) a.store(out, i, in[i]);
+                    }
                 }
             }
         }
