@@ -373,6 +373,10 @@ def test_multi_step_passes_equal_single_steps(grid, steps):
 # A D2Q9 state of 8192 x 7400 nodes takes 4.37e9 bytes, more than 32-bit byte
 # offsets reach, so its multi-step passes address with 64-bit indices.
 BIG_2D = (8192, 7400)
+# A D2Q9 state of 6144 x 6000 nodes takes 2.65e9 bytes: 32-bit byte offsets
+# still reach it, but a buffer descriptor's record count over it has its top
+# bit set.
+MID_2D = (6144, 6000)
 
 
 def test_multi_step_passes_beyond_4gib_state():
@@ -1048,13 +1052,16 @@ def test_adjoint_segment_equals_single_adjoint_steps(grid, m):
     s.close()
 
 
-def test_adjoint_segment_beyond_4gib_state():
-    """lb_adjoint_segment over state buffers larger than 4 GiB: recomputed
-    states and lambda bitwise equal to single steps and single adjoint
-    steps, the eps gradient equal to rounding."""
-    _say("adjoint segment", BIG_2D, 6)
+@pytest.mark.parametrize("grid", [BIG_2D, MID_2D], ids=["beyond_4gib", "2_to_4gib"])
+def test_adjoint_segment_large_state(grid):
+    """lb_adjoint_segment over state buffers larger than 4 GiB (64-bit
+    offsets) and between 2 and 4 GiB (32-bit offsets, buffer stores whose
+    record count exceeds 2^31): recomputed states and lambda bitwise equal
+    to single steps and single adjoint steps, the eps gradient equal to
+    rounding."""
+    _say("adjoint segment", grid, 6)
     SV = _solver_mod()
-    grid, m = BIG_2D, 6
+    m = 6
     dx, nu = 1.0 / grid[0], 0.01
     dt = 0.2 * dx * dx / nu
     s = SV.Solver(grid, dx, dt, nu, device=_dev())
