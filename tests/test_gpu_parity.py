@@ -662,7 +662,7 @@ def test_fourth_order_convergence_on_gpu():
 
 
 # ---------------------------------------------------------------------------
-# full-size workloads against the exact Fourier-mode evaluation (sampled)
+# full-size workloads against the exact Fourier-mode evaluation (every node)
 # ---------------------------------------------------------------------------
 
 def _full_size_case(wl, nsteps):
