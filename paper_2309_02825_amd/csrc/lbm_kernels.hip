@@ -562,7 +562,10 @@ __device__ __forceinline__ void ms_row(MsState<S>& st, int k,
                         // a buffer descriptor per state and the plane as a
                         // scalar offset shared by all S states: a 64-bit
                         // base per plane and state would exceed the scalar
-                        // registers (they spill into VGPR lanes)
+                        // registers (they spill into VGPR lanes).  Records:
+                        // the bytes of one state (below 2^32 here); cache
+                        // policy 2 is the non-temporal hint of the other
+                        // stores.
                         const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
                             out, (short)0, (int)(unsigned)((uint64_t)9 * CHUNK * 8 *
                                                           (uint64_t)((nx * ny + CHUNK - 1) >> 12)),
