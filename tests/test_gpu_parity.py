@@ -1052,6 +1052,50 @@ def test_adjoint_segment_equals_single_adjoint_steps(grid, m):
     s.close()
 
 
+@pytest.mark.parametrize("seed", range(8))
+def test_adjoint_segment_random_shapes(seed):
+    """lb_adjoint_segment on seeded random D2Q9 grids (1..259 per side, so
+    ragged strips and row segments of every length down to one row), segment
+    lengths 1..39 and pass limits 1/2/4/8: lambda bitwise equal to single
+    adjoint steps, the eps gradient equal to rounding."""
+    rng = np.random.default_rng(500 + seed)
+    nx, ny = int(rng.integers(1, 260)), int(rng.integers(1, 260))
+    m = int(rng.integers(1, 40))
+    spp = int(rng.choice([1, 2, 4, 8]))
+    _say("adjoint segment random", (nx, ny), m, spp)
+    SV = _solver_mod()
+    grid = (nx, ny)
+    dx, nu = 1.0 / max(grid), 0.02
+    dt = 0.17 * dx * dx / nu
+    s = SV.Solver(grid, dx, dt, nu, device=_dev())
+    shape = (9, ny, nx)
+    g = torch.Generator(device="cpu").manual_seed(seed)
+    v = (1.0 + 0.1 * torch.randn(shape, generator=g, dtype=torch.float64)).to(_dev())
+    lam = torch.randn(shape, generator=g, dtype=torch.float64).to(_dev())
+    s.set_state(v, 0)
+    ckpt = s.current().clone()
+    st = [ckpt]
+    for _ in range(1, m):
+        nxt = s.new_state()
+        s.step_buffers(st[-1], nxt)
+        st.append(nxt)
+    ge_ref = torch.zeros(1, dtype=torch.float64, device=_dev())
+    cur, other = s.to_layout(lam), s.new_state()
+    for n in range(m - 1, -1, -1):
+        s.adjoint_step(st[n], cur, other, ge_ref)
+        cur, other = other, cur
+    s.set_steps_per_pass(spp)
+    ge = torch.zeros(1, dtype=torch.float64, device=_dev())
+    lam_c = s.to_layout(lam)
+    work = (torch.full(((m - 1) * s.state_elems,), float("nan"), dtype=torch.float64,
+                       device=_dev()) if m > 1 else None)
+    s.adjoint_segment(ckpt, m, work, lam_c, s.new_state(), ge)
+    torch.cuda.synchronize()
+    assert torch.equal(s.from_layout(lam_c), s.from_layout(cur))
+    assert abs(ge.item() - ge_ref.item()) <= 1e-12 * max(abs(ge_ref.item()), 1.0)
+    s.close()
+
+
 @pytest.mark.parametrize("grid", [BIG_2D, MID_2D], ids=["beyond_4gib", "2_to_4gib"])
 def test_adjoint_segment_large_state(grid):
     """lb_adjoint_segment over state buffers larger than 4 GiB (64-bit
