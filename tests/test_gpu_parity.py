@@ -442,8 +442,15 @@ def test_d3q19_passes_beyond_the_buffer_load_plane_limit():
     torch.cuda.empty_cache()
 
 
+def _random_3d_case(seed):
+    rng = np.random.default_rng(900 + seed)
+    grid = tuple(int(rng.integers(1, 140)) for _ in range(3))
+    return grid, int(rng.integers(1, 12))
+
+
 @pytest.mark.parametrize("grid,steps", [((37, 29, 23), 5), ((5, 3, 2), 4), ((1, 1, 1), 3),
-                                         ((64, 9, 40), 8), ((130, 7, 11), 7), ((61, 5, 70), 6)])
+                                         ((64, 9, 40), 8), ((130, 7, 11), 7), ((61, 5, 70), 6)]
+                         + [_random_3d_case(k) for k in range(6)])
 def test_multi_step_passes_equal_single_steps_3d(grid, steps):
     """D3Q19 lb_step advances pairs of steps in one pass (x-y tiles marching
     along z); the state is bitwise that of one launch per step for ragged
